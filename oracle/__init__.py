@@ -1,0 +1,13 @@
+"""FP64 CPU oracle of the kinetic compressive sensing sweep.
+
+TEST INFRASTRUCTURE ONLY.  Imported by tests/, by the smoke check and by the CPU-baseline leg
+of bench.py, never by the HIP library or its Python binding.  Plain and slow on purpose: Siddon
+system matrix in C (siddon.c), everything else NumPy/SciPy in FP64, each function citing the
+passage of the paper it follows.
+"""
+from .geometry import (Geometry, build_oracle_library, forward, back, subset_angles, subset_rows,
+                       subset_sensitivity, system_matrix, siddon_line)
+from .model import Kinetics, cp, input_integrals, model_tac, cumulative_tissue, moments
+from .recon import (Frames, LMOptions, Prior, expected_counts, huber, huber_grad, icm, icm_sweep,
+                    initial_image, initial_state, lm_fit, lm_iteration, neighbour_terms, osl_update)
+from .study import Study, make_study

@@ -1,0 +1,196 @@
+"""FP64 oracle: OS-MAP-OSL-KP activity update, MAP-LM kinetic fit, ICM sweep.
+
+TEST INFRASTRUCTURE ONLY (see geometry.py).
+
+Readings of points the paper leaves open (each is also an argument here):
+  * OSL denominator (Eq. 2 with Eq. 3): Green's one-step-late form with the prior gradient
+    pulling x toward the model TAC F, and sigma^2 = F / n (Poisson-like variance of the subset
+    estimate), so D = n (1 + beta_kp (x - F) / max(F, eps_F)); x is unchanged where n = 0; the
+    prior is off in the first sweep (no kinetic maps exist yet).
+  * Expected counts add a flat background r_m (ordinary Poisson model, Sec. II-A):
+    ybar = E_m P x_m + r_m with E_m = c dt_m.
+  * Ordered subsets: subset q holds the angles a with a mod Q = q, processed q = 0..Q-1.
+  * MAP-LM (Eq. 4-7): Levenberg damping lambda I; the Huber term uses H(t) = t^2/2 inside
+    [-delta, delta] and delta |t| - delta^2/2 outside, so dH/dt = clip(t, -delta, delta); the
+    3x3 in-plane neighbourhood has weight 1 for edge neighbours and 1/sqrt(2) for diagonals,
+    neighbours outside the image are dropped; all voxels update synchronously from the maps of
+    the previous iteration; a step is kept only if the voxel's local objective
+    1/2 ||x - F||^2 + beta_h sum_k w_k sum_p H(xi_p - xi_kp) strictly decreases, then
+    lambda /= 10 (floor lam_min), otherwise lambda *= 10 (cap lam_max); lambda <= 0 on entry
+    is initialised to tau * max diag(J^T J); steps are clipped to the box [lo, hi].
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Tuple
+
+import numpy as np
+
+from . import geometry as geo
+from .model import Kinetics, model_tac
+
+
+@dataclass(frozen=True)
+class Prior:
+    beta_kp: float = 0.1
+    eps_F: float = 1e-2
+    beta_h: float = 0.1
+    delta: Tuple[float, float, float] = (1e-3, 1e-3, 1e-3)
+    kp_on: bool = True
+
+
+@dataclass(frozen=True)
+class LMOptions:
+    n_iter: int = 5
+    tau: float = 1e-3
+    lam_min: float = 1e-8
+    lam_max: float = 1e8
+    lo: Tuple[float, float, float] = (0.0, 1e-4, 0.0)
+    hi: Tuple[float, float, float] = (2.0, 2.0, 1.0)
+
+
+@dataclass
+class Frames:
+    t0: np.ndarray  # minutes
+    t1: np.ndarray
+    E: np.ndarray  # counts per (activity unit x mm), c * dt_m
+    r: np.ndarray  # background counts per bin
+
+    @property
+    def M(self) -> int:
+        return len(self.t0)
+
+
+# ------------------------------------------------------------------------------------------
+# OS-MAP-OSL-KP
+# ------------------------------------------------------------------------------------------
+
+def expected_counts(g: geo.Geometry, fr: Frames, x: np.ndarray, q: int, Q: int) -> np.ndarray:
+    """ybar_dm = E_m sum_v p_vd x_vm + r_m for the rays of subset q: (nz, A_q, n_bin, M)."""
+    return fr.E * geo.forward(g, x, q, Q) + fr.r
+
+
+def osl_update(g: geo.Geometry, fr: Frames, kin: Kinetics, prior: Prior, sino: np.ndarray, params: np.ndarray,
+               x: np.ndarray, q: int, Q: int, kp: bool) -> np.ndarray:
+    """One OS-MAP-OSL-KP update of the image x (nz, ny, nx, M) with subset q (Eq. 2-3)."""
+    ybar = expected_counts(g, fr, x, q, Q)
+    s_q = sino[:, geo.subset_angles(g.n_ang, q, Q)]
+    ratio = np.where(ybar > 0.0, s_q / np.where(ybar > 0.0, ybar, 1.0), 0.0)
+    bp = fr.E * geo.back(g, ratio, q, Q)
+    n = fr.E * geo.subset_sensitivity(g, q, Q)[None, :, :, None]
+    n = np.broadcast_to(n, x.shape)
+    if kp:
+        F = model_tac(params.reshape(3, -1).T, fr.t0, fr.t1, kin).reshape(x.shape)
+        D = n * (1.0 + prior.beta_kp * (x - F) / np.maximum(F, prior.eps_F))
+    else:
+        D = n
+    return np.where(n > 0.0, x * bp / np.where(n > 0.0, D, 1.0), x)
+
+
+def initial_image(g: geo.Geometry, fr: Frames, sino: np.ndarray) -> np.ndarray:
+    """Flat image per frame that reproduces the frame's net counts:
+    x_m = max(sum_d (s_dm - r_m), 1) / (E_m sum_v sum_d p_vd)."""
+    P = geo.system_matrix(g)
+    total_p = float(P.sum()) * g.nz
+    net = sino.reshape(-1, fr.M).sum(axis=0) - fr.r * (g.n_ang * g.n_bin * g.nz)
+    x_m = np.maximum(net, 1.0) / (fr.E * total_p)
+    return np.broadcast_to(x_m, (g.nz, g.ny, g.nx, fr.M)).copy()
+
+
+# ------------------------------------------------------------------------------------------
+# MAP-LM with the Huber prior
+# ------------------------------------------------------------------------------------------
+
+_OFFSETS = [(dy, dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1) if (dy, dx) != (0, 0)]
+
+
+def huber(t, delta):
+    at = np.abs(t)
+    return np.where(at <= delta, 0.5 * t * t, delta * at - 0.5 * delta * delta)
+
+
+def huber_grad(t, delta):
+    return np.clip(t, -delta, delta)
+
+
+def neighbour_terms(xi_eval: np.ndarray, xi_ref: np.ndarray, delta) -> Tuple[np.ndarray, np.ndarray]:
+    """For maps (3, nz, ny, nx): sum_k w_k psi(xi_eval_v - xi_ref_k) per parameter (3, ...) and
+    sum_k w_k sum_p H(xi_eval_vp - xi_ref_kp) (nz, ny, nx), over in-plane 8-neighbours k."""
+    _, nz, ny, nx = xi_ref.shape
+    grad = np.zeros_like(xi_eval)
+    energy = np.zeros(xi_eval.shape[1:])
+    for dy, dx in _OFFSETS:
+        w = 1.0 if dy == 0 or dx == 0 else 1.0 / np.sqrt(2.0)
+        ys, yd = (slice(0, ny - dy), slice(dy, ny)) if dy >= 0 else (slice(-dy, ny), slice(0, ny + dy))
+        xs, xd = (slice(0, nx - dx), slice(dx, nx)) if dx >= 0 else (slice(-dx, nx), slice(0, nx + dx))
+        # voxel at (y, x) = destination slice (ys, xs); its neighbour at (y+dy, x+dx) = (yd, xd)
+        for p in range(3):
+            t = xi_eval[p][:, ys, xs] - xi_ref[p][:, yd, xd]
+            grad[p][:, ys, xs] += w * huber_grad(t, delta[p])
+            energy[:, ys, xs] += w * huber(t, delta[p])
+    return grad, energy
+
+
+def lm_iteration(fr: Frames, kin: Kinetics, prior: Prior, opt: LMOptions, x: np.ndarray, params: np.ndarray,
+                 lam: np.ndarray):
+    """One synchronous MAP-LM iteration over all voxels (Eq. 4).  x: (nz, ny, nx, M);
+    params: (3, nz, ny, nx); lam: (nz, ny, nx).  Returns new (params, lam)."""
+    shp = params.shape[1:]
+    N = int(np.prod(shp))
+    xv = x.reshape(N, -1)
+    xi = params.reshape(3, N).T.copy()
+    F, J = model_tac(xi, fr.t0, fr.t1, kin, jacobian=True)
+    r = xv - F
+    pg, pe = neighbour_terms(params, params, prior.delta)
+    g = np.einsum("nmp,nm->np", J, r) - prior.beta_h * pg.reshape(3, N).T
+    A = np.einsum("nmp,nmq->npq", J, J)
+    lam = lam.reshape(N).copy()
+    init = lam <= 0.0
+    lam[init] = opt.tau * np.max(np.diagonal(A, axis1=1, axis2=2), axis=1)[init]
+    step = np.linalg.solve(A + lam[:, None, None] * np.eye(3)[None], g[:, :, None])[:, :, 0]
+    trial = np.clip(xi + step, np.array(opt.lo), np.array(opt.hi))
+    F1 = model_tac(trial, fr.t0, fr.t1, kin)
+    trial_maps = trial.T.reshape(params.shape)
+    _, pe1 = neighbour_terms(trial_maps, params, prior.delta)
+    phi0 = 0.5 * np.sum(r * r, axis=1) + prior.beta_h * pe.reshape(N)
+    phi1 = 0.5 * np.sum((xv - F1) ** 2, axis=1) + prior.beta_h * pe1.reshape(N)
+    accept = phi1 < phi0
+    new = np.where(accept[:, None], trial, xi)
+    lam = np.where(accept, np.maximum(lam / 10.0, opt.lam_min), np.minimum(lam * 10.0, opt.lam_max))
+    return new.T.reshape(params.shape).copy(), lam.reshape(shp)
+
+
+def lm_fit(fr, kin, prior, opt, x, params, lam):
+    for _ in range(opt.n_iter):
+        params, lam = lm_iteration(fr, kin, prior, opt, x, params, lam)
+    return params, lam
+
+
+# ------------------------------------------------------------------------------------------
+# ICM
+# ------------------------------------------------------------------------------------------
+
+def icm_sweep(g, fr, kin, prior, opt, sino, x, params, lam, Q: int, sweep_idx: int):
+    """One ICM sweep (Sec. II-D): OS-MAP-OSL-KP over all Q subsets given the maps, then MAP-LM
+    given the new image."""
+    kp = prior.kp_on and sweep_idx > 0
+    for q in range(Q):
+        x = osl_update(g, fr, kin, prior, sino, params, x, q, Q, kp)
+    params, lam = lm_fit(fr, kin, prior, opt, x, params, lam)
+    return x, params, lam
+
+
+def initial_state(g: geo.Geometry, fr: Frames, sino: np.ndarray, xi0=(0.08, 0.12, 0.05)):
+    x = initial_image(g, fr, sino)
+    params = np.empty((3, g.nz, g.ny, g.nx))
+    for p in range(3):
+        params[p] = xi0[p]
+    lam = np.zeros((g.nz, g.ny, g.nx))
+    return x, params, lam
+
+
+def icm(g, fr, kin, prior, opt, sino, Q: int, n_sweeps: int, state=None):
+    x, params, lam = state if state is not None else initial_state(g, fr, sino)
+    for s in range(n_sweeps):
+        x, params, lam = icm_sweep(g, fr, kin, prior, opt, sino, x, params, lam, Q, s)
+    return x, params, lam

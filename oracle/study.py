@@ -1,0 +1,67 @@
+"""FP64 oracle: synthesis of a study's measured sinogram from the seeded phantom.
+
+TEST INFRASTRUCTURE ONLY (see geometry.py).  The phantom maps, schedule and Poisson sampler
+come from the shared input module; the activity (model TACs of the true maps) and the expected
+counts come from this oracle, so no input of a parity test is produced by the HIP path.
+
+Count scaling: E_m = c dt_m with c chosen so that the expected trues over the scan equal the
+configured total; the flat background adds bg_frac x total counts spread uniformly over all
+bins in proportion to frame duration.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from paper_1803_10045_amd import inputs
+from . import geometry as geo
+from .model import Kinetics, cp, model_tac
+from .recon import Frames, LMOptions, Prior
+
+
+@dataclass
+class Study:
+    cfg: object
+    geom: geo.Geometry
+    frames: Frames
+    kin: Kinetics
+    prior: Prior
+    lm: LMOptions
+    sino: np.ndarray  # (nz, n_ang, n_bin, M) float32 counts
+    truth_params: np.ndarray  # (3, nz, ny, nx)
+    truth_x: np.ndarray  # (nz, ny, nx, M) frame-mean activity
+    mask: np.ndarray
+
+
+def peak_input(kin: Kinetics) -> float:
+    t = np.linspace(0.0, 2.0, 400001)
+    return float(cp(t, kin).max())
+
+
+def make_study(cfg, with_truth: bool = True) -> Study:
+    g = geo.Geometry.from_config(cfg)
+    kin = Kinetics(**inputs.FENG, vb=inputs.VB)
+    t0, t1 = inputs.frame_times()
+    dt = t1 - t0
+    M = len(t0)
+    maps, mask = inputs.phantom_maps(cfg)
+    x_true = np.zeros((cfg.nz, cfg.ny, cfg.nx, M))
+    idx = np.nonzero(mask.ravel())[0]
+    if len(idx):
+        F = model_tac(maps.reshape(3, -1).T[idx], t0, t1, kin)
+        x_true.reshape(-1, M)[idx] = F
+    proj = geo.forward(g, x_true)  # unit-calibration line integrals, (nz, n_ang, n_bin, M)
+    total = float(np.sum(proj.reshape(-1, M).sum(axis=0) * dt))
+    c = cfg.counts / total if total > 0 else 1.0
+    E = c * dt
+    r = cfg.bg_frac * cfg.counts * (dt / dt.sum()) / (cfg.n_ang * cfg.n_bin * cfg.nz)
+    expected = E * proj + r
+    sino = inputs.poisson_counts(expected, cfg.seed)
+    delta = inputs.huber_delta(maps, mask) if mask.any() else 1e-3
+    prior = Prior(beta_kp=inputs.BETA_KP, eps_F=1e-4 * peak_input(kin), beta_h=cfg.beta_h,
+                  delta=(delta, delta, delta), kp_on=True)
+    lm = LMOptions(n_iter=cfg.n_lm, tau=inputs.LM_TAU, lam_min=inputs.LM_LAM_MIN, lam_max=inputs.LM_LAM_MAX,
+                   lo=inputs.LM_LO, hi=inputs.LM_HI)
+    fr = Frames(t0=t0, t1=t1, E=E, r=r)
+    return Study(cfg, g, fr, kin, prior, lm, sino, maps, x_true if with_truth else None, mask)
