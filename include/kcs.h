@@ -1,0 +1,178 @@
+/*
+ * kcs.h -- kinetic compressive sensing (direct parametric PET reconstruction) on MI355X.
+ *
+ * C ABI of libkcs.so.  One ICM sweep (Sec. II-D) alternates
+ *   (a) an ordered-subsets MAP one-step-late activity update with the kinetics-derived prior
+ *       (Eq. 2 with the potential of Eq. 3), and
+ *   (b) a per-voxel MAP Levenberg-Marquardt fit of the irreversible two-tissue model with the
+ *       Huber prior on neighbour differences of the kinetic maps (Eq. 4-7).
+ *
+ * Conventions shared by every entry point
+ *   - Device arrays are FP32, C order, owned and allocated by the caller; the library never
+ *     frees them.  The time-frame index is innermost:
+ *       image x        [nz][ny][nx][M]      (frame-mean activity, units of the input function)
+ *       sinogram s     [nz][n_ang][n_bin][M] (counts)
+ *       subset sinogram[nz][A_q][n_bin][M]   (A_q = angles of subset q, see below)
+ *       kinetic maps   [3][nz][ny][nx]      (K1, k2, k3 planes, "structure of arrays")
+ *       damping lambda [nz][ny][nx]
+ *   - Host arrays (frame schedule, scales) are FP64 and only read during the call.
+ *   - Every call is asynchronous on `stream` (0 = the null stream) and never synchronises the
+ *     device.  Arguments are validated on the host before anything is launched, so a call
+ *     that returns an error has no side effect.  Return value: KCS_OK or a negative code;
+ *     kcs_last_error() gives a message for the calling thread.
+ *   - Calls that need the kinetic-model constants (everything but kcs_project / kcs_backproject)
+ *     build them with a small FP64 kernel in the caller's workspace, so no host-to-device copy is
+ *     made and every call only enqueues kernels (and device-to-device copies) on `stream`.
+ *   - Calls sharing a workspace must be ordered (same stream, or synchronised); the workspace
+ *     must be 256-byte aligned.
+ *   - M (frames) must be one of 8, 16, 24, 32.
+ *
+ * Geometry: 2D parallel-beam projections of direct planes.  Pixels are squares of side
+ * pixel_mm centred at ((i - (nx-1)/2) h, (j - (ny-1)/2) h).  Ray (a, b) is the line
+ * x cos(t_a) + y sin(t_a) = u_b with t_a = ang0_rad + a pi / n_ang and
+ * u_b = (b - (n_bin-1)/2) bin_mm.  The system matrix element p_vd (Eq. 2) is the exact length
+ * (mm) of ray d inside pixel v (Siddon's radiological path).  Ordered subset q of Q holds the
+ * angles a with a mod Q = q, in increasing order (A_q = ceil((n_ang - q) / Q) of them).
+ */
+#ifndef KCS_H
+#define KCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    KCS_OK = 0,
+    KCS_EINVAL = -1,     /* null pointer, non-positive size, unsorted frames, bad value */
+    KCS_ESHAPE = -2,     /* shape the library does not support (e.g. M not in {8,16,24,32}) */
+    KCS_EWORKSPACE = -3, /* workspace smaller than kcs_workspace_bytes() */
+    KCS_EHIP = -4        /* HIP runtime error (message has hipGetErrorString) */
+};
+
+typedef struct kcs_geometry {
+    int32_t nx, ny, nz; /* image grid, >= 1 each, nx*ny*nz < 2^31 */
+    double pixel_mm;    /* in-plane square pixel side h > 0 */
+    int32_t n_ang;      /* projection angles over 180 degrees, >= 1 */
+    int32_t n_bin;      /* radial bins per angle, >= 1 */
+    double bin_mm;      /* radial bin width > 0 */
+    double ang0_rad;    /* angle of projection 0 */
+} kcs_geometry;
+
+typedef struct kcs_frames {
+    int32_t n_frames;     /* M */
+    const double* t0_min; /* host [M] frame start, minutes, >= 0 */
+    const double* t1_min; /* host [M] frame end, > start, frames sorted and non-overlapping */
+    const double* scale;  /* host [M] E_m = c * (t1_m - t0_m): expected counts per activity unit per mm of path */
+    const double* bg;     /* host [M] r_m >= 0: flat additive background, counts per bin (randoms + scatter) */
+} kcs_frames;
+
+/* Plasma input Cp(t) = (A1 t - A2 - A3) e^{l1 t} + A2 e^{l2 t} + A3 e^{l3 t} (t >= 0, minutes;
+ * Cp = 0 before 0) and the measured TAC model C_PET = (1 - vb) C_T + vb Cp with the irreversible
+ * two-tissue tissue curve C_T(K1, k2, k3) (k4 = 0).  l1 < l2 < l3 < 0 distinct; 0 <= vb < 1. */
+typedef struct kcs_kinetics {
+    double A1, A2, A3, l1, l2, l3, vb;
+} kcs_kinetics;
+
+/* Priors.  OSL denominator (Eq. 2-3): D = n (1 + beta_kp (x - F) / max(F, eps_F)) with
+ * 0 <= beta_kp < 1 and eps_F > 0; kp_on = 0 turns the kinetics-derived prior off (plain OS-EM).
+ * MAP-LM (Eq. 4-7): weight beta_h >= 0 and Huber threshold delta[p] > 0 per kinetic parameter. */
+typedef struct kcs_prior {
+    double beta_kp, eps_F, beta_h, delta[3];
+    int32_t kp_on;
+} kcs_prior;
+
+/* Levenberg-Marquardt schedule: n_iter synchronous iterations; lambda <= 0 on entry is set to
+ * tau * max diag(J^T J); accepted step: lambda = max(lambda/10, lam_min), rejected:
+ * lambda = min(10 lambda, lam_max); parameters clipped to [lo, hi] (lo[1] + lo[2] > 0). */
+typedef struct kcs_lm_opts {
+    int32_t n_iter;
+    double tau, lam_min, lam_max, lo[3], hi[3];
+} kcs_lm_opts;
+
+/* Bytes of device workspace the calls below need for this geometry, frame count and subset count. */
+size_t kcs_workspace_bytes(const kcs_geometry* g, int32_t n_frames, int32_t Q);
+
+/* Device bytes one study occupies: sinogram, image, three maps, lambda, workspace. */
+size_t kcs_study_footprint_bytes(const kcs_geometry* g, int32_t n_frames, int32_t Q);
+
+/* Expected counts of subset q (denominator of Eq. 2 plus background):
+ *   ybar_dm = E_m sum_v p_vd x_vm + r_m   for the rays d of subset q.
+ * d_x: image [nz][ny][nx][M]; d_ybar: [nz][A_q][n_bin][M] (written).  0 <= q < Q <= n_ang. */
+int kcs_project(const kcs_geometry* g, const kcs_frames* f, const float* d_x, int32_t q, int32_t Q,
+                float* d_ybar, hipStream_t stream);
+
+/* Adjoint of the linear part of kcs_project (outer sum of Eq. 2):
+ *   b_vm = E_m sum_{d in S_q} p_vd y_dm,   sens_v = sum_{d in S_q} p_vd.
+ * d_y: [nz][A_q][n_bin][M]; d_b: [nz][ny][nx][M] (written); d_sens: [nz][ny][nx] or NULL. */
+int kcs_backproject(const kcs_geometry* g, const kcs_frames* f, const float* d_y, int32_t q, int32_t Q,
+                    float* d_b, float* d_sens, hipStream_t stream);
+
+/* Frame-averaged model TAC (Eq. 3's F(xi)_m, closed-form time integrals) for n voxels:
+ *   F_m = (1/dt_m) int_{t0_m}^{t1_m} [(1 - vb) C_T(t; K1, k2, k3) + vb Cp(t)] dt
+ * d_params: [3][n] (K1, k2, k3 with k2 + k3 > 0); d_F: [n][M]; d_J: [n][M][3] dF/d(K1,k2,k3) or NULL.
+ * d_work: at least kcs_workspace_bytes(NULL, M, 0) bytes. */
+int kcs_model_tac(const kcs_frames* f, const kcs_kinetics* k, const float* d_params, int64_t n, float* d_F,
+                  float* d_J, void* d_work, size_t work_bytes, hipStream_t stream);
+
+/* One OS-MAP-OSL-KP update with subset q (Eq. 2 with the potential of Eq. 3):
+ *   x_vm <- x_vm * b_vm / D_vm,  b_vm = E_m sum_{d in S_q} p_vd s_dm / ybar_dm,
+ *   D_vm = n_vm [1 + beta_kp (x_vm - F_vm) / max(F_vm, eps_F)] (prior on) or n_vm (off),
+ *   n_vm = E_m sum_{d in S_q} p_vd;  x unchanged where n_vm = 0;  F from d_params.
+ * d_sino: measured [nz][n_ang][n_bin][M]; d_params: [3][nz][ny][nx]; d_x updated in place. */
+int kcs_osl_update(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics* k, const kcs_prior* p,
+                   const float* d_sino, const float* d_params, int32_t q, int32_t Q, float* d_x, void* d_work,
+                   size_t work_bytes, hipStream_t stream);
+
+/* lm->n_iter synchronous MAP-LM iterations (Eq. 4-7) on every voxel of the image d_x:
+ *   g = J^T (x - F) - beta_h sum_k w_k psi(xi_v - xi_k),  step = (J^T J + lambda I)^{-1} g,
+ * trial clipped to [lo, hi] and kept iff the voxel's objective strictly decreases; neighbours k
+ * are the in-plane 8-neighbourhood (w = 1 edge, 1/sqrt 2 diagonal) read from the maps of the
+ * previous iteration.  d_params [3][nz][ny][nx] and d_lambda [nz][ny][nx] are updated. */
+int kcs_lm_fit(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics* k, const kcs_prior* p,
+               const kcs_lm_opts* lm, const float* d_x, float* d_params, float* d_lambda, void* d_work,
+               size_t work_bytes, hipStream_t stream);
+
+/* Initial ICM state: x_m = max(sum_d (s_dm - r_m), 1) / (E_m sum_v sum_d p_vd) in every voxel,
+ * maps = xi0 everywhere, lambda = 0 (initialised by the first LM iteration). */
+int kcs_init_state(const kcs_geometry* g, const kcs_frames* f, const float* d_sino, const double xi0[3],
+                   float* d_x, float* d_params, float* d_lambda, void* d_work, size_t work_bytes,
+                   hipStream_t stream);
+
+/* One ICM sweep (Sec. II-D): kcs_osl_update for q = 0..Q-1 (prior on iff p->kp_on and
+ * sweep_idx > 0), then kcs_lm_fit. */
+int kcs_icm_sweep(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics* k, const kcs_prior* p,
+                  const kcs_lm_opts* lm, const float* d_sino, int32_t Q, int32_t sweep_idx, float* d_x,
+                  float* d_params, float* d_lambda, void* d_work, size_t work_bytes, hipStream_t stream);
+
+/* Kernel timing for measurement harnesses.  While enabled, every kernel or copy the library
+ * launches is bracketed by a pair of HIP events recorded on the call's stream (the events are
+ * created by the library and reused).  kcs_timing_collect waits for the recorded events, adds
+ * the elapsed milliseconds per kind into total_ms[k] and the launch count into count[k]
+ * (arrays of KCS_TIMING_KINDS entries, overwritten), and forgets them.  Kinds: */
+enum {
+    KCS_T_SETUP = 0,   /* table setup */
+    KCS_T_PROJECT = 1, /* forward projection (K-proj, with or without the ratio) */
+    KCS_T_BACK = 2,    /* plain back projection */
+    KCS_T_OSL = 3,     /* back projection fused with the OSL update (K-back) */
+    KCS_T_LM = 4,      /* MAP-LM iteration (K-lm) */
+    KCS_T_MODEL = 5,   /* model TAC evaluation */
+    KCS_T_INIT = 6,    /* initial state */
+    KCS_T_COPY = 7,    /* device-to-device copy of the kinetic maps */
+    KCS_TIMING_KINDS = 8
+};
+int kcs_timing_enable(int32_t on);
+int kcs_timing_collect(double* total_ms, int64_t* count);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* kcs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KCS_H */

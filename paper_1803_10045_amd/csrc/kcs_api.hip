@@ -1,0 +1,573 @@
+// Host side of libkcs: argument validation, FP64 constants, workspace layout and the C ABI.
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "kcs_launch.h"
+
+namespace kcs {
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(KCS_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+constexpr int32_t kInitChunks = 2048;
+
+// ----------------------------------------------------------------------------------------------
+// Validation
+int check_geometry(const kcs_geometry* g) {
+    if (!g) return fail(KCS_EINVAL, "geometry is NULL");
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(KCS_EINVAL, "image size must be >= 1");
+    if (g->n_ang < 1 || g->n_bin < 1) return fail(KCS_EINVAL, "sinogram size must be >= 1");
+    if (!(g->pixel_mm > 0) || !is_finite(g->pixel_mm)) return fail(KCS_EINVAL, "pixel_mm must be > 0");
+    if (!(g->bin_mm > 0) || !is_finite(g->bin_mm)) return fail(KCS_EINVAL, "bin_mm must be > 0");
+    if (!is_finite(g->ang0_rad)) return fail(KCS_EINVAL, "ang0_rad must be finite");
+    if ((double)g->nx * g->ny * g->nz >= 2147483647.0) return fail(KCS_ESHAPE, "more than 2^31 voxels");
+    if (g->nx > 16384 || g->ny > 16384 || g->n_bin > 65536) return fail(KCS_ESHAPE, "grid too large");
+    return KCS_OK;
+}
+
+int check_frames(const kcs_frames* f) {
+    if (!f) return fail(KCS_EINVAL, "frames is NULL");
+    const int M = f->n_frames;
+    if (M != 8 && M != 16 && M != 24 && M != 32) return fail(KCS_ESHAPE, "n_frames must be 8, 16, 24 or 32 (got %d)", M);
+    if (!f->t0_min || !f->t1_min || !f->scale || !f->bg) return fail(KCS_EINVAL, "frame arrays must not be NULL");
+    for (int m = 0; m < M; ++m) {
+        if (!is_finite(f->t0_min[m]) || !is_finite(f->t1_min[m]) || f->t0_min[m] < 0 || !(f->t1_min[m] > f->t0_min[m]))
+            return fail(KCS_EINVAL, "frame %d: need 0 <= t0 < t1", m);
+        if (m > 0 && f->t0_min[m] < f->t1_min[m - 1]) return fail(KCS_EINVAL, "frames must be sorted and disjoint");
+        if (!(f->scale[m] > 0) || !is_finite(f->scale[m])) return fail(KCS_EINVAL, "frame %d: scale must be > 0", m);
+        if (!(f->bg[m] >= 0) || !is_finite(f->bg[m])) return fail(KCS_EINVAL, "frame %d: bg must be >= 0", m);
+    }
+    return KCS_OK;
+}
+
+int check_kinetics(const kcs_kinetics* k) {
+    if (!k) return fail(KCS_EINVAL, "kinetics is NULL");
+    const double v[] = {k->A1, k->A2, k->A3, k->l1, k->l2, k->l3, k->vb};
+    for (double x : v)
+        if (!is_finite(x)) return fail(KCS_EINVAL, "kinetics must be finite");
+    if (!(k->l1 < 0 && k->l2 < 0 && k->l3 < 0)) return fail(KCS_EINVAL, "input-function exponents must be negative");
+    if (!(k->vb >= 0 && k->vb < 1)) return fail(KCS_EINVAL, "vb must be in [0, 1)");
+    return KCS_OK;
+}
+
+int check_prior(const kcs_prior* p) {
+    if (!p) return fail(KCS_EINVAL, "prior is NULL");
+    if (!(p->beta_kp >= 0 && p->beta_kp < 1)) return fail(KCS_EINVAL, "beta_kp must be in [0, 1)");
+    if (!(p->eps_F > 0) || !is_finite(p->eps_F)) return fail(KCS_EINVAL, "eps_F must be > 0");
+    if (!(p->beta_h >= 0) || !is_finite(p->beta_h)) return fail(KCS_EINVAL, "beta_h must be >= 0");
+    for (int i = 0; i < 3; ++i)
+        if (!(p->delta[i] > 0) || !is_finite(p->delta[i])) return fail(KCS_EINVAL, "delta must be > 0");
+    return KCS_OK;
+}
+
+int check_lm(const kcs_lm_opts* o) {
+    if (!o) return fail(KCS_EINVAL, "lm options are NULL");
+    if (o->n_iter < 0 || o->n_iter > 100000) return fail(KCS_EINVAL, "n_iter out of range");
+    if (!(o->tau > 0) || !(o->lam_min > 0) || !(o->lam_max >= o->lam_min) || !is_finite(o->lam_max))
+        return fail(KCS_EINVAL, "need tau > 0 and 0 < lam_min <= lam_max");
+    for (int i = 0; i < 3; ++i)
+        if (!is_finite(o->lo[i]) || !is_finite(o->hi[i]) || !(o->lo[i] <= o->hi[i])) return fail(KCS_EINVAL, "need lo <= hi");
+    if (!(o->lo[1] + o->lo[2] > 0)) return fail(KCS_EINVAL, "lo[1] + lo[2] must be > 0 (k2 + k3 > 0)");
+    return KCS_OK;
+}
+
+int check_subset(const kcs_geometry* g, int32_t q, int32_t Q) {
+    if (Q < 1 || Q > g->n_ang) return fail(KCS_EINVAL, "need 1 <= Q <= n_ang");
+    if (q < 0 || q >= Q) return fail(KCS_EINVAL, "need 0 <= q < Q");
+    if ((g->n_ang + Q - 1) / Q > 1024) return fail(KCS_ESHAPE, "more than 1024 angles in a subset");
+    return KCS_OK;
+}
+
+#define KCS_TRY(x)                  \
+    do {                            \
+        const int _rc = (x);        \
+        if (_rc != KCS_OK) return _rc; \
+    } while (0)
+
+// ----------------------------------------------------------------------------------------------
+// FP64 constants
+
+// m_k(x) = int_0^1 s^k e^{x s} ds, k = 0..2, for x <= 0 (series near 0, recursion otherwise)
+void moments3(double x, double m[3]) {
+    if (std::fabs(x) < 1.0) {
+        double term = 1.0;
+        m[0] = m[1] = m[2] = 0.0;
+        for (int j = 0; j < 30; ++j) {
+            for (int k = 0; k < 3; ++k) m[k] += term / (j + k + 1);
+            term *= x / (j + 1);
+        }
+        return;
+    }
+    const double e = std::exp(x);
+    m[0] = std::expm1(x) / x;
+    m[1] = (e - m[0]) / x;
+    m[2] = (e - 2.0 * m[1]) / x;
+}
+
+// P1(t) = int_0^t Cp and P2(t) = int_0^t P1 for the Feng input (sum of c t^n e^{l t} terms)
+void input_integrals(const kcs_kinetics& k, double t, double& P1, double& P2) {
+    const double c[4] = {k.A1, -(k.A2 + k.A3), k.A2, k.A3};
+    const double l[4] = {k.l1, k.l1, k.l2, k.l3};
+    const int n[4] = {1, 0, 0, 0};
+    P1 = P2 = 0.0;
+    for (int i = 0; i < 4; ++i) {
+        double m[3];
+        moments3(l[i] * t, m);
+        const double tp = std::pow(t, n[i] + 1);
+        P1 += c[i] * tp * m[n[i]];
+        P2 += c[i] * tp * t * (m[n[i]] - m[n[i] + 1]);
+    }
+}
+
+struct Schedule {
+    FrameTab fr;
+    SetupArgs setup;
+};
+
+Schedule make_schedule(const kcs_frames& f, const kcs_kinetics* k) {
+    Schedule S{};
+    const int M = f.n_frames;
+    S.fr.M = M;
+    S.fr.contiguous = 1;
+    for (int m = 1; m < M; ++m)
+        if (f.t0_min[m] != f.t1_min[m - 1]) S.fr.contiguous = 0;
+    std::vector<double> tb;
+    for (int m = 0; m < M; ++m) {
+        tb.push_back(f.t0_min[m]);
+        tb.push_back(f.t1_min[m]);
+    }
+    std::sort(tb.begin(), tb.end());
+    tb.erase(std::unique(tb.begin(), tb.end()), tb.end());
+    S.setup.n_bound = (int32_t)tb.size();
+    for (size_t b = 0; b < tb.size(); ++b) S.setup.t[b] = tb[b];
+    S.setup.M = M;
+    for (int m = 0; m < M; ++m) {
+        S.setup.i0[m] = (int32_t)(std::lower_bound(tb.begin(), tb.end(), f.t0_min[m]) - tb.begin());
+        S.setup.i1[m] = (int32_t)(std::lower_bound(tb.begin(), tb.end(), f.t1_min[m]) - tb.begin());
+        const double dt = f.t1_min[m] - f.t0_min[m];
+        S.fr.E[m] = (float)f.scale[m];
+        S.fr.r[m] = (float)f.bg[m];
+        S.fr.inv_dt[m] = (float)(1.0 / dt);
+    }
+    if (k) {
+        S.setup.A1 = k->A1;
+        S.setup.A2 = k->A2;
+        S.setup.A3 = k->A3;
+        S.setup.l[0] = k->l1;
+        S.setup.l[1] = k->l2;
+        S.setup.l[2] = k->l3;
+        S.setup.vb = k->vb;
+        S.fr.one_minus_vb = (float)(1.0 - k->vb);
+        for (int m = 0; m < M; ++m) {
+            double a1, a2, b1, b2;
+            input_integrals(*k, f.t0_min[m], a1, a2);
+            input_integrals(*k, f.t1_min[m], b1, b2);
+            S.fr.blood[m] = (float)(k->vb * (b1 - a1));
+            S.fr.dP2[m] = (float)(b2 - a2);
+        }
+    }
+    return S;
+}
+
+int32_t subset_size(const kcs_geometry& g, int32_t q, int32_t Q) { return (g.n_ang - q + Q - 1) / Q; }
+
+ProjArgs proj_args(const kcs_geometry& g, const FrameTab& fr, int32_t q, int32_t Q) {
+    ProjArgs p{};
+    p.nx = g.nx;
+    p.ny = g.ny;
+    p.nz = g.nz;
+    p.n_ang = g.n_ang;
+    p.n_bin = g.n_bin;
+    p.q = q;
+    p.Q = Q;
+    p.A_q = subset_size(g, q, Q);
+    p.rays_per_plane = p.A_q * g.n_bin;
+    p.h = (float)g.pixel_mm;
+    p.inv_h = (float)(1.0 / g.pixel_mm);
+    p.du = (float)g.bin_mm;
+    p.inv_du = (float)(1.0 / g.bin_mm);
+    p.ang0 = g.ang0_rad;
+    p.fr = fr;
+    return p;
+}
+
+// Total length of all rays inside the image square: sum_v sum_d p_vd over one plane.
+double total_path_length(const kcs_geometry& g) {
+    const double h = g.pixel_mm, X0 = -0.5 * g.nx * h, Y0 = -0.5 * g.ny * h;
+    double tot = 0.0;
+    for (int a = 0; a < g.n_ang; ++a) {
+        const double th = g.ang0_rad + (double)a * 3.141592653589793 / (double)g.n_ang;
+        double c = std::cos(th), s = std::sin(th);
+        if (std::fabs(c) < 1e-12) {
+            c = 0.0;
+            s = s > 0 ? 1.0 : -1.0;
+        }
+        if (std::fabs(s) < 1e-12) {
+            s = 0.0;
+            c = c > 0 ? 1.0 : -1.0;
+        }
+        for (int b = 0; b < g.n_bin; ++b) {
+            const double u = ((double)b - 0.5 * (g.n_bin - 1)) * g.bin_mm;
+            // clip the line {u (c, s) + t (-s, c)} to the half-open rectangle
+            double t0 = -1e300, t1 = 1e300;
+            const double px = u * c, py = u * s, dx = -s, dy = c;
+            bool miss = false;
+            auto clip = [&](double p0, double d, double lo, double hi) {
+                if (d == 0.0) {
+                    if (!(p0 >= lo && p0 < hi)) miss = true;
+                    return;
+                }
+                double a0 = (lo - p0) / d, a1 = (hi - p0) / d;
+                if (a0 > a1) std::swap(a0, a1);
+                t0 = std::max(t0, a0);
+                t1 = std::min(t1, a1);
+            };
+            clip(px, dx, X0, -X0);
+            clip(py, dy, Y0, -Y0);
+            if (!miss && t1 > t0) tot += t1 - t0;
+        }
+    }
+    return tot;
+}
+
+// Workspace layout
+struct Layout {
+    size_t kin, ratio, xi, init, total;
+};
+
+// Offsets of the workspace regions.  The ratio buffer (the largest subset's sinogram) comes
+// last so that calls without projections (Q = 0) need only the leading regions.
+Layout layout(const kcs_geometry* g, int32_t M, int32_t Q) {
+    Layout L{};
+    size_t off = 0;
+    L.kin = off;
+    off = align_up(off + sizeof(KinTab), 256);
+    if (g) {
+        const size_t N = (size_t)g->nx * g->ny * g->nz;
+        L.xi = off;
+        off = align_up(off + 3 * N * sizeof(float), 256);
+        L.init = off;
+        off = align_up(off + ((size_t)kInitChunks * M + M) * sizeof(double), 256);
+        L.ratio = off;
+        if (Q > 0) {
+            const size_t A_max = (size_t)((g->n_ang + Q - 1) / Q);
+            off = align_up(off + (size_t)g->nz * A_max * g->n_bin * M * sizeof(float), 256);
+        }
+    }
+    L.total = off;
+    return L;
+}
+
+int check_work(const kcs_geometry* g, int32_t M, int32_t Q, void* d_work, size_t work_bytes) {
+    if (!d_work) return fail(KCS_EINVAL, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(d_work) & 255) != 0) return fail(KCS_EINVAL, "workspace must be 256-byte aligned");
+    const size_t need = layout(g, M, Q).total;
+    if (work_bytes < need) return fail(KCS_EWORKSPACE, "workspace has %zu bytes, needs %zu", work_bytes, need);
+    return KCS_OK;
+}
+
+template <class T>
+T* at(void* base, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+int launched(hipError_t e, const char* what) { return e == hipSuccess ? KCS_OK : hip_fail(e, what); }
+
+// Optional event timing of every launch (measurement only).
+struct TimedLaunch {
+    int kind;
+    hipEvent_t a, b;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<TimedLaunch> g_launches;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t pooled_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Runs `launch` (which enqueues work on `st`), bracketed by events when timing is enabled.
+template <class F>
+hipError_t timed(int kind, hipStream_t st, F&& launch) {
+    std::unique_lock<std::mutex> lk(g_tmu);
+    if (!g_timing) {
+        lk.unlock();
+        return launch();
+    }
+    hipEvent_t a = pooled_event(), b = pooled_event();
+    if (a) hipEventRecord(a, st);
+    const hipError_t e = launch();
+    if (b) hipEventRecord(b, st);
+    if (a && b) g_launches.push_back({kind, a, b});
+    return e;
+}
+
+// Internal bodies (arguments already validated)
+int do_setup(const Schedule& S, void* d_work, hipStream_t st) {
+    return launched(timed(KCS_T_SETUP, st, [&] { return launch_setup(S.setup, at<KinTab>(d_work, layout(nullptr, 0, 0).kin), st); }),
+                    "table setup");
+}
+
+int do_osl(const kcs_geometry& g, const Schedule& S, const kcs_prior& p, bool kp, const float* sino, const float* params,
+           int32_t q, int32_t Q, float* x, void* d_work, hipStream_t st) {
+    const Layout L = layout(&g, S.fr.M, Q);
+    OslArgs a{};
+    a.g = proj_args(g, S.fr, q, Q);
+    a.beta_kp = (float)p.beta_kp;
+    a.eps_F = (float)p.eps_F;
+    a.kp = kp ? 1 : 0;
+    float* ratio = at<float>(d_work, L.ratio);
+    KCS_TRY(launched(timed(KCS_T_PROJECT, st, [&] { return launch_project(S.fr.M, x, sino, ratio, a.g, true, st); }),
+                     "forward projection"));
+    return launched(
+        timed(KCS_T_OSL, st, [&] { return launch_osl(S.fr.M, ratio, params, at<KinTab>(d_work, L.kin), x, a, st); }),
+        "OSL update");
+}
+
+int do_lm(const kcs_geometry& g, const Schedule& S, const kcs_prior& p, const kcs_lm_opts& o, const float* x,
+          float* params, float* lam, void* d_work, int32_t Q, hipStream_t st) {
+    if (o.n_iter == 0) return KCS_OK;
+    const Layout L = layout(&g, S.fr.M, Q);
+    const size_t N = (size_t)g.nx * g.ny * g.nz;
+    LmArgs a{};
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.nz = g.nz;
+    a.fr = S.fr;
+    a.beta_h = (float)p.beta_h;
+    for (int i = 0; i < 3; ++i) {
+        a.delta[i] = (float)p.delta[i];
+        a.lo[i] = (float)o.lo[i];
+        a.hi[i] = (float)o.hi[i];
+    }
+    a.tau = (float)o.tau;
+    a.lam_min = (float)o.lam_min;
+    a.lam_max = (float)o.lam_max;
+    float* other = at<float>(d_work, L.xi);
+    // ping-pong so that the last iteration writes into `params`
+    float* src = params;
+    float* dst = other;
+    if (o.n_iter % 2 == 1) {
+        hipError_t e = timed(KCS_T_COPY, st, [&] {
+            return hipMemcpyAsync(other, params, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, st);
+        });
+        if (e != hipSuccess) return hip_fail(e, "map copy");
+        src = other;
+        dst = params;
+    }
+    const KinTab* K = at<KinTab>(d_work, L.kin);
+    for (int it = 0; it < o.n_iter; ++it) {
+        KCS_TRY(launched(timed(KCS_T_LM, st, [&] { return launch_lm(S.fr.M, K, x, src, dst, lam, a, st); }),
+                         "MAP-LM iteration"));
+        std::swap(src, dst);
+    }
+    return KCS_OK;
+}
+
+}  // namespace
+}  // namespace kcs
+
+using namespace kcs;
+
+extern "C" {
+
+const char* kcs_last_error(void) { return g_err.c_str(); }
+
+int kcs_timing_enable(int32_t on) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_timing = on != 0;
+    return KCS_OK;
+}
+
+int kcs_timing_collect(double* total_ms, int64_t* count) {
+    if (!total_ms || !count) return fail(KCS_EINVAL, "output arrays must not be NULL");
+    std::vector<TimedLaunch> ls;
+    {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        ls.swap(g_launches);
+    }
+    for (int k = 0; k < KCS_TIMING_KINDS; ++k) {
+        total_ms[k] = 0.0;
+        count[k] = 0;
+    }
+    int rc = KCS_OK;
+    for (const TimedLaunch& t : ls) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(t.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.a, t.b);
+        if (e != hipSuccess && rc == KCS_OK) rc = hip_fail(e, "timing event");
+        total_ms[t.kind] += ms;
+        count[t.kind] += 1;
+    }
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (const TimedLaunch& t : ls) {
+        g_event_pool.push_back(t.a);
+        g_event_pool.push_back(t.b);
+    }
+    return rc;
+}
+
+size_t kcs_workspace_bytes(const kcs_geometry* g, int32_t n_frames, int32_t Q) {
+    if (g && check_geometry(g) != KCS_OK) return 0;
+    if (Q < 0) Q = 0;
+    return layout(g, n_frames > 0 ? n_frames : kMaxFrames, Q).total;
+}
+
+size_t kcs_study_footprint_bytes(const kcs_geometry* g, int32_t n_frames, int32_t Q) {
+    if (!g || check_geometry(g) != KCS_OK) return 0;
+    const size_t N = (size_t)g->nx * g->ny * g->nz;
+    const size_t S = (size_t)g->nz * g->n_ang * g->n_bin * n_frames;
+    return (S + N * n_frames + 3 * N + N) * sizeof(float) + kcs_workspace_bytes(g, n_frames, Q);
+}
+
+int kcs_project(const kcs_geometry* g, const kcs_frames* f, const float* d_x, int32_t q, int32_t Q, float* d_ybar,
+                hipStream_t stream) {
+    KCS_TRY(check_geometry(g));
+    KCS_TRY(check_frames(f));
+    KCS_TRY(check_subset(g, q, Q));
+    if (!d_x || !d_ybar) return fail(KCS_EINVAL, "device pointers must not be NULL");
+    const Schedule S = make_schedule(*f, nullptr);
+    g_err.clear();
+    const ProjArgs pa = proj_args(*g, S.fr, q, Q);
+    return launched(
+        timed(KCS_T_PROJECT, stream, [&] { return launch_project(f->n_frames, d_x, nullptr, d_ybar, pa, false, stream); }),
+        "forward projection");
+}
+
+int kcs_backproject(const kcs_geometry* g, const kcs_frames* f, const float* d_y, int32_t q, int32_t Q, float* d_b,
+                    float* d_sens, hipStream_t stream) {
+    KCS_TRY(check_geometry(g));
+    KCS_TRY(check_frames(f));
+    KCS_TRY(check_subset(g, q, Q));
+    if (!d_y || !d_b) return fail(KCS_EINVAL, "device pointers must not be NULL");
+    const Schedule S = make_schedule(*f, nullptr);
+    g_err.clear();
+    const ProjArgs pa = proj_args(*g, S.fr, q, Q);
+    return launched(
+        timed(KCS_T_BACK, stream, [&] { return launch_backproject(f->n_frames, d_y, d_b, d_sens, pa, stream); }),
+        "back projection");
+}
+
+int kcs_model_tac(const kcs_frames* f, const kcs_kinetics* k, const float* d_params, int64_t n, float* d_F, float* d_J,
+                  void* d_work, size_t work_bytes, hipStream_t stream) {
+    KCS_TRY(check_frames(f));
+    KCS_TRY(check_kinetics(k));
+    if (n < 0) return fail(KCS_EINVAL, "n must be >= 0");
+    if (n > 0 && (!d_params || !d_F)) return fail(KCS_EINVAL, "device pointers must not be NULL");
+    KCS_TRY(check_work(nullptr, f->n_frames, 0, d_work, work_bytes));
+    if (n == 0) return KCS_OK;
+    const Schedule S = make_schedule(*f, k);
+    g_err.clear();
+    KCS_TRY(do_setup(S, d_work, stream));
+    const KinTab* K = at<KinTab>(d_work, layout(nullptr, 0, 0).kin);
+    return launched(
+        timed(KCS_T_MODEL, stream, [&] { return launch_model(f->n_frames, K, S.fr, d_params, n, d_F, d_J, stream); }),
+        "model evaluation");
+}
+
+int kcs_osl_update(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics* k, const kcs_prior* p,
+                   const float* d_sino, const float* d_params, int32_t q, int32_t Q, float* d_x, void* d_work,
+                   size_t work_bytes, hipStream_t stream) {
+    KCS_TRY(check_geometry(g));
+    KCS_TRY(check_frames(f));
+    KCS_TRY(check_kinetics(k));
+    KCS_TRY(check_prior(p));
+    KCS_TRY(check_subset(g, q, Q));
+    if (!d_sino || !d_x || (p->kp_on && !d_params)) return fail(KCS_EINVAL, "device pointers must not be NULL");
+    KCS_TRY(check_work(g, f->n_frames, Q, d_work, work_bytes));
+    const Schedule S = make_schedule(*f, k);
+    g_err.clear();
+    if (p->kp_on) KCS_TRY(do_setup(S, d_work, stream));
+    return do_osl(*g, S, *p, p->kp_on != 0, d_sino, d_params, q, Q, d_x, d_work, stream);
+}
+
+int kcs_lm_fit(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics* k, const kcs_prior* p,
+               const kcs_lm_opts* lm, const float* d_x, float* d_params, float* d_lambda, void* d_work,
+               size_t work_bytes, hipStream_t stream) {
+    KCS_TRY(check_geometry(g));
+    KCS_TRY(check_frames(f));
+    KCS_TRY(check_kinetics(k));
+    KCS_TRY(check_prior(p));
+    KCS_TRY(check_lm(lm));
+    if (!d_x || !d_params || !d_lambda) return fail(KCS_EINVAL, "device pointers must not be NULL");
+    KCS_TRY(check_work(g, f->n_frames, 0, d_work, work_bytes));
+    const Schedule S = make_schedule(*f, k);
+    g_err.clear();
+    KCS_TRY(do_setup(S, d_work, stream));
+    return do_lm(*g, S, *p, *lm, d_x, d_params, d_lambda, d_work, 0, stream);
+}
+
+int kcs_init_state(const kcs_geometry* g, const kcs_frames* f, const float* d_sino, const double xi0[3], float* d_x,
+                   float* d_params, float* d_lambda, void* d_work, size_t work_bytes, hipStream_t stream) {
+    KCS_TRY(check_geometry(g));
+    KCS_TRY(check_frames(f));
+    if (!d_sino || !d_x || !d_params || !d_lambda || !xi0) return fail(KCS_EINVAL, "pointers must not be NULL");
+    for (int i = 0; i < 3; ++i)
+        if (!is_finite(xi0[i])) return fail(KCS_EINVAL, "xi0 must be finite");
+    KCS_TRY(check_work(g, f->n_frames, 0, d_work, work_bytes));
+    const Schedule S = make_schedule(*f, nullptr);
+    const double sumP = total_path_length(*g);
+    if (!(sumP > 0)) return fail(KCS_EINVAL, "no ray crosses the image");
+    const Layout L = layout(g, f->n_frames, 0);
+    const int64_t rows = (int64_t)g->nz * g->n_ang * g->n_bin;
+    const int32_t N = g->nx * g->ny * g->nz;
+    g_err.clear();
+    return launched(timed(KCS_T_INIT, stream,
+                          [&] {
+                              return launch_init(f->n_frames, d_sino, rows, S.fr, sumP * g->nz, N, xi0,
+                                                 at<double>(d_work, L.init), kInitChunks, d_x, d_params, d_lambda,
+                                                 stream);
+                          }),
+                    "initial state");
+}
+
+int kcs_icm_sweep(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics* k, const kcs_prior* p,
+                  const kcs_lm_opts* lm, const float* d_sino, int32_t Q, int32_t sweep_idx, float* d_x, float* d_params,
+                  float* d_lambda, void* d_work, size_t work_bytes, hipStream_t stream) {
+    KCS_TRY(check_geometry(g));
+    KCS_TRY(check_frames(f));
+    KCS_TRY(check_kinetics(k));
+    KCS_TRY(check_prior(p));
+    KCS_TRY(check_lm(lm));
+    KCS_TRY(check_subset(g, 0, Q));
+    if (sweep_idx < 0) return fail(KCS_EINVAL, "sweep_idx must be >= 0");
+    if (!d_sino || !d_x || !d_params || !d_lambda) return fail(KCS_EINVAL, "device pointers must not be NULL");
+    KCS_TRY(check_work(g, f->n_frames, Q, d_work, work_bytes));
+    const Schedule S = make_schedule(*f, k);
+    g_err.clear();
+    KCS_TRY(do_setup(S, d_work, stream));
+    const bool kp = p->kp_on != 0 && sweep_idx > 0;
+    for (int32_t q = 0; q < Q; ++q) KCS_TRY(do_osl(*g, S, *p, kp, d_sino, d_params, q, Q, d_x, d_work, stream));
+    return do_lm(*g, S, *p, *lm, d_x, d_params, d_lambda, d_work, Q, stream);
+}
+
+}  // extern "C"

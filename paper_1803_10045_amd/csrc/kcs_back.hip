@@ -1,0 +1,165 @@
+// K-back: voxel-driven (gather) back projector and the fused OS-MAP-OSL-KP update.
+//
+// One thread per voxel.  For each angle of the subset the voxel's footprint on the detector
+// covers at most ceil(2 w1 / du) + 1 bins; the exact intersection length of each bin's ray with
+// the voxel square (the pixel chord, identical to the Siddon length of that ray in that pixel)
+// weights the bin's M-frame record.  The gather needs no atomics and no transposed system
+// matrix; the subset's angle constants are built once per workgroup in LDS.
+//
+// OSL update (Eq. 2 with the kinetics-derived potential of Eq. 3, sigma^2 = F / n):
+//   x_new = x * b / D,  b = E_m sum_d p_vd q_dm,  D = n_m (1 + beta (x - F) / max(F, eps_F)),
+//   n_m = E_m sum_d p_vd;  E_m cancels between b and D.  x is kept where sum_d p_vd = 0.
+#include "kcs_device.h"
+#include "kcs_launch.h"
+#include "kcs_model.h"
+
+namespace kcs {
+
+constexpr int kTileX = 64, kTileY = 4;
+constexpr int kMaxSubsetAngles = 1024;
+
+struct TileIdx {
+    int i, j, z;
+    bool valid;
+};
+
+__device__ __forceinline__ TileIdx tile_voxel(int nx, int ny, int nz) {
+    const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
+    const uint32_t tx = (nx + kTileX - 1) / kTileX, ty = (ny + kTileY - 1) / kTileY;
+    TileIdx t;
+    t.z = w / (tx * ty);
+    const uint32_t r = w % (tx * ty);
+    t.j = (r / tx) * kTileY + threadIdx.x / kTileX;
+    t.i = (r % tx) * kTileX + threadIdx.x % kTileX;
+    t.valid = t.z < nz && t.i < nx && t.j < ny;
+    return t;
+}
+
+__host__ inline uint32_t tile_blocks(int nx, int ny, int nz) {
+    const uint32_t tx = (nx + kTileX - 1) / kTileX, ty = (ny + kTileY - 1) / kTileY;
+    return xcd_round_up(tx * ty * (uint32_t)nz);
+}
+
+// Builds the subset's angle constants in LDS; all threads of the block take part.
+__device__ __forceinline__ void subset_angles_to_lds(AngleRec* sA, const ProjArgs& p) {
+    for (int al = threadIdx.x; al < p.A_q; al += blockDim.x) sA[al] = make_angle(p.q + al * p.Q, p.n_ang, p.ang0, p.h);
+    __syncthreads();
+}
+
+// acc_m = sum_{d in S_q} p_vd y_dm and sens = sum_{d in S_q} p_vd for voxel (i, j, z).
+template <int M>
+__device__ __forceinline__ void gather(const AngleRec* sA, const ProjArgs& p, const float* __restrict__ y, int i, int j,
+                                       int z, float (&acc)[M], float& sens) {
+    const float xc = ((float)i - 0.5f * (float)(p.nx - 1)) * p.h;
+    const float yc = ((float)j - 0.5f * (float)(p.ny - 1)) * p.h;
+    const float bc = 0.5f * (float)(p.n_bin - 1);
+#pragma unroll
+    for (int m = 0; m < M; ++m) acc[m] = 0.0f;
+    sens = 0.0f;
+    const float* yz = y + (size_t)z * p.A_q * p.n_bin * M;
+    for (int al = 0; al < p.A_q; ++al) {
+        const AngleRec A = sA[al];
+        const float tc = fmaf(xc, A.c, yc * A.s);  // voxel centre on the detector axis
+        const float beta = fmaf(tc, p.inv_du, bc);  // ... in bin units
+        const float rb = A.w1 * p.inv_du;
+        const int b0 = max((int)ceilf(beta - rb), 0);
+        const int b1 = min((int)floorf(beta + rb), p.n_bin - 1);
+        for (int b = b0; b <= b1; ++b) {
+            const float t = fmaf((float)b - bc, p.du, -tc);
+            const float len = pixel_chord(A, t);
+            if (len > 0.0f) {
+                float v[M];
+                load_record<M>(yz + ((size_t)al * p.n_bin + b) * M, v);
+#pragma unroll
+                for (int m = 0; m < M; ++m) acc[m] = fmaf(len, v[m], acc[m]);
+                sens += len;
+            }
+        }
+    }
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void kback_kernel(const float* __restrict__ y, float* __restrict__ bout,
+                                                    float* __restrict__ sens_out, ProjArgs p) {
+    extern __shared__ AngleRec sA[];
+    subset_angles_to_lds(sA, p);
+    const TileIdx t = tile_voxel(p.nx, p.ny, p.nz);
+    if (!t.valid) return;
+    float acc[M], sens;
+    gather<M>(sA, p, y, t.i, t.j, t.z, acc, sens);
+    const size_t v = ((size_t)t.z * p.ny + t.j) * p.nx + t.i;
+#pragma unroll
+    for (int m = 0; m < M; ++m) acc[m] *= p.fr.E[m];
+    store_record<M>(bout + v * M, acc);
+    if (sens_out) sens_out[v] = sens;
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void kosl_kernel(const float* __restrict__ ratio, const float* __restrict__ params,
+                                                   const KinTab* __restrict__ K, float* __restrict__ x, OslArgs a) {
+    extern __shared__ AngleRec sA[];
+    const ProjArgs& p = a.g;
+    subset_angles_to_lds(sA, p);
+    const TileIdx t = tile_voxel(p.nx, p.ny, p.nz);
+    if (!t.valid) return;
+    float acc[M], sens;
+    gather<M>(sA, p, ratio, t.i, t.j, t.z, acc, sens);
+    if (!(sens > 0.0f)) return;  // no ray of this subset sees the voxel: keep x
+    const size_t v = ((size_t)t.z * p.ny + t.j) * p.nx + t.i;
+    float xv[M];
+    load_record<M>(x + v * M, xv);
+    const float inv_sens = 1.0f / sens;
+    if (a.kp) {
+        const size_t N = (size_t)p.nx * p.ny * p.nz;
+        const float K1 = params[v], k2 = params[N + v], k3 = params[2 * N + v];
+        model_frames<M, false>(p.fr, *K, K1, k2, k3, [&](int m, float F, float, float, float) {
+            const float d = fmaf(a.beta_kp, (xv[m] - F) / fmaxf(F, a.eps_F), 1.0f);
+            xv[m] = xv[m] * acc[m] * inv_sens / d;
+        });
+    } else {
+#pragma unroll
+        for (int m = 0; m < M; ++m) xv[m] = xv[m] * acc[m] * inv_sens;
+    }
+    store_record<M>(x + v * M, xv);
+}
+
+template <int M>
+static hipError_t launch_back_m(const float* y, float* b, float* sens, const ProjArgs& p, hipStream_t st) {
+    hipLaunchKernelGGL((kback_kernel<M>), dim3(tile_blocks(p.nx, p.ny, p.nz)), dim3(kTileX * kTileY), p.A_q * sizeof(AngleRec), st, y, b,
+                       sens, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_backproject(int M, const float* y, float* b, float* sens, const ProjArgs& p, hipStream_t st) {
+    if (p.A_q > kMaxSubsetAngles) return hipErrorInvalidValue;
+    switch (M) {
+        case 8: return launch_back_m<8>(y, b, sens, p, st);
+        case 16: return launch_back_m<16>(y, b, sens, p, st);
+        case 24: return launch_back_m<24>(y, b, sens, p, st);
+        case 32: return launch_back_m<32>(y, b, sens, p, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int M>
+static hipError_t launch_osl_m(const float* ratio, const float* params, const KinTab* K, float* x, const OslArgs& a,
+                               hipStream_t st) {
+    const ProjArgs& p = a.g;
+    hipLaunchKernelGGL((kosl_kernel<M>), dim3(tile_blocks(p.nx, p.ny, p.nz)), dim3(kTileX * kTileY), p.A_q * sizeof(AngleRec), st, ratio,
+                       params, K, x, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_osl(int M, const float* ratio, const float* params, const KinTab* K, float* x, const OslArgs& a,
+                      hipStream_t st) {
+    if (a.g.A_q > kMaxSubsetAngles) return hipErrorInvalidValue;
+    switch (M) {
+        case 8: return launch_osl_m<8>(ratio, params, K, x, a, st);
+        case 16: return launch_osl_m<16>(ratio, params, K, x, a, st);
+        case 24: return launch_osl_m<24>(ratio, params, K, x, a, st);
+        case 32: return launch_osl_m<32>(ratio, params, K, x, a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace kcs

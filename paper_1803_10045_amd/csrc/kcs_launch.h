@@ -1,0 +1,58 @@
+// Kernel launchers and their argument blocks (host side of libkcs).
+#pragma once
+
+#include "kcs_internal.h"
+
+namespace kcs {
+
+// Arguments common to the projector kernels (passed by value).
+struct ProjArgs {
+    int32_t nx, ny, nz, n_ang, n_bin;
+    int32_t q, Q, A_q;        // subset q of Q holds angles q, q+Q, ...; A_q of them
+    int32_t rays_per_plane;   // A_q * n_bin
+    float h, inv_h, du, inv_du;
+    double ang0;
+    FrameTab fr;
+};
+
+// Arguments of the OSL update: projector geometry plus the prior.
+struct OslArgs {
+    ProjArgs g;
+    float beta_kp, eps_F;
+    int32_t kp;
+};
+
+// Arguments of one MAP-LM iteration.
+struct LmArgs {
+    int32_t nx, ny, nz;
+    FrameTab fr;
+    float beta_h;
+    float delta[3];
+    float tau, lam_min, lam_max;
+    float lo[3], hi[3];
+};
+
+// Inputs of the FP64 table-setup kernel.
+struct SetupArgs {
+    double A1, A2, A3, l[3], vb;
+    int32_t n_bound;
+    double t[kMaxBoundaries];
+    int32_t M;
+    int32_t i0[kMaxFrames], i1[kMaxFrames];
+};
+
+hipError_t launch_setup(const SetupArgs& s, KinTab* K, hipStream_t st);
+hipError_t launch_project(int M, const float* x, const float* sino, float* out, const ProjArgs& p, bool ratio,
+                          hipStream_t st);
+hipError_t launch_backproject(int M, const float* y, float* b, float* sens, const ProjArgs& p, hipStream_t st);
+hipError_t launch_osl(int M, const float* ratio, const float* params, const KinTab* K, float* x, const OslArgs& a,
+                      hipStream_t st);
+hipError_t launch_lm(int M, const KinTab* K, const float* x, const float* xi_in, float* xi_out, float* lam,
+                     const LmArgs& a, hipStream_t st);
+hipError_t launch_model(int M, const KinTab* K, const FrameTab& fr, const float* params, int64_t n, float* F, float* J,
+                        hipStream_t st);
+hipError_t launch_init(int M, const float* sino, int64_t rows, const FrameTab& fr, double denom_scale, int32_t nz_ny_nx,
+                       const double xi0[3], double* partial, int32_t n_partial, float* x, float* params, float* lam,
+                       hipStream_t st);
+
+}  // namespace kcs

@@ -1,0 +1,154 @@
+// K-lm: one synchronous MAP Levenberg-Marquardt iteration (Eq. 4-7), one thread per voxel.
+//
+// Per voxel: model TAC F and its 3 Jacobian columns from the closed form (frame by frame,
+// accumulating J^T J and J^T r on the fly, so no Jacobian is stored), the Huber neighbour
+// gradient over the in-plane 8-neighbourhood read from the previous maps (Jacobi update, all
+// voxels see the same old neighbours), the damped 3x3 normal equations solved by a
+// diagonally scaled Cholesky factorisation in registers, box clipping, and the accept test.
+// The test uses the exact change of the voxel's objective,
+//   dPhi = sum_m (F_m - F'_m)(2 x_m - F_m - F'_m) / 2 + beta_h (E(xi') - E(xi)),
+// which equals Phi(xi') - Phi(xi) but avoids cancelling two large sums in FP32.
+#include "kcs_device.h"
+#include "kcs_launch.h"
+#include "kcs_model.h"
+
+namespace kcs {
+
+constexpr int kLmTileX = 64, kLmTileY = 4;
+
+__device__ __forceinline__ float huber(float t, float d) {
+    const float at = fabsf(t);
+    return at <= d ? 0.5f * t * t : d * at - 0.5f * d * d;
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void klm_kernel(const KinTab* __restrict__ K, const float* __restrict__ x,
+                                                  const float* __restrict__ xi_in, float* __restrict__ xi_out,
+                                                  float* __restrict__ lam_io, LmArgs a) {
+    const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
+    const uint32_t tx = (a.nx + kLmTileX - 1) / kLmTileX, ty = (a.ny + kLmTileY - 1) / kLmTileY;
+    const int z = w / (tx * ty);
+    const uint32_t rr = w % (tx * ty);
+    const int j = (rr / tx) * kLmTileY + threadIdx.x / kLmTileX;
+    const int i = (rr % tx) * kLmTileX + threadIdx.x % kLmTileX;
+    if (z >= a.nz || i >= a.nx || j >= a.ny) return;
+    const size_t plane = (size_t)a.nx * a.ny;
+    const size_t N = plane * a.nz;
+    const size_t v = (size_t)z * plane + (size_t)j * a.nx + i;
+
+    float xv[M];
+    load_record<M>(x + v * M, xv);
+    const float p0 = xi_in[v], p1 = xi_in[N + v], p2 = xi_in[2 * N + v];
+
+    // neighbours from the previous maps
+    float nb[8][3], wn[8];
+    int nn = 0;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            if (dy == 0 && dx == 0) continue;
+            const int jj = j + dy, ii = i + dx;
+            const bool in = jj >= 0 && jj < a.ny && ii >= 0 && ii < a.nx;
+            const size_t u = in ? (size_t)z * plane + (size_t)jj * a.nx + ii : v;
+            nb[nn][0] = xi_in[u];
+            nb[nn][1] = xi_in[N + u];
+            nb[nn][2] = xi_in[2 * N + u];
+            wn[nn] = in ? ((dy == 0 || dx == 0) ? 1.0f : 0.70710678118654752f) : 0.0f;
+            ++nn;
+        }
+    }
+    float psi[3] = {0.0f, 0.0f, 0.0f}, e0 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float d0 = p0 - nb[k][0], d1 = p1 - nb[k][1], d2 = p2 - nb[k][2];
+        psi[0] += wn[k] * fminf(fmaxf(d0, -a.delta[0]), a.delta[0]);
+        psi[1] += wn[k] * fminf(fmaxf(d1, -a.delta[1]), a.delta[1]);
+        psi[2] += wn[k] * fminf(fmaxf(d2, -a.delta[2]), a.delta[2]);
+        e0 += wn[k] * (huber(d0, a.delta[0]) + huber(d1, a.delta[1]) + huber(d2, a.delta[2]));
+    }
+
+    // model, Jacobian and normal equations at the current parameters
+    float F0[M];
+    float A00 = 0, A01 = 0, A02 = 0, A11 = 0, A12 = 0, A22 = 0, g0 = 0, g1 = 0, g2 = 0;
+    model_frames<M, true>(a.fr, *K, p0, p1, p2, [&](int m, float F, float j0, float j1, float j2) {
+        F0[m] = F;
+        const float r = xv[m] - F;
+        A00 = fmaf(j0, j0, A00);
+        A01 = fmaf(j0, j1, A01);
+        A02 = fmaf(j0, j2, A02);
+        A11 = fmaf(j1, j1, A11);
+        A12 = fmaf(j1, j2, A12);
+        A22 = fmaf(j2, j2, A22);
+        g0 = fmaf(j0, r, g0);
+        g1 = fmaf(j1, r, g1);
+        g2 = fmaf(j2, r, g2);
+    });
+    g0 -= a.beta_h * psi[0];
+    g1 -= a.beta_h * psi[1];
+    g2 -= a.beta_h * psi[2];
+
+    float lam = lam_io[v];
+    if (!(lam > 0.0f)) lam = a.tau * fmaxf(A00, fmaxf(A11, A22));
+
+    // (A + lam I) step = g, symmetrically scaled by the inverse square roots of the diagonal,
+    // then a Cholesky factorisation in registers
+    const float s0 = rsqrtf(A00 + lam), s1 = rsqrtf(A11 + lam), s2 = rsqrtf(A22 + lam);
+    const float B00 = (A00 + lam) * s0 * s0, B11 = (A11 + lam) * s1 * s1, B22 = (A22 + lam) * s2 * s2;
+    const float B01 = A01 * s0 * s1, B02 = A02 * s0 * s2, B12 = A12 * s1 * s2;
+    const float L00 = sqrtf(B00);
+    const float L10 = B01 / L00, L20 = B02 / L00;
+    const float L11 = sqrtf(fmaxf(B11 - L10 * L10, 1e-30f));
+    const float L21 = (B12 - L20 * L10) / L11;
+    const float L22 = sqrtf(fmaxf(B22 - L20 * L20 - L21 * L21, 1e-30f));
+    const float y0 = g0 * s0 / L00;
+    const float y1 = (g1 * s1 - L10 * y0) / L11;
+    const float y2 = (g2 * s2 - L20 * y0 - L21 * y1) / L22;
+    const float z2 = y2 / L22;
+    const float z1 = (y1 - L21 * z2) / L11;
+    const float z0 = (y0 - L10 * z1 - L20 * z2) / L00;
+    const float q0 = fminf(fmaxf(p0 + z0 * s0, a.lo[0]), a.hi[0]);
+    const float q1 = fminf(fmaxf(p1 + z1 * s1, a.lo[1]), a.hi[1]);
+    const float q2 = fminf(fmaxf(p2 + z2 * s2, a.lo[2]), a.hi[2]);
+
+    float e1 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        e1 += wn[k] * (huber(q0 - nb[k][0], a.delta[0]) + huber(q1 - nb[k][1], a.delta[1]) +
+                       huber(q2 - nb[k][2], a.delta[2]));
+
+    float dphi = 0.0f;
+    model_frames<M, false>(a.fr, *K, q0, q1, q2, [&](int m, float F, float, float, float) {
+        const float df = F0[m] - F;
+        dphi = fmaf(0.5f * df, 2.0f * xv[m] - F0[m] - F, dphi);
+    });
+    dphi = fmaf(a.beta_h, e1 - e0, dphi);
+
+    const bool accept = dphi < 0.0f;
+    xi_out[v] = accept ? q0 : p0;
+    xi_out[N + v] = accept ? q1 : p1;
+    xi_out[2 * N + v] = accept ? q2 : p2;
+    lam_io[v] = accept ? fmaxf(lam * 0.1f, a.lam_min) : fminf(lam * 10.0f, a.lam_max);
+}
+
+template <int M>
+static hipError_t launch_lm_m(const KinTab* K, const float* x, const float* xi_in, float* xi_out, float* lam,
+                              const LmArgs& a, hipStream_t st) {
+    const uint32_t tx = (a.nx + kLmTileX - 1) / kLmTileX, ty = (a.ny + kLmTileY - 1) / kLmTileY;
+    const uint32_t n = xcd_round_up(tx * ty * (uint32_t)a.nz);
+    hipLaunchKernelGGL((klm_kernel<M>), dim3(n), dim3(kLmTileX * kLmTileY), 0, st, K, x, xi_in, xi_out, lam, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lm(int M, const KinTab* K, const float* x, const float* xi_in, float* xi_out, float* lam,
+                     const LmArgs& a, hipStream_t st) {
+    switch (M) {
+        case 8: return launch_lm_m<8>(K, x, xi_in, xi_out, lam, a, st);
+        case 16: return launch_lm_m<16>(K, x, xi_in, xi_out, lam, a, st);
+        case 24: return launch_lm_m<24>(K, x, xi_in, xi_out, lam, a, st);
+        case 32: return launch_lm_m<32>(K, x, xi_in, xi_out, lam, a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace kcs

@@ -1,0 +1,319 @@
+"""Python binding of libkcs (include/kcs.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and forwards device pointers of
+FP32 torch tensors plus the current torch stream; all arithmetic happens in the HIP library.
+If the library is not built the import of any entry point raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from functools import lru_cache
+from typing import Optional, Sequence
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkcs.so")
+
+KCS_OK, KCS_EINVAL, KCS_ESHAPE, KCS_EWORKSPACE, KCS_EHIP = 0, -1, -2, -3, -4
+
+# Entry points declared in include/kcs.h (checked against the header by the tests).
+ENTRY_POINTS = ("kcs_workspace_bytes", "kcs_study_footprint_bytes", "kcs_project", "kcs_backproject",
+                "kcs_model_tac", "kcs_osl_update", "kcs_lm_fit", "kcs_init_state", "kcs_icm_sweep",
+                "kcs_timing_enable", "kcs_timing_collect", "kcs_last_error")
+
+TIMING_KINDS = ("setup", "project", "back", "osl", "lm", "model", "init", "copy")
+
+
+class KcsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"kcs error {code}: {msg}")
+        self.code = code
+
+
+class c_geometry(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("pixel_mm", ctypes.c_double),
+                ("n_ang", ctypes.c_int32), ("n_bin", ctypes.c_int32), ("bin_mm", ctypes.c_double),
+                ("ang0_rad", ctypes.c_double)]
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class c_frames(ctypes.Structure):
+    _fields_ = [("n_frames", ctypes.c_int32), ("t0_min", _dp), ("t1_min", _dp), ("scale", _dp), ("bg", _dp)]
+
+
+class c_kinetics(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("A1", "A2", "A3", "l1", "l2", "l3", "vb")]
+
+
+class c_prior(ctypes.Structure):
+    _fields_ = [("beta_kp", ctypes.c_double), ("eps_F", ctypes.c_double), ("beta_h", ctypes.c_double),
+                ("delta", ctypes.c_double * 3), ("kp_on", ctypes.c_int32)]
+
+
+class c_lm_opts(ctypes.Structure):
+    _fields_ = [("n_iter", ctypes.c_int32), ("tau", ctypes.c_double), ("lam_min", ctypes.c_double),
+                ("lam_max", ctypes.c_double), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+
+
+@lru_cache(maxsize=1)
+def lib() -> ctypes.CDLL:
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is not built; run __graft_entry__.build() or "
+                          "python paper_1803_10045_amd/build.py")
+    L = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.POINTER
+    vp, sz, i32, i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64
+    L.kcs_workspace_bytes.argtypes = [P(c_geometry), i32, i32]
+    L.kcs_workspace_bytes.restype = sz
+    L.kcs_study_footprint_bytes.argtypes = [P(c_geometry), i32, i32]
+    L.kcs_study_footprint_bytes.restype = sz
+    L.kcs_project.argtypes = [P(c_geometry), P(c_frames), vp, i32, i32, vp, vp]
+    L.kcs_backproject.argtypes = [P(c_geometry), P(c_frames), vp, i32, i32, vp, vp, vp]
+    L.kcs_model_tac.argtypes = [P(c_frames), P(c_kinetics), vp, i64, vp, vp, vp, sz, vp]
+    L.kcs_osl_update.argtypes = [P(c_geometry), P(c_frames), P(c_kinetics), P(c_prior), vp, vp, i32, i32, vp, vp, sz,
+                                 vp]
+    L.kcs_lm_fit.argtypes = [P(c_geometry), P(c_frames), P(c_kinetics), P(c_prior), P(c_lm_opts), vp, vp, vp, vp, sz,
+                             vp]
+    L.kcs_init_state.argtypes = [P(c_geometry), P(c_frames), vp, P(ctypes.c_double), vp, vp, vp, vp, sz, vp]
+    L.kcs_icm_sweep.argtypes = [P(c_geometry), P(c_frames), P(c_kinetics), P(c_prior), P(c_lm_opts), vp, i32, i32, vp,
+                                vp, vp, vp, sz, vp]
+    for name in ("kcs_project", "kcs_backproject", "kcs_model_tac", "kcs_osl_update", "kcs_lm_fit",
+                 "kcs_init_state", "kcs_icm_sweep"):
+        getattr(L, name).restype = ctypes.c_int
+    L.kcs_timing_enable.argtypes = [i32]
+    L.kcs_timing_enable.restype = ctypes.c_int
+    L.kcs_timing_collect.argtypes = [P(ctypes.c_double), P(ctypes.c_int64)]
+    L.kcs_timing_collect.restype = ctypes.c_int
+    L.kcs_last_error.argtypes = []
+    L.kcs_last_error.restype = ctypes.c_char_p
+    return L
+
+
+# ----------------------------------------------------------------------------------------------
+# Host-side argument objects
+# ----------------------------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class Geometry:
+    nx: int
+    ny: int
+    nz: int
+    pixel_mm: float
+    n_ang: int
+    n_bin: int
+    bin_mm: float
+    ang0_rad: float = 0.0
+
+    @classmethod
+    def from_config(cls, cfg) -> "Geometry":
+        return cls(cfg.nx, cfg.ny, cfg.nz, cfg.pixel_mm, cfg.n_ang, cfg.n_bin, cfg.bin_mm, cfg.ang0)
+
+    def c(self) -> c_geometry:
+        return c_geometry(self.nx, self.ny, self.nz, self.pixel_mm, self.n_ang, self.n_bin, self.bin_mm, self.ang0_rad)
+
+    @property
+    def n_vox(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def subset_size(self, q: int, Q: int) -> int:
+        return (self.n_ang - q + Q - 1) // Q
+
+
+class Frames:
+    """Frame schedule (minutes) with per-frame scale E_m and background r_m (FP64 host arrays)."""
+
+    def __init__(self, t0, t1, scale, bg):
+        self.t0 = np.ascontiguousarray(t0, dtype=np.float64)
+        self.t1 = np.ascontiguousarray(t1, dtype=np.float64)
+        self.scale = np.ascontiguousarray(scale, dtype=np.float64)
+        self.bg = np.ascontiguousarray(bg, dtype=np.float64)
+        n = len(self.t0)
+        if not (len(self.t1) == len(self.scale) == len(self.bg) == n):
+            raise ValueError("frame arrays must have equal length")
+
+    @property
+    def M(self) -> int:
+        return len(self.t0)
+
+    def c(self) -> c_frames:
+        p = lambda a: a.ctypes.data_as(_dp)
+        return c_frames(self.M, p(self.t0), p(self.t1), p(self.scale), p(self.bg))
+
+
+@dataclass(frozen=True)
+class Kinetics:
+    A1: float
+    A2: float
+    A3: float
+    l1: float
+    l2: float
+    l3: float
+    vb: float
+
+    def c(self) -> c_kinetics:
+        return c_kinetics(self.A1, self.A2, self.A3, self.l1, self.l2, self.l3, self.vb)
+
+
+@dataclass(frozen=True)
+class Prior:
+    beta_kp: float
+    eps_F: float
+    beta_h: float
+    delta: Sequence[float]
+    kp_on: bool = True
+
+    def c(self) -> c_prior:
+        return c_prior(self.beta_kp, self.eps_F, self.beta_h, (ctypes.c_double * 3)(*self.delta), int(self.kp_on))
+
+
+@dataclass(frozen=True)
+class LMOptions:
+    n_iter: int
+    tau: float
+    lam_min: float
+    lam_max: float
+    lo: Sequence[float]
+    hi: Sequence[float]
+
+    def c(self) -> c_lm_opts:
+        return c_lm_opts(self.n_iter, self.tau, self.lam_min, self.lam_max, (ctypes.c_double * 3)(*self.lo),
+                         (ctypes.c_double * 3)(*self.hi))
+
+
+# ----------------------------------------------------------------------------------------------
+# Marshalling helpers
+# ----------------------------------------------------------------------------------------------
+
+def _stream(stream) -> ctypes.c_void_p:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t, shape=None, name="tensor", dtype=None) -> ctypes.c_void_p:
+    import torch
+    if t is None:
+        return ctypes.c_void_p(0)
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    want = torch.float32 if dtype is None else dtype
+    if t.dtype != want:
+        raise ValueError(f"{name} must be {want}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(rc: int):
+    if rc != KCS_OK:
+        raise KcsError(rc, lib().kcs_last_error().decode())
+
+
+def _work(w):
+    import torch
+    if w is None or not w.is_cuda or w.dtype != torch.uint8:
+        raise ValueError("workspace must be a uint8 device tensor")
+    return ctypes.c_void_p(w.data_ptr()), ctypes.c_size_t(w.numel())
+
+
+# ----------------------------------------------------------------------------------------------
+# Entry points
+# ----------------------------------------------------------------------------------------------
+
+def kcs_workspace_bytes(g: Optional[Geometry], n_frames: int, Q: int) -> int:
+    gc = g.c() if g is not None else None
+    return int(lib().kcs_workspace_bytes(ctypes.byref(gc) if gc is not None else None, n_frames, Q))
+
+
+def kcs_study_footprint_bytes(g: Geometry, n_frames: int, Q: int) -> int:
+    gc = g.c()
+    return int(lib().kcs_study_footprint_bytes(ctypes.byref(gc), n_frames, Q))
+
+
+def alloc_workspace(g: Optional[Geometry], n_frames: int, Q: int, device="cuda"):
+    import torch
+    return torch.empty(max(kcs_workspace_bytes(g, n_frames, Q), 256), dtype=torch.uint8, device=device)
+
+
+def kcs_project(g: Geometry, f: Frames, x, q: int, Q: int, ybar, stream=None):
+    M = f.M
+    gc, fc = g.c(), f.c()
+    _check(lib().kcs_project(ctypes.byref(gc), ctypes.byref(fc), _ptr(x, (g.nz, g.ny, g.nx, M), "x"), q, Q,
+                             _ptr(ybar, (g.nz, g.subset_size(q, Q), g.n_bin, M), "ybar"), _stream(stream)))
+
+
+def kcs_backproject(g: Geometry, f: Frames, y, q: int, Q: int, b, sens=None, stream=None):
+    M = f.M
+    gc, fc = g.c(), f.c()
+    _check(lib().kcs_backproject(ctypes.byref(gc), ctypes.byref(fc),
+                                 _ptr(y, (g.nz, g.subset_size(q, Q), g.n_bin, M), "y"), q, Q,
+                                 _ptr(b, (g.nz, g.ny, g.nx, M), "b"), _ptr(sens, (g.nz, g.ny, g.nx), "sens"),
+                                 _stream(stream)))
+
+
+def kcs_model_tac(f: Frames, k: Kinetics, params, F, J=None, work=None, stream=None):
+    n = params.shape[1]
+    fc, kc = f.c(), k.c()
+    wp, wn = _work(work)
+    _check(lib().kcs_model_tac(ctypes.byref(fc), ctypes.byref(kc), _ptr(params, (3, n), "params"), n,
+                               _ptr(F, (n, f.M), "F"), _ptr(J, (n, f.M, 3), "J"), wp, wn, _stream(stream)))
+
+
+def kcs_osl_update(g: Geometry, f: Frames, k: Kinetics, p: Prior, sino, params, q: int, Q: int, x, work,
+                   stream=None):
+    gc, fc, kc, pc = g.c(), f.c(), k.c(), p.c()
+    wp, wn = _work(work)
+    _check(lib().kcs_osl_update(ctypes.byref(gc), ctypes.byref(fc), ctypes.byref(kc), ctypes.byref(pc),
+                                _ptr(sino, (g.nz, g.n_ang, g.n_bin, f.M), "sino"),
+                                _ptr(params, (3, g.nz, g.ny, g.nx), "params"), q, Q,
+                                _ptr(x, (g.nz, g.ny, g.nx, f.M), "x"), wp, wn, _stream(stream)))
+
+
+def kcs_lm_fit(g: Geometry, f: Frames, k: Kinetics, p: Prior, lm: LMOptions, x, params, lam, work, stream=None):
+    gc, fc, kc, pc, lc = g.c(), f.c(), k.c(), p.c(), lm.c()
+    wp, wn = _work(work)
+    _check(lib().kcs_lm_fit(ctypes.byref(gc), ctypes.byref(fc), ctypes.byref(kc), ctypes.byref(pc), ctypes.byref(lc),
+                            _ptr(x, (g.nz, g.ny, g.nx, f.M), "x"), _ptr(params, (3, g.nz, g.ny, g.nx), "params"),
+                            _ptr(lam, (g.nz, g.ny, g.nx), "lambda"), wp, wn, _stream(stream)))
+
+
+def kcs_init_state(g: Geometry, f: Frames, sino, xi0, x, params, lam, work, stream=None):
+    gc, fc = g.c(), f.c()
+    xi = (ctypes.c_double * 3)(*xi0)
+    wp, wn = _work(work)
+    _check(lib().kcs_init_state(ctypes.byref(gc), ctypes.byref(fc), _ptr(sino, (g.nz, g.n_ang, g.n_bin, f.M), "sino"),
+                                xi, _ptr(x, (g.nz, g.ny, g.nx, f.M), "x"), _ptr(params, (3, g.nz, g.ny, g.nx), "params"),
+                                _ptr(lam, (g.nz, g.ny, g.nx), "lambda"), wp, wn, _stream(stream)))
+
+
+def kcs_icm_sweep(g: Geometry, f: Frames, k: Kinetics, p: Prior, lm: LMOptions, sino, Q: int, sweep_idx: int, x,
+                  params, lam, work, stream=None):
+    gc, fc, kc, pc, lc = g.c(), f.c(), k.c(), p.c(), lm.c()
+    wp, wn = _work(work)
+    _check(lib().kcs_icm_sweep(ctypes.byref(gc), ctypes.byref(fc), ctypes.byref(kc), ctypes.byref(pc),
+                               ctypes.byref(lc), _ptr(sino, (g.nz, g.n_ang, g.n_bin, f.M), "sino"), Q, sweep_idx,
+                               _ptr(x, (g.nz, g.ny, g.nx, f.M), "x"), _ptr(params, (3, g.nz, g.ny, g.nx), "params"),
+                               _ptr(lam, (g.nz, g.ny, g.nx), "lambda"), wp, wn, _stream(stream)))
+
+
+def kcs_timing_enable(on: bool):
+    _check(lib().kcs_timing_enable(1 if on else 0))
+
+
+def kcs_timing_collect() -> dict:
+    """{kind: (total_ms, launches)} for the launches recorded since the last collection."""
+    n = len(TIMING_KINDS)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    _check(lib().kcs_timing_collect(ms, cnt))
+    return {k: (ms[i], int(cnt[i])) for i, k in enumerate(TIMING_KINDS)}
+
+
+def kcs_last_error() -> str:
+    return lib().kcs_last_error().decode()

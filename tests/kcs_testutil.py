@@ -1,0 +1,45 @@
+"""Helpers shared by the GPU parity tests: oracle study -> binding objects and device tensors."""
+import numpy as np
+
+import oracle
+from paper_1803_10045_amd import inputs
+from paper_1803_10045_amd import kcs
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def kcs_objects(st):
+    """Binding objects carrying exactly the oracle study's constants."""
+    g = kcs.Geometry(st.geom.nx, st.geom.ny, st.geom.nz, st.geom.h, st.geom.n_ang, st.geom.n_bin, st.geom.du,
+                     st.geom.ang0)
+    f = kcs.Frames(st.frames.t0, st.frames.t1, st.frames.E, st.frames.r)
+    k = kcs.Kinetics(st.kin.A1, st.kin.A2, st.kin.A3, st.kin.l1, st.kin.l2, st.kin.l3, st.kin.vb)
+    p = kcs.Prior(st.prior.beta_kp, st.prior.eps_F, st.prior.beta_h, st.prior.delta, st.prior.kp_on)
+    lm = kcs.LMOptions(st.lm.n_iter, st.lm.tau, st.lm.lam_min, st.lm.lam_max, st.lm.lo, st.lm.hi)
+    return g, f, k, p, lm
+
+
+def geometry_pair(nx, ny, nz, h, n_ang, n_bin, du, ang0=0.0):
+    return (oracle.Geometry(nx, ny, nz, h, n_ang, n_bin, du, ang0),
+            kcs.Geometry(nx, ny, nz, h, n_ang, n_bin, du, ang0))
+
+
+def make_image(nz, ny, nx, M, seed):
+    """Positive, smooth-plus-noise image, exactly representable in FP32."""
+    rng = np.random.default_rng(seed)
+    yy, xx = np.meshgrid(np.linspace(-1, 1, ny), np.linspace(-1, 1, nx), indexing="ij")
+    base = np.exp(-2 * (xx ** 2 + yy ** 2))[None, :, :, None] * np.linspace(1, 5, M)[None, None, None, :]
+    img = base * (1 + 0.3 * rng.random((nz, ny, nx, M))) + 0.1 * rng.random((nz, ny, nx, M))
+    return img.astype(np.float32).astype(np.float64)
+
+
+def default_frames(M=24, seed=0):
+    t0, t1 = inputs.frame_times()
+    rng = np.random.default_rng(seed)
+    E = (t1 - t0) * rng.uniform(0.5, 2.0)
+    r = rng.uniform(0.01, 0.3, M)
+    return oracle.Frames(t0, t1, E, r)

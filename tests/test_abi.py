@@ -1,0 +1,104 @@
+"""The C ABI: the library loads, exports every entry point the header declares, and rejects
+invalid arguments on the host before launching anything (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1803_10045_amd import inputs
+from paper_1803_10045_amd import kcs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "kcs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kcs_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_entry_point():
+    L = kcs.lib()
+    names = header_functions()
+    assert set(names) == set(kcs.ENTRY_POINTS)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def geometry():
+    return kcs.Geometry.from_config(inputs.cfg1())
+
+
+def frames(M=24):
+    t0, t1 = inputs.frame_times()
+    return kcs.Frames(t0[:M], t1[:M], np.ones(M), np.zeros(M))
+
+
+def call_project(g, f, q=0, Q=4, x=1, y=1):
+    gc, fc = g.c(), f.c()
+    return kcs.lib().kcs_project(ctypes.byref(gc), ctypes.byref(fc), ctypes.c_void_p(x), q, Q, ctypes.c_void_p(y),
+                                 None)
+
+
+def test_workspace_sizes():
+    g = geometry()
+    w4 = kcs.kcs_workspace_bytes(g, 24, 4)
+    w1 = kcs.kcs_workspace_bytes(g, 24, 1)
+    w0 = kcs.kcs_workspace_bytes(g, 24, 0)
+    assert w0 < w4 < w1
+    # the ratio buffer holds the largest subset's sinogram
+    assert w1 - w0 >= g.nz * g.n_ang * g.n_bin * 24 * 4
+    assert kcs.kcs_study_footprint_bytes(g, 24, 4) > w4
+    assert kcs.kcs_workspace_bytes(None, 24, 0) > 0
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(q=4, Q=4), kcs.KCS_EINVAL), (dict(q=0, Q=0), kcs.KCS_EINVAL), (dict(q=0, Q=61), kcs.KCS_EINVAL),
+    (dict(x=0), kcs.KCS_EINVAL), (dict(y=0), kcs.KCS_EINVAL)])
+def test_project_rejects_bad_arguments(bad, code):
+    assert call_project(geometry(), frames(), **bad) == code
+    assert kcs.kcs_last_error() != ""
+
+
+def test_bad_geometry_and_frames():
+    g = geometry()
+    bad = kcs.Geometry(0, 64, 1, 4.0, 60, 64, 4.0)
+    assert call_project(bad, frames()) == kcs.KCS_EINVAL
+    neg = kcs.Geometry(64, 64, 1, -1.0, 60, 64, 4.0)
+    assert call_project(neg, frames()) == kcs.KCS_EINVAL
+    assert call_project(g, frames(M=12)) == kcs.KCS_ESHAPE
+    t0, t1 = inputs.frame_times()
+    unsorted = kcs.Frames(t0[::-1].copy(), t1[::-1].copy(), np.ones(24), np.zeros(24))
+    assert call_project(g, unsorted) == kcs.KCS_EINVAL
+    negscale = kcs.Frames(t0, t1, -np.ones(24), np.zeros(24))
+    assert call_project(g, negscale) == kcs.KCS_EINVAL
+
+
+def test_priors_and_lm_options_validated():
+    g = geometry()
+    f = frames()
+    k = kcs.Kinetics(**inputs.FENG, vb=inputs.VB).c()
+    gc, fc = g.c(), f.c()
+    good_p = kcs.Prior(0.1, 0.01, 0.1, (1e-3,) * 3).c()
+    good_l = kcs.LMOptions(5, 1e-3, 1e-8, 1e8, inputs.LM_LO, inputs.LM_HI).c()
+    vp = ctypes.c_void_p
+    work = ctypes.c_size_t(1 << 30)
+
+    def lm(p, l):
+        return kcs.lib().kcs_lm_fit(ctypes.byref(gc), ctypes.byref(fc), ctypes.byref(k), ctypes.byref(p),
+                                    ctypes.byref(l), vp(256), vp(256), vp(256), vp(256), work, None)
+
+    assert lm(kcs.Prior(1.0, 0.01, 0.1, (1e-3,) * 3).c(), good_l) == kcs.KCS_EINVAL  # beta_kp >= 1
+    assert lm(kcs.Prior(0.1, 0.0, 0.1, (1e-3,) * 3).c(), good_l) == kcs.KCS_EINVAL  # eps_F = 0
+    assert lm(kcs.Prior(0.1, 0.01, 0.1, (0.0, 1e-3, 1e-3)).c(), good_l) == kcs.KCS_EINVAL  # delta = 0
+    assert lm(good_p, kcs.LMOptions(5, 1e-3, 1e-8, 1e8, (0, 0, 0), inputs.LM_HI).c()) == kcs.KCS_EINVAL
+    assert lm(good_p, kcs.LMOptions(5, 1e-3, 1.0, 0.1, inputs.LM_LO, inputs.LM_HI).c()) == kcs.KCS_EINVAL
+    small = ctypes.c_size_t(1024)
+    rc = kcs.lib().kcs_lm_fit(ctypes.byref(gc), ctypes.byref(fc), ctypes.byref(k), ctypes.byref(good_p),
+                              ctypes.byref(good_l), vp(256), vp(256), vp(256), vp(256), small, None)
+    assert rc == kcs.KCS_EWORKSPACE
+    misaligned = kcs.lib().kcs_lm_fit(ctypes.byref(gc), ctypes.byref(fc), ctypes.byref(k), ctypes.byref(good_p),
+                                      ctypes.byref(good_l), vp(256), vp(256), vp(256), vp(260), work, None)
+    assert misaligned == kcs.KCS_EINVAL
