@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Benchmark of the kinetic compressive sensing hot path on one MI355X.
+
+A step is one ICM sweep over one synthetic study: OS-MAP-OSL-KP over all subsets (forward
+projection with the measured/expected ratio, gather back projection fused with the OSL update
+and the kinetics-derived prior) followed by the synchronous MAP-LM iterations.  The default
+workload is the clinical-scale study: 344x344x127 voxels (2.09 mm), 252 angles x 344 bins,
+24 frames over 40 min, 21 subsets, 5 LM iterations, 3e8 counts + 15 % background.
+
+Inputs are synthesised on the device (phantom maps from the seeded generator, activity from
+kcs_model_tac, expected counts from kcs_project, Poisson draws) and are resident in HBM before
+the timed region starts.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def synthesize(cfg, dev, seed_offset=0):
+    """Measured sinogram and study constants for `cfg`, built with the HIP library."""
+    import numpy as np
+    import torch
+
+    from paper_1803_10045_amd import inputs, kcs
+
+    g = kcs.Geometry.from_config(cfg)
+    t0, t1 = inputs.frame_times()
+    dt = t1 - t0
+    M = len(t0)
+    kin = kcs.Kinetics(**inputs.FENG, vb=inputs.VB)
+    maps, mask = inputs.phantom_maps(cfg)
+    delta = inputs.huber_delta(maps, mask)
+    N = g.n_vox
+    p = torch.from_numpy(maps.reshape(3, N).astype(np.float32)).to(dev)
+    m = torch.from_numpy(mask.reshape(N)).to(dev)
+    p[:, ~m] = torch.tensor(inputs.XI0, dtype=torch.float32, device=dev)[:, None]  # any valid triple
+    x = torch.empty((N, M), device=dev)
+    work = kcs.alloc_workspace(None, M, 0, dev)
+    kcs.kcs_model_tac(kcs.Frames(t0, t1, np.ones(M), np.zeros(M)), kin, p, x, None, work)
+    x[~m] = 0.0
+    x = x.view(g.nz, g.ny, g.nx, M)
+    del p
+    unit = kcs.Frames(t0, t1, np.ones(M), np.zeros(M))
+    y = torch.empty((g.nz, g.n_ang, g.n_bin, M), device=dev)
+    kcs.kcs_project(g, unit, x, 0, 1, y)
+    per_frame = y.view(-1, M).sum(dim=0, dtype=torch.float64).cpu().numpy()
+    total = float((per_frame * dt).sum())
+    c = cfg.counts / total
+    E = c * dt
+    r = cfg.bg_frac * cfg.counts * (dt / dt.sum()) / (cfg.n_ang * cfg.n_bin * cfg.nz)
+    y.mul_(torch.from_numpy(E.astype(np.float32)).to(dev)).add_(torch.from_numpy(r.astype(np.float32)).to(dev))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(cfg.seed + seed_offset)
+    sino = torch.poisson(y, generator=gen)
+    del y, x
+    f = kcs.Frames(t0, t1, E, r)
+    from scipy.optimize import minimize_scalar  # only for the peak of the input function
+    cp = lambda t: -((inputs.FENG["A1"] * t - inputs.FENG["A2"] - inputs.FENG["A3"]) * np.exp(inputs.FENG["l1"] * t)
+                     + inputs.FENG["A2"] * np.exp(inputs.FENG["l2"] * t) + inputs.FENG["A3"] * np.exp(inputs.FENG["l3"] * t))
+    peak = -minimize_scalar(cp, bounds=(0.0, 2.0), method="bounded", options=dict(xatol=1e-10)).fun
+    prior = kcs.Prior(inputs.BETA_KP, 1e-4 * peak, cfg.beta_h, (delta,) * 3, True)
+    lm = kcs.LMOptions(cfg.n_lm, inputs.LM_TAU, inputs.LM_LAM_MIN, inputs.LM_LAM_MAX, inputs.LM_LO, inputs.LM_HI)
+    return g, f, kin, prior, lm, sino
+
+
+def algorithmic_bytes(g, M, Q):
+    """Compulsory HBM bytes per launch of each kernel (FP32; model TAC and sensitivity on the fly).
+    K-proj (ratio): reads image I and the subset's measured sinogram, writes the ratio.
+    K-back (OSL): reads the ratio, the image and the 3 maps, writes the image.
+    K-lm: reads image, maps and lambda, writes maps and lambda."""
+    N = g.n_vox
+    I = N * M * 4
+    A_mean = g.n_ang / Q
+    S_q = g.nz * A_mean * g.n_bin * M * 4
+    return {"project": I + 2 * S_q, "osl": 2 * I + S_q + 12 * N, "lm": I + 32 * N}
+
+
+def cpu_baseline(cfg):
+    """The FP64 oracle on a bounded sample of the same workload, extrapolated to one sweep."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    from paper_1803_10045_amd import inputs
+
+    sample = inputs.scaled(cfg, nz=1)
+    st = oracle.make_study(sample)
+    x, params, lam = oracle.initial_state(st.geom, st.frames, st.sino.astype(np.float64))
+    params = np.broadcast_to(np.array(inputs.GRAY)[:, None, None, None], params.shape).copy()
+    oracle.system_matrix(st.geom)  # build outside the timed part (geometry setup, not per sweep)
+    with threadpool_limits(1):
+        t = time.perf_counter()
+        oracle.osl_update(st.geom, st.frames, st.kin, st.prior, st.sino.astype(np.float64), params, x, 0, cfg.Q, True)
+        t_osl = time.perf_counter() - t
+        ny, nx = 64, 64
+        y0, x0 = cfg.ny // 2 - ny // 2, cfg.nx // 2 - nx // 2
+        xs = np.ascontiguousarray(st.truth_x[:, y0:y0 + ny, x0:x0 + nx])
+        ps = np.ascontiguousarray(params[:, :, y0:y0 + ny, x0:x0 + nx])
+        ls = np.zeros((1, ny, nx))
+        t = time.perf_counter()
+        oracle.lm_iteration(st.frames, st.kin, st.prior, st.lm, xs, ps, ls)
+        t_lm = time.perf_counter() - t
+    n_vox = cfg.nx * cfg.ny * cfg.nz
+    sweep_s = cfg.nz * cfg.Q * t_osl + cfg.n_lm * n_vox * t_lm / (nx * ny)
+    return {"value": 1.0 / sweep_s, "unit": "sweeps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"1 OSL subset update on one {cfg.nx}x{cfg.ny} plane ({t_osl:.2f} s) and 1 MAP-LM "
+                       f"iteration on {nx * ny} voxels ({t_lm:.2f} s), FP64, 1 thread; extrapolated to "
+                       f"{cfg.nz} planes x {cfg.Q} subsets and {cfg.n_lm} iterations x {n_vox} voxels")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="cfg3", choices=["cfg1", "cfg2", "cfg3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the ICM sweep shards by plane with no "
+              "exchange, so a multi-GPU run is not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1803_10045_amd import inputs, kcs
+
+    dev = torch.device("cuda:0")
+    cfg = inputs.CONFIGS[args.config]()
+    t = time.perf_counter()
+    g, f, kin, prior, lm, sino = synthesize(cfg, dev)
+    torch.cuda.synchronize()
+    log(f"synthesised {cfg.name} in {time.perf_counter() - t:.1f} s; counts {float(sino.sum()):.3e}")
+    M, Q = f.M, cfg.Q
+    x = torch.empty((g.nz, g.ny, g.nx, M), device=dev)
+    params = torch.empty((3, g.nz, g.ny, g.nx), device=dev)
+    lam = torch.empty((g.nz, g.ny, g.nx), device=dev)
+    work = kcs.alloc_workspace(g, M, Q, dev)
+    kcs.kcs_init_state(g, f, sino, inputs.XI0, x, params, lam, work)
+    sweep = 0
+    for _ in range(args.warmup):
+        kcs.kcs_icm_sweep(g, f, kin, prior, lm, sino, Q, sweep, x, params, lam, work)
+        sweep += 1
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} sweeps done")
+
+    kcs.kcs_timing_enable(True)
+    kcs.kcs_timing_collect()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.steps):
+        kcs.kcs_icm_sweep(g, f, kin, prior, lm, sino, Q, sweep, x, params, lam, work)
+        sweep += 1
+    stop.record()
+    torch.cuda.synchronize()
+    elapsed_ms = start.elapsed_time(stop)
+    timing = kcs.kcs_timing_collect()
+    kcs.kcs_timing_enable(False)
+    log(f"timed {args.steps} sweeps: {elapsed_ms:.2f} ms")
+    if not torch.isfinite(x).all() or not torch.isfinite(params).all():
+        raise RuntimeError("non-finite values in the reconstruction")
+
+    nbytes = algorithmic_bytes(g, M, Q)
+    kernels = {}
+    for kind in ("project", "osl", "lm"):
+        ms, n = timing[kind]
+        if n == 0:
+            continue
+        avg = ms / n
+        gbps = nbytes[kind] / (avg * 1e-3) / 1e9
+        kernels[kind] = {"launches": n, "avg_ms": round(avg, 4), "ms_per_sweep": round(ms / args.steps, 3),
+                         "alg_bytes_per_launch": int(nbytes[kind]), "alg_GBps": round(gbps, 1),
+                         "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4)}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_sweep"])
+    roof = {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["alg_GBps"], "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s", "frac": kernels[dom]["hbm_frac"], "traffic": None}
+    value = args.steps / (elapsed_ms * 1e-3)
+    out = {
+        "metric": "ICM sweeps/s",
+        "value": round(value, 3),
+        "unit": "sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed_ms / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded phantom, closed-form FDG TACs, Poisson counts)",
+        "config": {"workload": f"{cfg.name}: {cfg.nx}x{cfg.ny}x{cfg.nz} voxels, {cfg.n_ang} angles x {cfg.n_bin} "
+                               f"bins, {M} frames, {Q} subsets, {cfg.n_lm} MAP-LM iterations per sweep",
+                   "counts": cfg.counts, "background": cfg.bg_frac},
+        "roofline": roof,
+        "kernels": kernels,
+        "proj_backproj_GBps": {"project": kernels.get("project", {}).get("alg_GBps"),
+                               "backproject_osl": kernels.get("osl", {}).get("alg_GBps")},
+    }
+    if not args.no_cpu_baseline:
+        t = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(cfg)
+        log(f"cpu baseline in {time.perf_counter() - t:.1f} s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

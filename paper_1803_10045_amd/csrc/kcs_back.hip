@@ -52,29 +52,19 @@ __device__ __forceinline__ void gather(const AngleRec* sA, const ProjArgs& p, co
                                        int z, float (&acc)[M], float& sens) {
     const float xc = ((float)i - 0.5f * (float)(p.nx - 1)) * p.h;
     const float yc = ((float)j - 0.5f * (float)(p.ny - 1)) * p.h;
-    const float bc = 0.5f * (float)(p.n_bin - 1);
 #pragma unroll
     for (int m = 0; m < M; ++m) acc[m] = 0.0f;
     sens = 0.0f;
     const float* yz = y + (size_t)z * p.A_q * p.n_bin * M;
     for (int al = 0; al < p.A_q; ++al) {
-        const AngleRec A = sA[al];
-        const float tc = fmaf(xc, A.c, yc * A.s);  // voxel centre on the detector axis
-        const float beta = fmaf(tc, p.inv_du, bc);  // ... in bin units
-        const float rb = A.w1 * p.inv_du;
-        const int b0 = max((int)ceilf(beta - rb), 0);
-        const int b1 = min((int)floorf(beta + rb), p.n_bin - 1);
-        for (int b = b0; b <= b1; ++b) {
-            const float t = fmaf((float)b - bc, p.du, -tc);
-            const float len = pixel_chord(A, t);
-            if (len > 0.0f) {
-                float v[M];
-                load_record<M>(yz + ((size_t)al * p.n_bin + b) * M, v);
+        const float* ya = yz + (size_t)al * p.n_bin * M;
+        pixel_footprint(sA[al], xc, yc, p.n_bin, p.du, p.inv_du, [&](int b, float len) {
+            float v[M];
+            load_record<M>(ya + (size_t)b * M, v);
 #pragma unroll
-                for (int m = 0; m < M; ++m) acc[m] = fmaf(len, v[m], acc[m]);
-                sens += len;
-            }
-        }
+            for (int m = 0; m < M; ++m) acc[m] = fmaf(len, v[m], acc[m]);
+            sens += len;
+        });
     }
 }
 

@@ -40,7 +40,7 @@ __device__ __forceinline__ void store_record(float* __restrict__ p, const float 
 
 // Constants of projection angle a: t_a = ang0 + a pi / n_ang, cos and sin computed in FP64 and
 // snapped exactly at multiples of pi/2, then rounded to FP32.
-__device__ __forceinline__ AngleRec make_angle(int a, int n_ang, double ang0, float h) {
+__host__ __device__ inline AngleRec make_angle(int a, int n_ang, double ang0, float h) {
     const double t = ang0 + (double)a * 3.141592653589793 / (double)n_ang;
     double s, c;
     sincos(t, &s, &c);
@@ -67,7 +67,7 @@ __device__ __forceinline__ AngleRec make_angle(int a, int n_ang, double ang0, fl
 
 // Chord of a ray through a pixel square: the exact intersection length as a function of the
 // signed distance t between the ray and the pixel centre, measured along the detector.
-__device__ __forceinline__ float pixel_chord(const AngleRec& A, float t) {
+__host__ __device__ __forceinline__ float pixel_chord(const AngleRec& A, float t) {
     if (A.axis == 0) {
         const float f = fminf(fmaxf((A.w1 - fabsf(t)) * A.inv_dw, 0.0f), 1.0f);
         return A.m * f;
@@ -77,6 +77,96 @@ __device__ __forceinline__ float pixel_chord(const AngleRec& A, float t) {
     const float w0 = A.w1;
     const bool in = cs > 0.0f ? (t >= -w0 && t < w0) : (t > -w0 && t <= w0);
     return in ? A.m : 0.0f;
+}
+
+// Incremental Siddon traversal of ray (A, u) through an nx x ny grid of h-pixels centred on the
+// origin: calls visit(i, j, len) for every pixel the ray crosses, in order, with the exact
+// intersection length.  Coordinates are in pixel units, X = (x + nx h / 2) / h, and the point
+// at parameter lam (pixel units of length along the ray) is (Xc - lam s, Yc + lam c).  The
+// crossing parameters are re-derived from the grid-line index at each step, so the rounding
+// error does not accumulate along the ray.  At most nx + ny + 2 steps.
+template <class Visit>
+__host__ __device__ __forceinline__ void siddon_traverse(const AngleRec& A, float u, int nx, int ny, float h,
+                                                         float inv_h, Visit&& visit) {
+    const float Xc = u * A.c * inv_h + 0.5f * (float)nx;
+    const float Yc = u * A.s * inv_h + 0.5f * (float)ny;
+    float lin = -3.0e38f, lout = 3.0e38f;
+    bool hit = true;
+    if (A.s != 0.0f) {
+        const float l0 = Xc * A.inv_s, l1 = (Xc - (float)nx) * A.inv_s;
+        lin = fmaxf(lin, fminf(l0, l1));
+        lout = fminf(lout, fmaxf(l0, l1));
+    } else {
+        hit = hit && Xc >= 0.0f && Xc < (float)nx;
+    }
+    if (A.c != 0.0f) {
+        const float l0 = -Yc * A.inv_c, l1 = ((float)ny - Yc) * A.inv_c;
+        lin = fmaxf(lin, fminf(l0, l1));
+        lout = fminf(lout, fmaxf(l0, l1));
+    } else {
+        hit = hit && Yc >= 0.0f && Yc < (float)ny;
+    }
+    if (!(hit && lout > lin)) return;
+    // first pixel: the one the ray enters, judged by its direction of travel
+    int i, j, si = 0, sj = 0;
+    float dlx = 0.0f, dly = 0.0f;
+    if (A.s != 0.0f) {
+        const float Xin = Xc - lin * A.s;
+        si = A.s < 0.0f ? 1 : -1;
+        i = si > 0 ? (int)floorf(Xin) : (int)ceilf(Xin) - 1;
+        i = min(max(i, 0), nx - 1);
+        dlx = fabsf(A.inv_s);
+    } else {
+        i = (int)floorf(Xc);
+    }
+    if (A.c != 0.0f) {
+        const float Yin = Yc + lin * A.c;
+        sj = A.c > 0.0f ? 1 : -1;
+        j = sj > 0 ? (int)floorf(Yin) : (int)ceilf(Yin) - 1;
+        j = min(max(j, 0), ny - 1);
+        dly = fabsf(A.inv_c);
+    } else {
+        j = (int)floorf(Yc);
+    }
+    const float bx0 = (float)(si > 0 ? i + 1 : i), by0 = (float)(sj > 0 ? j + 1 : j);
+    const float lx0 = si ? (Xc - bx0) * A.inv_s : 3.0e38f;
+    const float ly0 = sj ? (by0 - Yc) * A.inv_c : 3.0e38f;
+    float lx = lx0, ly = ly0, lcur = lin;
+    int kx = 0, ky = 0;
+    const int max_steps = nx + ny + 2;
+    for (int step = 0; step < max_steps; ++step) {
+        const float lnext = fminf(fminf(lx, ly), lout);
+        visit(i, j, (lnext - lcur) * h);
+        if (lnext >= lout) break;
+        if (lx <= ly) {
+            i += si;
+            ++kx;
+            lx = fmaf((float)kx, dlx, lx0);
+        } else {
+            j += sj;
+            ++ky;
+            ly = fmaf((float)ky, dly, ly0);
+        }
+        if (i < 0 || i >= nx || j < 0 || j >= ny) break;
+        lcur = lnext;
+    }
+}
+
+// Bins whose rays cross the pixel centred at (xc, yc): calls visit(b, len) with the chord.
+// The footprint of a pixel on the detector is |t| < w1 around the centre's projection.
+template <class Visit>
+__host__ __device__ __forceinline__ void pixel_footprint(const AngleRec& A, float xc, float yc, int n_bin, float du,
+                                                         float inv_du, Visit&& visit) {
+    const float bc = 0.5f * (float)(n_bin - 1);
+    const float tc = fmaf(xc, A.c, yc * A.s);  // pixel centre on the detector axis
+    const float beta = fmaf(tc, inv_du, bc);    // ... in bin units
+    const float rb = A.w1 * inv_du;
+    const int b0 = max((int)ceilf(beta - rb), 0);
+    const int b1 = min((int)floorf(beta + rb), n_bin - 1);
+    for (int b = b0; b <= b1; ++b) {
+        const float len = pixel_chord(A, fmaf((float)b - bc, du, -tc));
+        if (len > 0.0f) visit(b, len);
+    }
 }
 
 }  // namespace kcs

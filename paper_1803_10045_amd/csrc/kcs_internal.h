@@ -13,9 +13,12 @@ namespace kcs {
 constexpr int kMaxFrames = 32;
 constexpr int kMaxBoundaries = 2 * kMaxFrames;  // frame starts and ends
 constexpr int kRates = 3;                       // distinct exponents of the input function
-constexpr int kTaylor = 10;                     // terms of the near-singular series
+constexpr int kTaylor = 12;                     // terms of the near-singular series
 constexpr int kTaylorCoef = kTaylor + 3;        // c_1 .. c_{kTaylor+3}
-constexpr float kTaylorRadius = 0.5f;           // |(l_i + a) t| below which the series is used
+// The series replaces the divided differences where |(l_i + a) t| < kTaylorR0 + kTaylorR1 |l_i t|:
+// there the quotient form loses about (3 + |l_i t|) / |(l_i + a) t| digits per order.
+constexpr float kTaylorR0 = 0.5f;
+constexpr float kTaylorR1 = 0.25f;
 
 // Per-angle constants of the parallel-beam geometry (FP32 copies of FP64 host values).
 struct AngleRec {
@@ -52,8 +55,9 @@ struct BoundaryRec {
     float u[kRates];      // t^2 phi2(l_i t)
     float u1p;            // t^3 phi2'(l_1 t)
     float x[kRates];      // l_i t
+    float hsw[kRates];    // switch radius kTaylorR0 + kTaylorR1 |l_i t|
     float coef[kRates][kTaylorCoef];
-    float pad[1];
+    float pad[2];
 };
 
 struct KinTab {

@@ -16,7 +16,7 @@ namespace kcs {
 
 // phi2(y) = (e^y - 1 - y) / y^2 and phi2'(y) for y <= 0; inv_y = 1 / y.
 template <bool DERIV>
-__device__ __forceinline__ void phi2_pair(float y, float inv_y, float& p2, float& p2d) {
+__host__ __device__ __forceinline__ void phi2_pair(float y, float inv_y, float& p2, float& p2d) {
     if (y > -1.0f) {
         // power series: phi2 = sum y^n / (n+2)!, phi2' = sum (n+1) y^n / (n+3)!
         float s = 2.08767569878681e-09f;  // 1/12!
@@ -57,7 +57,7 @@ struct VoxelRates {
     float inv_b[kRates];  // 1 / (l_i + a)
 };
 
-__device__ __forceinline__ VoxelRates voxel_rates(const KinTab& K, float k2, float k3) {
+__host__ __device__ __forceinline__ VoxelRates voxel_rates(const KinTab& K, float k2, float k3) {
     VoxelRates v;
     v.a = k2 + k3;
     v.inv_a = 1.0f / v.a;
@@ -68,7 +68,7 @@ __device__ __forceinline__ VoxelRates voxel_rates(const KinTab& K, float k2, flo
 
 // J(t) and (if DERIV) dJ/da at one boundary.
 template <bool DERIV>
-__device__ __forceinline__ void boundary_J(const KinTab& K, const BoundaryRec& B, const VoxelRates& R, float& J,
+__host__ __device__ __forceinline__ void boundary_J(const KinTab& K, const BoundaryRec& B, const VoxelRates& R, float& J,
                                            float& dJ) {
     const float t = B.t;
     if (t == 0.0f) {
@@ -87,7 +87,7 @@ __device__ __forceinline__ void boundary_J(const KinTab& K, const BoundaryRec& B
 #pragma unroll
     for (int i = 0; i < kRates; ++i) {
         const float h = B.x[i] - y;  // (l_i + a) t
-        if (fabsf(h) >= kTaylorRadius) {
+        if (fabsf(h) >= B.hsw[i]) {
             Ji[i] = (B.u[i] - v) * R.inv_b[i];
             if (DERIV) dJi[i] = -(dv + Ji[i]) * R.inv_b[i];
             if (i == 0) {
@@ -129,7 +129,7 @@ __device__ __forceinline__ void boundary_J(const KinTab& K, const BoundaryRec& B
 
 // Calls sink(m, F_m, dF/dK1, dF/dk2, dF/dk3) for every frame m (derivatives 0 when !DERIV).
 template <int M, bool DERIV, class Sink>
-__device__ __forceinline__ void model_frames(const FrameTab& FT, const KinTab& K, float K1, float k2, float k3,
+__host__ __device__ __forceinline__ void model_frames(const FrameTab& FT, const KinTab& K, float K1, float k2, float k3,
                                              Sink&& sink) {
     const VoxelRates R = voxel_rates(K, k2, k3);
     const float g = FT.one_minus_vb;
@@ -154,6 +154,62 @@ __device__ __forceinline__ void model_frames(const FrameTab& FT, const KinTab& K
         Jprev = J1;
         dJprev = dJ1;
     }
+}
+
+// m_k(x) = int_0^1 s^k e^{x s} ds for k = 0..kmax (x <= 0), FP64.  Upward recursion
+// m_k = (e^x - k m_{k-1}) / x is stable for |x| > k; otherwise the downward recursion
+// m_{k-1} = (e^x - x m_k) / k from a high start value given by its power series.
+__host__ __device__ inline void moments_fp64(double x, int kmax, double* m) {
+    if (x == 0.0) {
+        for (int k = 0; k <= kmax; ++k) m[k] = 1.0 / (k + 1);
+        return;
+    }
+    const double e = exp(x);
+    if (-x > (double)(kmax + 1)) {
+        m[0] = expm1(x) / x;
+        for (int k = 1; k <= kmax; ++k) m[k] = (e - k * m[k - 1]) / x;
+        return;
+    }
+    const int K0 = kmax + 60;
+    double term = 1.0, acc = 0.0;
+    for (int j = 0; j < 400; ++j) {
+        acc += term / (double)(j + K0 + 1);
+        term *= x / (double)(j + 1);
+        if (fabs(term) < 1e-30 * fabs(acc)) break;
+    }
+    double mk = acc;
+    for (int k = K0; k > 0; --k) {
+        const double prev = (e - x * mk) / (double)k;
+        if (k - 1 <= kmax) m[k - 1] = prev;
+        mk = prev;
+    }
+}
+
+// Boundary record at time t (minutes) for the input-function exponents l[0..2], FP64 -> FP32.
+__host__ __device__ inline BoundaryRec make_boundary(double t, const double* l) {
+    constexpr int kMom = kTaylorCoef + 1;
+    BoundaryRec R;
+    R.t = (float)t;
+    R.t2 = (float)(t * t);
+    R.t3 = (float)(t * t * t);
+    R.t4 = (float)(t * t * t * t);
+    R.t5 = (float)(t * t * t * t * t);
+    double m[kMom + 1];
+    for (int i = 0; i < kRates; ++i) {
+        const double x = l[i] * t;
+        moments_fp64(x, kMom, m);
+        R.x[i] = (float)x;
+        R.hsw[i] = (float)(kTaylorR0 + kTaylorR1 * fabs(x));
+        R.u[i] = (float)(t * t * (m[0] - m[1]));  // t^2 phi2(x), phi2(x) = int_0^1 (1-s) e^{xs} ds
+        if (i == 0) R.u1p = (float)(t * t * t * (m[1] - m[2]));  // t^3 phi2'(x)
+        double fact = 1.0;
+        for (int k = 1; k <= kTaylorCoef; ++k) {
+            fact *= k;
+            R.coef[i][k - 1] = (float)((m[k] - m[k + 1]) / fact);  // phi2^(k)(x) / k!
+        }
+    }
+    R.pad[0] = R.pad[1] = 0.0f;
+    return R;
 }
 
 }  // namespace kcs

@@ -31,82 +31,14 @@ __global__ __launch_bounds__(256) void kproj_kernel(const float* __restrict__ x,
 #pragma unroll
     for (int m = 0; m < M; ++m) acc[m] = 0.0f;
 
-    // Ray x c + y s = u in pixel units: X = (x - X0)/h, Y = (y - Y0)/h; point at parameter lam
-    // (pixel units of length): X = Xc - lam s, Y = Yc + lam c.
     const float u = ((float)b - 0.5f * (float)(p.n_bin - 1)) * p.du;
-    const float Xc = u * A.c * p.inv_h + 0.5f * (float)p.nx;
-    const float Yc = u * A.s * p.inv_h + 0.5f * (float)p.ny;
-    float lin = -3.0e38f, lout = 3.0e38f;
-    bool hit = true;
-    if (A.s != 0.0f) {
-        const float l0 = Xc * A.inv_s, l1 = (Xc - (float)p.nx) * A.inv_s;
-        lin = fmaxf(lin, fminf(l0, l1));
-        lout = fminf(lout, fmaxf(l0, l1));
-    } else {
-        hit = hit && Xc >= 0.0f && Xc < (float)p.nx;
-    }
-    if (A.c != 0.0f) {
-        const float l0 = -Yc * A.inv_c, l1 = ((float)p.ny - Yc) * A.inv_c;
-        lin = fmaxf(lin, fminf(l0, l1));
-        lout = fminf(lout, fmaxf(l0, l1));
-    } else {
-        hit = hit && Yc >= 0.0f && Yc < (float)p.ny;
-    }
-    hit = hit && lout > lin;
-
-    if (hit) {
-        // first pixel: the one the ray enters, judged by its direction of travel
-        int i, j, si = 0, sj = 0;
-        float lx = 3.0e38f, ly = 3.0e38f, dlx = 0.0f, dly = 0.0f;
-        if (A.s != 0.0f) {
-            const float Xin = Xc - lin * A.s;
-            si = A.s < 0.0f ? 1 : -1;
-            i = si > 0 ? (int)floorf(Xin) : (int)ceilf(Xin) - 1;
-            i = min(max(i, 0), p.nx - 1);
-            dlx = fabsf(A.inv_s);
-        } else {
-            i = (int)floorf(Xc);
-        }
-        if (A.c != 0.0f) {
-            const float Yin = Yc + lin * A.c;
-            sj = A.c > 0.0f ? 1 : -1;
-            j = sj > 0 ? (int)floorf(Yin) : (int)ceilf(Yin) - 1;
-            j = min(max(j, 0), p.ny - 1);
-            dly = fabsf(A.inv_c);
-        } else {
-            j = (int)floorf(Yc);
-        }
-        // parameters of the next grid-line crossings, re-derived from the line index each step
-        const float bx0 = (float)(si > 0 ? i + 1 : i), by0 = (float)(sj > 0 ? j + 1 : j);
-        const float lx0 = si ? (Xc - bx0) * A.inv_s : 3.0e38f;
-        const float ly0 = sj ? (by0 - Yc) * A.inv_c : 3.0e38f;
-        int kx = 0, ky = 0;
-        lx = lx0;
-        ly = ly0;
-        float lcur = lin;
-        const float* plane = x + (size_t)z * p.nx * p.ny * M;
-        const int max_steps = p.nx + p.ny + 2;
-        for (int step = 0; step < max_steps; ++step) {
-            const float lnext = fminf(fminf(lx, ly), lout);
-            const float len = (lnext - lcur) * p.h;
-            float v[M];
-            load_record<M>(plane + ((size_t)j * p.nx + i) * M, v);
+    const float* plane = x + (size_t)z * p.nx * p.ny * M;
+    siddon_traverse(A, u, p.nx, p.ny, p.h, p.inv_h, [&](int i, int j, float len) {
+        float v[M];
+        load_record<M>(plane + ((size_t)j * p.nx + i) * M, v);
 #pragma unroll
-            for (int m = 0; m < M; ++m) acc[m] = fmaf(len, v[m], acc[m]);
-            if (lnext >= lout) break;
-            if (lx <= ly) {
-                i += si;
-                ++kx;
-                lx = fmaf((float)kx, dlx, lx0);
-            } else {
-                j += sj;
-                ++ky;
-                ly = fmaf((float)ky, dly, ly0);
-            }
-            if (i < 0 || i >= p.nx || j < 0 || j >= p.ny) break;
-            lcur = lnext;
-        }
-    }
+        for (int m = 0; m < M; ++m) acc[m] = fmaf(len, v[m], acc[m]);
+    });
 
     const size_t o = (((size_t)z * p.A_q + al) * p.n_bin + b) * M;
     float y[M];

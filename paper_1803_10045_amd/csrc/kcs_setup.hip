@@ -9,37 +9,7 @@
 
 namespace kcs {
 
-// m_k(x) = int_0^1 s^k e^{x s} ds for k = 0..kmax (x <= 0), FP64.  Upward recursion
-// m_k = (e^x - k m_{k-1}) / x is stable for |x| > k; otherwise the downward recursion
-// m_{k-1} = (e^x - x m_k) / k from a high start value given by its power series.
-__device__ void moments_fp64(double x, int kmax, double* m) {
-    if (x == 0.0) {
-        for (int k = 0; k <= kmax; ++k) m[k] = 1.0 / (k + 1);
-        return;
-    }
-    const double e = exp(x);
-    if (-x > (double)(kmax + 1)) {
-        m[0] = expm1(x) / x;
-        for (int k = 1; k <= kmax; ++k) m[k] = (e - k * m[k - 1]) / x;
-        return;
-    }
-    const int K0 = kmax + 60;
-    double term = 1.0, acc = 0.0;
-    for (int j = 0; j < 400; ++j) {
-        acc += term / (double)(j + K0 + 1);
-        term *= x / (double)(j + 1);
-        if (fabs(term) < 1e-30 * fabs(acc)) break;
-    }
-    double mk = acc;
-    for (int k = K0; k > 0; --k) {
-        const double prev = (e - x * mk) / (double)k;
-        if (k - 1 <= kmax) m[k - 1] = prev;
-        mk = prev;
-    }
-}
-
 __global__ void ktab_setup_kernel(SetupArgs s, KinTab* __restrict__ K) {
-    constexpr int kMom = kTaylorCoef + 1;
     const int b = threadIdx.x;
     if (b == 0) {
         for (int i = 0; i < kRates; ++i) K->l[i] = (float)s.l[i];
@@ -54,28 +24,7 @@ __global__ void ktab_setup_kernel(SetupArgs s, KinTab* __restrict__ K) {
         }
     }
     if (b >= s.n_bound) return;
-    const double t = s.t[b];
-    BoundaryRec R;
-    R.t = (float)t;
-    R.t2 = (float)(t * t);
-    R.t3 = (float)(t * t * t);
-    R.t4 = (float)(t * t * t * t);
-    R.t5 = (float)(t * t * t * t * t);
-    double m[kMom + 1];
-    for (int i = 0; i < kRates; ++i) {
-        const double x = s.l[i] * t;
-        moments_fp64(x, kMom, m);
-        R.x[i] = (float)x;
-        R.u[i] = (float)(t * t * (m[0] - m[1]));  // t^2 phi2(x), phi2(x) = int_0^1 (1-s) e^{xs} ds
-        if (i == 0) R.u1p = (float)(t * t * t * (m[1] - m[2]));  // t^3 phi2'(x)
-        double fact = 1.0;
-        for (int k = 1; k <= kTaylorCoef; ++k) {
-            fact *= k;
-            R.coef[i][k - 1] = (float)((m[k] - m[k + 1]) / fact);  // phi2^(k)(x) / k!
-        }
-    }
-    R.pad[0] = 0.0f;
-    K->b[b] = R;
+    K->b[b] = make_boundary(s.t[b], s.l);
 }
 
 hipError_t launch_setup(const SetupArgs& s, KinTab* K, hipStream_t st) {
