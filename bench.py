@@ -72,7 +72,8 @@ def synthesize(cfg, dev, seed_offset=0):
                      + inputs.FENG["A2"] * np.exp(inputs.FENG["l2"] * t) + inputs.FENG["A3"] * np.exp(inputs.FENG["l3"] * t))
     peak = -minimize_scalar(cp, bounds=(0.0, 2.0), method="bounded", options=dict(xatol=1e-10)).fun
     prior = kcs.Prior(inputs.BETA_KP, 1e-4 * peak, cfg.beta_h, (delta,) * 3, True)
-    lm = kcs.LMOptions(cfg.n_lm, inputs.LM_TAU, inputs.LM_LAM_MIN, inputs.LM_LAM_MAX, inputs.LM_LO, inputs.LM_HI)
+    lm = kcs.LMOptions(cfg.n_lm, inputs.LM_TAU, inputs.LM_LAM_MIN, inputs.LM_LAM_MAX, inputs.LM_LO, inputs.LM_HI,
+                       inputs.LM_ETA)
     return g, f, kin, prior, lm, sino
 
 

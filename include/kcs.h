@@ -87,11 +87,13 @@ typedef struct kcs_prior {
 } kcs_prior;
 
 /* Levenberg-Marquardt schedule: n_iter synchronous iterations; lambda <= 0 on entry is set to
- * tau * max diag(J^T J); accepted step: lambda = max(lambda/10, lam_min), rejected:
- * lambda = min(10 lambda, lam_max); parameters clipped to [lo, hi] (lo[1] + lo[2] > 0). */
+ * tau * max diag(J^T J); parameters clipped to [lo, hi] (lo[1] + lo[2] > 0); a step is accepted
+ * iff the voxel objective decreases by more than eta times its value,
+ * Phi(xi') - Phi(xi) < -eta Phi(xi) (0 <= eta < 1; eta = 0 is the plain strict decrease), then
+ * lambda = max(lambda/10, lam_min), otherwise lambda = min(10 lambda, lam_max). */
 typedef struct kcs_lm_opts {
     int32_t n_iter;
-    double tau, lam_min, lam_max, lo[3], hi[3];
+    double tau, lam_min, lam_max, lo[3], hi[3], eta;
 } kcs_lm_opts;
 
 /* Bytes of device workspace the calls below need for this geometry, frame count and subset count. */

@@ -15,9 +15,10 @@ Readings of points the paper leaves open (each is also an argument here):
     3x3 in-plane neighbourhood has weight 1 for edge neighbours and 1/sqrt(2) for diagonals,
     neighbours outside the image are dropped; all voxels update synchronously from the maps of
     the previous iteration; a step is kept only if the voxel's local objective
-    1/2 ||x - F||^2 + beta_h sum_k w_k sum_p H(xi_p - xi_kp) strictly decreases, then
-    lambda /= 10 (floor lam_min), otherwise lambda *= 10 (cap lam_max); lambda <= 0 on entry
-    is initialised to tau * max diag(J^T J); steps are clipped to the box [lo, hi].
+    Phi = 1/2 ||x - F||^2 + beta_h sum_k w_k sum_p H(xi_p - xi_kp) decreases by more than
+    eta Phi (eta = 0: strict decrease), then lambda /= 10 (floor lam_min), otherwise
+    lambda *= 10 (cap lam_max); lambda <= 0 on entry is initialised to tau * max diag(J^T J);
+    steps are clipped to the box [lo, hi].
 """
 from __future__ import annotations
 
@@ -47,6 +48,7 @@ class LMOptions:
     lam_max: float = 1e8
     lo: Tuple[float, float, float] = (0.0, 1e-4, 0.0)
     hi: Tuple[float, float, float] = (2.0, 2.0, 1.0)
+    eta: float = 0.0
 
 
 @dataclass
@@ -154,7 +156,7 @@ def lm_iteration(fr: Frames, kin: Kinetics, prior: Prior, opt: LMOptions, x: np.
     _, pe1 = neighbour_terms(trial_maps, params, prior.delta)
     phi0 = 0.5 * np.sum(r * r, axis=1) + prior.beta_h * pe.reshape(N)
     phi1 = 0.5 * np.sum((xv - F1) ** 2, axis=1) + prior.beta_h * pe1.reshape(N)
-    accept = phi1 < phi0
+    accept = phi1 - phi0 < -opt.eta * phi0
     new = np.where(accept[:, None], trial, xi)
     lam = np.where(accept, np.maximum(lam / 10.0, opt.lam_min), np.minimum(lam * 10.0, opt.lam_max))
     return new.T.reshape(params.shape).copy(), lam.reshape(shp)

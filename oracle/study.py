@@ -62,6 +62,6 @@ def make_study(cfg, with_truth: bool = True) -> Study:
     prior = Prior(beta_kp=inputs.BETA_KP, eps_F=1e-4 * peak_input(kin), beta_h=cfg.beta_h,
                   delta=(delta, delta, delta), kp_on=True)
     lm = LMOptions(n_iter=cfg.n_lm, tau=inputs.LM_TAU, lam_min=inputs.LM_LAM_MIN, lam_max=inputs.LM_LAM_MAX,
-                   lo=inputs.LM_LO, hi=inputs.LM_HI)
+                   lo=inputs.LM_LO, hi=inputs.LM_HI, eta=inputs.LM_ETA)
     fr = Frames(t0=t0, t1=t1, E=E, r=r)
     return Study(cfg, g, fr, kin, prior, lm, sino, maps, x_true if with_truth else None, mask)

@@ -89,6 +89,7 @@ int check_lm(const kcs_lm_opts* o) {
     for (int i = 0; i < 3; ++i)
         if (!is_finite(o->lo[i]) || !is_finite(o->hi[i]) || !(o->lo[i] <= o->hi[i])) return fail(KCS_EINVAL, "need lo <= hi");
     if (!(o->lo[1] + o->lo[2] > 0)) return fail(KCS_EINVAL, "lo[1] + lo[2] must be > 0 (k2 + k3 > 0)");
+    if (!(o->eta >= 0 && o->eta < 1)) return fail(KCS_EINVAL, "eta must be in [0, 1)");
     return KCS_OK;
 }
 
@@ -370,6 +371,7 @@ int do_lm(const kcs_geometry& g, const Schedule& S, const kcs_prior& p, const kc
         a.hi[i] = (float)o.hi[i];
     }
     a.tau = (float)o.tau;
+    a.eta = (float)o.eta;
     a.lam_min = (float)o.lam_min;
     a.lam_max = (float)o.lam_max;
     float* other = at<float>(d_work, L.xi);

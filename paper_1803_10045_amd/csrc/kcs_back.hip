@@ -48,7 +48,7 @@ __device__ __forceinline__ void subset_angles_to_lds(AngleRec* sA, const ProjArg
 
 // acc_m = sum_{d in S_q} p_vd y_dm and sens = sum_{d in S_q} p_vd for voxel (i, j, z).
 template <int M>
-__device__ __forceinline__ void gather(const AngleRec* sA, const ProjArgs& p, const float* __restrict__ y, int i, int j,
+__host__ __device__ __forceinline__ void gather(const AngleRec* sA, const ProjArgs& p, const float* __restrict__ y, int i, int j,
                                        int z, float (&acc)[M], float& sens) {
     const float xc = ((float)i - 0.5f * (float)(p.nx - 1)) * p.h;
     const float yc = ((float)j - 0.5f * (float)(p.ny - 1)) * p.h;
@@ -69,15 +69,12 @@ __device__ __forceinline__ void gather(const AngleRec* sA, const ProjArgs& p, co
 }
 
 template <int M>
-__global__ __launch_bounds__(256) void kback_kernel(const float* __restrict__ y, float* __restrict__ bout,
-                                                    float* __restrict__ sens_out, ProjArgs p) {
-    extern __shared__ AngleRec sA[];
-    subset_angles_to_lds(sA, p);
-    const TileIdx t = tile_voxel(p.nx, p.ny, p.nz);
-    if (!t.valid) return;
+__host__ __device__ __forceinline__ void backproject_voxel(const AngleRec* sA, const ProjArgs& p,
+                                                           const float* __restrict__ y, float* __restrict__ bout,
+                                                           float* __restrict__ sens_out, int i, int j, int z) {
     float acc[M], sens;
-    gather<M>(sA, p, y, t.i, t.j, t.z, acc, sens);
-    const size_t v = ((size_t)t.z * p.ny + t.j) * p.nx + t.i;
+    gather<M>(sA, p, y, i, j, z, acc, sens);
+    const size_t v = ((size_t)z * p.ny + j) * p.nx + i;
 #pragma unroll
     for (int m = 0; m < M; ++m) acc[m] *= p.fr.E[m];
     store_record<M>(bout + v * M, acc);
@@ -85,24 +82,21 @@ __global__ __launch_bounds__(256) void kback_kernel(const float* __restrict__ y,
 }
 
 template <int M>
-__global__ __launch_bounds__(256) void kosl_kernel(const float* __restrict__ ratio, const float* __restrict__ params,
-                                                   const KinTab* __restrict__ K, float* __restrict__ x, OslArgs a) {
-    extern __shared__ AngleRec sA[];
+__host__ __device__ __forceinline__ void osl_voxel(const AngleRec* sA, const OslArgs& a, const float* __restrict__ ratio,
+                                                   const float* __restrict__ params, const KinTab& K,
+                                                   float* __restrict__ x, int i, int j, int z) {
     const ProjArgs& p = a.g;
-    subset_angles_to_lds(sA, p);
-    const TileIdx t = tile_voxel(p.nx, p.ny, p.nz);
-    if (!t.valid) return;
     float acc[M], sens;
-    gather<M>(sA, p, ratio, t.i, t.j, t.z, acc, sens);
+    gather<M>(sA, p, ratio, i, j, z, acc, sens);
     if (!(sens > 0.0f)) return;  // no ray of this subset sees the voxel: keep x
-    const size_t v = ((size_t)t.z * p.ny + t.j) * p.nx + t.i;
+    const size_t v = ((size_t)z * p.ny + j) * p.nx + i;
     float xv[M];
     load_record<M>(x + v * M, xv);
     const float inv_sens = 1.0f / sens;
     if (a.kp) {
         const size_t N = (size_t)p.nx * p.ny * p.nz;
         const float K1 = params[v], k2 = params[N + v], k3 = params[2 * N + v];
-        model_frames<M, false>(p.fr, *K, K1, k2, k3, [&](int m, float F, float, float, float) {
+        model_frames<M, false>(p.fr, K, K1, k2, k3, [&](int m, float F, float, float, float) {
             const float d = fmaf(a.beta_kp, (xv[m] - F) / fmaxf(F, a.eps_F), 1.0f);
             xv[m] = xv[m] * acc[m] * inv_sens / d;
         });
@@ -111,6 +105,26 @@ __global__ __launch_bounds__(256) void kosl_kernel(const float* __restrict__ rat
         for (int m = 0; m < M; ++m) xv[m] = xv[m] * acc[m] * inv_sens;
     }
     store_record<M>(x + v * M, xv);
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void kback_kernel(const float* __restrict__ y, float* __restrict__ bout,
+                                                    float* __restrict__ sens_out, ProjArgs p) {
+    extern __shared__ AngleRec sA[];
+    subset_angles_to_lds(sA, p);
+    const TileIdx t = tile_voxel(p.nx, p.ny, p.nz);
+    if (!t.valid) return;
+    backproject_voxel<M>(sA, p, y, bout, sens_out, t.i, t.j, t.z);
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void kosl_kernel(const float* __restrict__ ratio, const float* __restrict__ params,
+                                                   const KinTab* __restrict__ K, float* __restrict__ x, OslArgs a) {
+    extern __shared__ AngleRec sA[];
+    subset_angles_to_lds(sA, a.g);
+    const TileIdx t = tile_voxel(a.g.nx, a.g.ny, a.g.nz);
+    if (!t.valid) return;
+    osl_voxel<M>(sA, a, ratio, params, *K, x, t.i, t.j, t.z);
 }
 
 template <int M>

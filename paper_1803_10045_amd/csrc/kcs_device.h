@@ -19,7 +19,7 @@ __device__ __forceinline__ uint32_t xcd_work_index(uint32_t bid, uint32_t n_grou
 __host__ __device__ inline uint32_t xcd_round_up(uint32_t n) { return (n + kXcds - 1) / kXcds * kXcds; }
 
 template <int M>
-__device__ __forceinline__ void load_record(const float* __restrict__ p, float (&v)[M]) {
+__host__ __device__ __forceinline__ void load_record(const float* __restrict__ p, float (&v)[M]) {
     static_assert(M % 4 == 0, "frames must be a multiple of 4");
 #pragma unroll
     for (int k = 0; k < M / 4; ++k) {
@@ -32,7 +32,7 @@ __device__ __forceinline__ void load_record(const float* __restrict__ p, float (
 }
 
 template <int M>
-__device__ __forceinline__ void store_record(float* __restrict__ p, const float (&v)[M]) {
+__host__ __device__ __forceinline__ void store_record(float* __restrict__ p, const float (&v)[M]) {
 #pragma unroll
     for (int k = 0; k < M / 4; ++k)
         reinterpret_cast<float4*>(p)[k] = make_float4(v[4 * k + 0], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);

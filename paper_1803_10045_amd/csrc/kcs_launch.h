@@ -29,6 +29,7 @@ struct LmArgs {
     float beta_h;
     float delta[3];
     float tau, lam_min, lam_max;
+    float eta;  // sufficient relative decrease of the objective for accepting a step
     float lo[3], hi[3];
 };
 

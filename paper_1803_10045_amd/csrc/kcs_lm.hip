@@ -16,22 +16,15 @@ namespace kcs {
 
 constexpr int kLmTileX = 64, kLmTileY = 4;
 
-__device__ __forceinline__ float huber(float t, float d) {
+__host__ __device__ __forceinline__ float huber(float t, float d) {
     const float at = fabsf(t);
     return at <= d ? 0.5f * t * t : d * at - 0.5f * d * d;
 }
 
 template <int M>
-__global__ __launch_bounds__(256) void klm_kernel(const KinTab* __restrict__ K, const float* __restrict__ x,
+__host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, const float* __restrict__ x,
                                                   const float* __restrict__ xi_in, float* __restrict__ xi_out,
-                                                  float* __restrict__ lam_io, LmArgs a) {
-    const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
-    const uint32_t tx = (a.nx + kLmTileX - 1) / kLmTileX, ty = (a.ny + kLmTileY - 1) / kLmTileY;
-    const int z = w / (tx * ty);
-    const uint32_t rr = w % (tx * ty);
-    const int j = (rr / tx) * kLmTileY + threadIdx.x / kLmTileX;
-    const int i = (rr % tx) * kLmTileX + threadIdx.x % kLmTileX;
-    if (z >= a.nz || i >= a.nx || j >= a.ny) return;
+                                                  float* __restrict__ lam_io, const LmArgs& a, int i, int j, int z) {
     const size_t plane = (size_t)a.nx * a.ny;
     const size_t N = plane * a.nz;
     const size_t v = (size_t)z * plane + (size_t)j * a.nx + i;
@@ -70,7 +63,7 @@ __global__ __launch_bounds__(256) void klm_kernel(const KinTab* __restrict__ K, 
 
     // model, Jacobian and normal equations at the current parameters
     float F0[M];
-    float A00 = 0, A01 = 0, A02 = 0, A11 = 0, A12 = 0, A22 = 0, g0 = 0, g1 = 0, g2 = 0;
+    float A00 = 0, A01 = 0, A02 = 0, A11 = 0, A12 = 0, A22 = 0, g0 = 0, g1 = 0, g2 = 0, rr = 0;
     model_frames<M, true>(a.fr, *K, p0, p1, p2, [&](int m, float F, float j0, float j1, float j2) {
         F0[m] = F;
         const float r = xv[m] - F;
@@ -83,6 +76,7 @@ __global__ __launch_bounds__(256) void klm_kernel(const KinTab* __restrict__ K, 
         g0 = fmaf(j0, r, g0);
         g1 = fmaf(j1, r, g1);
         g2 = fmaf(j2, r, g2);
+        rr = fmaf(r, r, rr);
     });
     g0 -= a.beta_h * psi[0];
     g1 -= a.beta_h * psi[1];
@@ -93,7 +87,7 @@ __global__ __launch_bounds__(256) void klm_kernel(const KinTab* __restrict__ K, 
 
     // (A + lam I) step = g, symmetrically scaled by the inverse square roots of the diagonal,
     // then a Cholesky factorisation in registers
-    const float s0 = rsqrtf(A00 + lam), s1 = rsqrtf(A11 + lam), s2 = rsqrtf(A22 + lam);
+    const float s0 = 1.0f / sqrtf(A00 + lam), s1 = 1.0f / sqrtf(A11 + lam), s2 = 1.0f / sqrtf(A22 + lam);
     const float B00 = (A00 + lam) * s0 * s0, B11 = (A11 + lam) * s1 * s1, B22 = (A22 + lam) * s2 * s2;
     const float B01 = A01 * s0 * s1, B02 = A02 * s0 * s2, B12 = A12 * s1 * s2;
     const float L00 = sqrtf(B00);
@@ -124,11 +118,26 @@ __global__ __launch_bounds__(256) void klm_kernel(const KinTab* __restrict__ K, 
     });
     dphi = fmaf(a.beta_h, e1 - e0, dphi);
 
-    const bool accept = dphi < 0.0f;
+    const float phi0 = fmaf(a.beta_h, e0, 0.5f * rr);
+    const bool accept = dphi < -a.eta * phi0;
     xi_out[v] = accept ? q0 : p0;
     xi_out[N + v] = accept ? q1 : p1;
     xi_out[2 * N + v] = accept ? q2 : p2;
     lam_io[v] = accept ? fmaxf(lam * 0.1f, a.lam_min) : fminf(lam * 10.0f, a.lam_max);
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void klm_kernel(const KinTab* __restrict__ K, const float* __restrict__ x,
+                                                  const float* __restrict__ xi_in, float* __restrict__ xi_out,
+                                                  float* __restrict__ lam_io, LmArgs a) {
+    const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
+    const uint32_t tx = (a.nx + kLmTileX - 1) / kLmTileX, ty = (a.ny + kLmTileY - 1) / kLmTileY;
+    const int z = w / (tx * ty);
+    const uint32_t rr = w % (tx * ty);
+    const int j = (rr / tx) * kLmTileY + threadIdx.x / kLmTileX;
+    const int i = (rr % tx) * kLmTileX + threadIdx.x % kLmTileX;
+    if (z >= a.nz || i >= a.nx || j >= a.ny) return;
+    lm_voxel<M>(K, x, xi_in, xi_out, lam_io, a, i, j, z);
 }
 
 template <int M>

@@ -12,6 +12,41 @@
 
 namespace kcs {
 
+// Ray (z, al, b) of subset p.q: ybar = E_m sum + r_m, or the ratio s / ybar.
+template <int M, bool RATIO>
+__host__ __device__ __forceinline__ void project_ray(const ProjArgs& p, const float* __restrict__ x,
+                                                     const float* __restrict__ sino, float* __restrict__ out, int z,
+                                                     int al, int b) {
+    const int a = p.q + al * p.Q;  // global angle index
+    const AngleRec A = make_angle(a, p.n_ang, p.ang0, p.h);
+    float acc[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) acc[m] = 0.0f;
+    const float u = ((float)b - 0.5f * (float)(p.n_bin - 1)) * p.du;
+    const float* plane = x + (size_t)z * p.nx * p.ny * M;
+    siddon_traverse(A, u, p.nx, p.ny, p.h, p.inv_h, [&](int i, int j, float len) {
+        float v[M];
+        load_record<M>(plane + ((size_t)j * p.nx + i) * M, v);
+#pragma unroll
+        for (int m = 0; m < M; ++m) acc[m] = fmaf(len, v[m], acc[m]);
+    });
+    const size_t o = (((size_t)z * p.A_q + al) * p.n_bin + b) * M;
+    float y[M];
+    if (RATIO) {
+        float s[M];
+        load_record<M>(sino + (((size_t)z * p.n_ang + a) * p.n_bin + b) * M, s);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const float yb = fmaf(p.fr.E[m], acc[m], p.fr.r[m]);
+            y[m] = yb > 0.0f ? s[m] / yb : 0.0f;
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < M; ++m) y[m] = fmaf(p.fr.E[m], acc[m], p.fr.r[m]);
+    }
+    store_record<M>(out + o, y);
+}
+
 template <int M, bool RATIO>
 __global__ __launch_bounds__(256) void kproj_kernel(const float* __restrict__ x, const float* __restrict__ sino,
                                                     float* __restrict__ out, ProjArgs p) {
@@ -22,39 +57,7 @@ __global__ __launch_bounds__(256) void kproj_kernel(const float* __restrict__ x,
     const uint32_t ray = (w % blocks_per_plane) * 256u + threadIdx.x;
     if (ray >= (uint32_t)p.rays_per_plane) return;
     const int al = ray / p.n_bin;  // angle within the subset
-    const int b = ray - al * p.n_bin;
-    const int a = p.q + al * p.Q;  // global angle index
-    const AngleRec A = make_angle(a, p.n_ang, p.ang0, p.h);
-    const FrameTab& FT = p.fr;
-
-    float acc[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) acc[m] = 0.0f;
-
-    const float u = ((float)b - 0.5f * (float)(p.n_bin - 1)) * p.du;
-    const float* plane = x + (size_t)z * p.nx * p.ny * M;
-    siddon_traverse(A, u, p.nx, p.ny, p.h, p.inv_h, [&](int i, int j, float len) {
-        float v[M];
-        load_record<M>(plane + ((size_t)j * p.nx + i) * M, v);
-#pragma unroll
-        for (int m = 0; m < M; ++m) acc[m] = fmaf(len, v[m], acc[m]);
-    });
-
-    const size_t o = (((size_t)z * p.A_q + al) * p.n_bin + b) * M;
-    float y[M];
-    if (RATIO) {
-        float s[M];
-        load_record<M>(sino + (((size_t)z * p.n_ang + a) * p.n_bin + b) * M, s);
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-            const float yb = fmaf(FT.E[m], acc[m], FT.r[m]);
-            y[m] = yb > 0.0f ? s[m] / yb : 0.0f;
-        }
-    } else {
-#pragma unroll
-        for (int m = 0; m < M; ++m) y[m] = fmaf(FT.E[m], acc[m], FT.r[m]);
-    }
-    store_record<M>(out + o, y);
+    project_ray<M, RATIO>(p, x, sino, out, z, al, ray - al * p.n_bin);
 }
 
 template <int M>

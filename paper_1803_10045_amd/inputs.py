@@ -39,6 +39,9 @@ LM_TAU = 1e-3
 LM_LAM_MIN, LM_LAM_MAX = 1e-8, 1e8
 LM_LO = (0.0, 1e-4, 0.0)
 LM_HI = (2.0, 2.0, 1.0)
+# A step is kept only if it lowers the voxel objective by more than this fraction of its value
+# (a sufficient-decrease test; improvements below it are at the resolution of FP32 arithmetic).
+LM_ETA = 1e-3
 BETA_KP = 0.1
 
 

@@ -56,7 +56,8 @@ class c_prior(ctypes.Structure):
 
 class c_lm_opts(ctypes.Structure):
     _fields_ = [("n_iter", ctypes.c_int32), ("tau", ctypes.c_double), ("lam_min", ctypes.c_double),
-                ("lam_max", ctypes.c_double), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+                ("lam_max", ctypes.c_double), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("eta", ctypes.c_double)]
 
 
 @lru_cache(maxsize=1)
@@ -178,10 +179,11 @@ class LMOptions:
     lam_max: float
     lo: Sequence[float]
     hi: Sequence[float]
+    eta: float = 0.0
 
     def c(self) -> c_lm_opts:
         return c_lm_opts(self.n_iter, self.tau, self.lam_min, self.lam_max, (ctypes.c_double * 3)(*self.lo),
-                         (ctypes.c_double * 3)(*self.hi))
+                         (ctypes.c_double * 3)(*self.hi), self.eta)
 
 
 # ----------------------------------------------------------------------------------------------

@@ -183,11 +183,35 @@ def test_lm_fit_parity():
         e = rel_l2(gp[i][mask], op[i][mask])
         print(f"lm param {i}: relL2 over object {e:.2e}")
         assert e < 1e-4
-    assert np.mean(ld.cpu().numpy() == ol.astype(np.float32)) > 0.99
+    # same accept/reject history <=> lambda equal up to rounding (it moves by factors of 10)
+    same = np.abs(ld.cpu().numpy() / ol - 1.0) < 1e-3
+    assert same.mean() > 0.99
+
+
+def compare_icm(gx, gp, glam, ox, op, olam, frames, label, tol_img=1e-3, tol_maps=1e-3, max_branched=0.01):
+    """Whole-schedule comparison.  The MAP-LM accept test is a branch on a difference of two
+    FP32 objective values; where that difference falls within FP32 resolution of the threshold
+    the GPU and the FP64 oracle take different branches and that voxel's trajectory separates
+    (lambda then differs by powers of 10).  Such voxels are counted and must stay rare; the
+    maps of all other voxels above 10 % of peak activity must agree to tol_maps."""
+    ex = rel_l2(gx, ox)
+    act = (ox * (frames.t1 - frames.t0)).sum(axis=-1)
+    mask = act >= 0.1 * act.max()
+    same = np.abs(glam / olam - 1.0) < 1e-3
+    literal = [rel_l2(gp[i][mask], op[i][mask]) for i in range(3)]
+    matched = [rel_l2(gp[i][mask & same], op[i][mask & same]) for i in range(3)]
+    branched = 1.0 - same[mask].mean()
+    print(f"{label}: image relL2 {ex:.2e}; maps over active voxels {['%.2e' % e for e in literal]}; "
+          f"over active voxels with the same LM history {['%.2e' % e for e in matched]}; "
+          f"branched fraction {branched:.4f} ({int((~same & mask).sum())} of {int(mask.sum())})")
+    assert ex < tol_img
+    assert max(matched) < tol_maps
+    assert branched <= max_branched
+    assert max(literal) < 20 * tol_maps
 
 
 def test_icm_full_schedule_cfg1():
-    """The whole cfg1 schedule (10 sweeps x (4 subsets + 5 LM)) from the same initial state."""
+    """The whole 64x64 schedule (10 sweeps x (4 subsets + 5 LM)) from the same initial state."""
     st = cfg1_study()
     cfg = st.cfg
     g, f, k, p, lm = kcs_objects(st)
@@ -200,13 +224,43 @@ def test_icm_full_schedule_cfg1():
     for s in range(cfg.n_sweeps):
         kcs.kcs_icm_sweep(g, f, k, p, lm, sino, cfg.Q, s, x, params, lam, work)
     torch.cuda.synchronize()
-    ox, op, _ = oracle.icm(st.geom, st.frames, st.kin, st.prior, st.lm, st.sino.astype(np.float64), cfg.Q, cfg.n_sweeps)
-    gx, gp = x.cpu().numpy(), params.cpu().numpy()
-    ex = rel_l2(gx, ox)
-    act = (ox * (st.frames.t1 - st.frames.t0)).sum(axis=-1)
-    mask = act >= 0.1 * act.max()
-    ep = [rel_l2(gp[i][mask], op[i][mask]) for i in range(3)]
-    eall = [rel_l2(gp[i], op[i]) for i in range(3)]
-    print(f"cfg1 ICM: image relL2 {ex:.2e}; maps (active voxels) {ep}; maps (all) {eall}")
-    assert ex < 1e-3
-    assert max(ep) < 1e-3
+    ox, op, ol = oracle.icm(st.geom, st.frames, st.kin, st.prior, st.lm, st.sino.astype(np.float64), cfg.Q,
+                            cfg.n_sweeps)
+    compare_icm(x.cpu().numpy(), params.cpu().numpy(), lam.cpu().numpy(), ox, op, ol, st.frames, "64x64 ICM")
+
+
+def run_tiled_plane(cfg_full, n_sweeps, n_distinct=1):
+    """GPU run at the full size of cfg_full whose sinogram repeats the oracle-synthesised planes of
+    `n_distinct` single-plane studies (seeds 1..n_distinct); returns the GPU state, the plane
+    studies and the repetition index of every plane."""
+    planes = [oracle.make_study(inputs.scaled(cfg_full, nz=1, seed=1 + i)) for i in range(n_distinct)]
+    st0 = planes[0]
+    nz = cfg_full.nz
+    which = np.arange(nz) % n_distinct
+    sino = np.concatenate([planes[w].sino for w in which], axis=0)
+    g = kcs.Geometry.from_config(cfg_full)
+    _, f, k, p, lm = kcs_objects(st0)  # scales and background of the single-plane study
+    sd = dev(sino)
+    x = torch.empty((g.nz, g.ny, g.nx, M), device=DEV)
+    params = torch.empty((3, g.nz, g.ny, g.nx), device=DEV)
+    lam = torch.empty((g.nz, g.ny, g.nx), device=DEV)
+    work = kcs.alloc_workspace(g, M, cfg_full.Q, DEV)
+    kcs.kcs_init_state(g, f, sd, inputs.XI0, x, params, lam, work)
+    for s in range(n_sweeps):
+        kcs.kcs_icm_sweep(g, f, k, p, lm, sd, cfg_full.Q, s, x, params, lam, work)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), params.cpu().numpy(), lam.cpu().numpy(), planes, which
+
+
+@pytest.mark.parametrize("cfg_name,n_sweeps", [("cfg2", 3), ("cfg3", 1)])
+def test_icm_full_size_sampled_planes(cfg_name, n_sweeps):
+    """Full-size study in the benchmark's launch configuration; planes are independent, so each
+    sampled plane is checked against the oracle run on that plane alone, and planes with the
+    same input must come out bit-identical."""
+    cfg = inputs.CONFIGS[cfg_name]()
+    gx, gp, gl, planes, which = run_tiled_plane(cfg, n_sweeps)
+    st = planes[0]
+    for zz in range(1, cfg.nz):
+        assert np.array_equal(gx[zz], gx[0]) and np.array_equal(gp[:, zz], gp[:, 0])
+    ox, op, ol = oracle.icm(st.geom, st.frames, st.kin, st.prior, st.lm, st.sino.astype(np.float64), cfg.Q, n_sweeps)
+    compare_icm(gx[:1], gp[:, :1], gl[:1], ox, op, ol, st.frames, f"{cfg_name} full size, plane 0, {n_sweeps} sweeps")
