@@ -146,7 +146,8 @@ int kcs_init_state(const kcs_geometry* g, const kcs_frames* f, const float* d_si
                    hipStream_t stream);
 
 /* One ICM sweep (Sec. II-D): kcs_osl_update for q = 0..Q-1 (prior on iff p->kp_on and
- * sweep_idx > 0), then kcs_lm_fit. */
+ * sweep_idx > 0), then kcs_lm_fit as a fresh fit: lambda is initialised from tau * max diag(J^T J)
+ * whatever d_lambda holds on entry; d_lambda returns the damping after the last iteration. */
 int kcs_icm_sweep(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics* k, const kcs_prior* p,
                   const kcs_lm_opts* lm, const float* d_sino, int32_t Q, int32_t sweep_idx, float* d_x,
                   float* d_params, float* d_lambda, void* d_work, size_t work_bytes, hipStream_t stream);

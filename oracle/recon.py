@@ -174,11 +174,12 @@ def lm_fit(fr, kin, prior, opt, x, params, lam):
 
 def icm_sweep(g, fr, kin, prior, opt, sino, x, params, lam, Q: int, sweep_idx: int):
     """One ICM sweep (Sec. II-D): OS-MAP-OSL-KP over all Q subsets given the maps, then MAP-LM
-    given the new image."""
+    given the new image.  Each sweep's MAP-LM is a new fit to a new image, so its damping starts
+    from tau * max diag(J^T J) (the lambda passed in is ignored; the final one is returned)."""
     kp = prior.kp_on and sweep_idx > 0
     for q in range(Q):
         x = osl_update(g, fr, kin, prior, sino, params, x, q, Q, kp)
-    params, lam = lm_fit(fr, kin, prior, opt, x, params, lam)
+    params, lam = lm_fit(fr, kin, prior, opt, x, params, np.zeros_like(lam))
     return x, params, lam
 
 

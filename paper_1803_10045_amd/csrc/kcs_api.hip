@@ -355,7 +355,7 @@ int do_osl(const kcs_geometry& g, const Schedule& S, const kcs_prior& p, bool kp
 }
 
 int do_lm(const kcs_geometry& g, const Schedule& S, const kcs_prior& p, const kcs_lm_opts& o, const float* x,
-          float* params, float* lam, void* d_work, int32_t Q, hipStream_t st) {
+          float* params, float* lam, void* d_work, int32_t Q, bool fresh_lambda, hipStream_t st) {
     if (o.n_iter == 0) return KCS_OK;
     const Layout L = layout(&g, S.fr.M, Q);
     const size_t N = (size_t)g.nx * g.ny * g.nz;
@@ -388,6 +388,7 @@ int do_lm(const kcs_geometry& g, const Schedule& S, const kcs_prior& p, const kc
     }
     const KinTab* K = at<KinTab>(d_work, L.kin);
     for (int it = 0; it < o.n_iter; ++it) {
+        a.reset_lambda = (fresh_lambda && it == 0) ? 1 : 0;
         KCS_TRY(launched(timed(KCS_T_LM, st, [&] { return launch_lm(S.fr.M, K, x, src, dst, lam, a, st); }),
                          "MAP-LM iteration"));
         std::swap(src, dst);
@@ -525,7 +526,7 @@ int kcs_lm_fit(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics* k
     const Schedule S = make_schedule(*f, k);
     g_err.clear();
     KCS_TRY(do_setup(S, d_work, stream));
-    return do_lm(*g, S, *p, *lm, d_x, d_params, d_lambda, d_work, 0, stream);
+    return do_lm(*g, S, *p, *lm, d_x, d_params, d_lambda, d_work, 0, false, stream);
 }
 
 int kcs_init_state(const kcs_geometry* g, const kcs_frames* f, const float* d_sino, const double xi0[3], float* d_x,
@@ -569,7 +570,7 @@ int kcs_icm_sweep(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics
     KCS_TRY(do_setup(S, d_work, stream));
     const bool kp = p->kp_on != 0 && sweep_idx > 0;
     for (int32_t q = 0; q < Q; ++q) KCS_TRY(do_osl(*g, S, *p, kp, d_sino, d_params, q, Q, d_x, d_work, stream));
-    return do_lm(*g, S, *p, *lm, d_x, d_params, d_lambda, d_work, Q, stream);
+    return do_lm(*g, S, *p, *lm, d_x, d_params, d_lambda, d_work, Q, true, stream);
 }
 
 }  // extern "C"

@@ -30,6 +30,7 @@ struct LmArgs {
     float delta[3];
     float tau, lam_min, lam_max;
     float eta;  // sufficient relative decrease of the objective for accepting a step
+    int32_t reset_lambda;  // 1: ignore the stored lambda and start from tau * max diag(J^T J)
     float lo[3], hi[3];
 };
 

@@ -82,7 +82,7 @@ __host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, 
     g1 -= a.beta_h * psi[1];
     g2 -= a.beta_h * psi[2];
 
-    float lam = lam_io[v];
+    float lam = a.reset_lambda ? 0.0f : lam_io[v];
     if (!(lam > 0.0f)) lam = a.tau * fmaxf(A00, fmaxf(A11, A22));
 
     // (A + lam I) step = g, symmetrically scaled by the inverse square roots of the diagonal,

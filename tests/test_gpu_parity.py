@@ -188,26 +188,19 @@ def test_lm_fit_parity():
     assert same.mean() > 0.99
 
 
-def compare_icm(gx, gp, glam, ox, op, olam, frames, label, tol_img=1e-3, tol_maps=1e-3, max_branched=0.01):
-    """Whole-schedule comparison.  The MAP-LM accept test is a branch on a difference of two
-    FP32 objective values; where that difference falls within FP32 resolution of the threshold
-    the GPU and the FP64 oracle take different branches and that voxel's trajectory separates
-    (lambda then differs by powers of 10).  Such voxels are counted and must stay rare; the
-    maps of all other voxels above 10 % of peak activity must agree to tol_maps."""
+def compare_icm(gx, gp, glam, ox, op, olam, frames, label, tol_img=1e-3, tol_maps=1e-3):
+    """Whole-schedule comparison: relative L2 of the image over all voxels and of each map over the
+    voxels above 10 % of peak activity.  Also reports how many voxels took a different MAP-LM
+    accept/reject path (their final lambda differs by a power of 10)."""
     ex = rel_l2(gx, ox)
     act = (ox * (frames.t1 - frames.t0)).sum(axis=-1)
     mask = act >= 0.1 * act.max()
     same = np.abs(glam / olam - 1.0) < 1e-3
-    literal = [rel_l2(gp[i][mask], op[i][mask]) for i in range(3)]
-    matched = [rel_l2(gp[i][mask & same], op[i][mask & same]) for i in range(3)]
-    branched = 1.0 - same[mask].mean()
-    print(f"{label}: image relL2 {ex:.2e}; maps over active voxels {['%.2e' % e for e in literal]}; "
-          f"over active voxels with the same LM history {['%.2e' % e for e in matched]}; "
-          f"branched fraction {branched:.4f} ({int((~same & mask).sum())} of {int(mask.sum())})")
+    maps = [rel_l2(gp[i][mask], op[i][mask]) for i in range(3)]
+    print(f"{label}: image relL2 {ex:.2e}; maps over active voxels {['%.2e' % e for e in maps]}; "
+          f"voxels with a different LM path {int((~same & mask).sum())} of {int(mask.sum())}")
     assert ex < tol_img
-    assert max(matched) < tol_maps
-    assert branched <= max_branched
-    assert max(literal) < 20 * tol_maps
+    assert max(maps) < tol_maps
 
 
 def test_icm_full_schedule_cfg1():
