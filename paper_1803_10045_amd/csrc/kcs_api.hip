@@ -1,6 +1,7 @@
 // Host side of libkcs: argument validation, FP64 constants, workspace layout and the C ABI.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <mutex>
 #include <cstdarg>
 #include <cstdio>
@@ -254,11 +255,24 @@ double total_path_length(const kcs_geometry& g) {
 
 // Workspace layout
 struct Layout {
-    size_t kin, ratio, xi, init, total;
+    size_t kin, xi, init, F, ratio, psum, total;
 };
 
-// Offsets of the workspace regions.  The ratio buffer (the largest subset's sinogram) comes
-// last so that calls without projections (Q = 0) need only the leading regions.
+// Forward projector variant for a geometry: 0 = ray-driven, T = LDS tiles of T x T pixels.
+// Images whose plane exceeds an XCD's L2 use tiles.  KCS_PROJ_TILE overrides (0, 16, 32).
+int projector_tile(const kcs_geometry& g, int M) {
+    if (const char* e = getenv("KCS_PROJ_TILE")) {
+        const int t = atoi(e);
+        if (t == 0 || t == 16 || (t == 32 && M <= 24)) return t;
+    }
+    const double plane_bytes = (double)g.nx * g.ny * M * 4.0;
+    if (plane_bytes < 2.0 * 1024 * 1024) return 0;
+    return M <= 24 ? 32 : 16;
+}
+
+// Offsets of the workspace regions.  The model TACs of the maps and the ratio buffer (the
+// largest subset's sinogram) come last so that calls without projections (Q = 0) need only the
+// leading regions.
 Layout layout(const kcs_geometry* g, int32_t M, int32_t Q) {
     Layout L{};
     size_t off = 0;
@@ -270,10 +284,22 @@ Layout layout(const kcs_geometry* g, int32_t M, int32_t Q) {
         off = align_up(off + 3 * N * sizeof(float), 256);
         L.init = off;
         off = align_up(off + ((size_t)kInitChunks * M + M) * sizeof(double), 256);
+        L.F = off;
+        if (Q > 0) off = align_up(off + N * M * sizeof(float), 256);
         L.ratio = off;
+        L.psum = off;
         if (Q > 0) {
             const size_t A_max = (size_t)((g->n_ang + Q - 1) / Q);
             off = align_up(off + (size_t)g->nz * A_max * g->n_bin * M * sizeof(float), 256);
+            L.psum = off;
+            ProjArgs pa{};
+            pa.nx = g->nx;
+            pa.ny = g->ny;
+            pa.nz = g->nz;
+            pa.A_q = (int32_t)A_max;
+            pa.h = (float)g->pixel_mm;
+            pa.du = (float)g->bin_mm;
+            off = align_up(off + std::max(tile_partial_bytes(16, pa, M), tile_partial_bytes(32, pa, M)), 256);
         }
     }
     L.total = off;
@@ -338,8 +364,21 @@ int do_setup(const Schedule& S, void* d_work, hipStream_t st) {
                     "table setup");
 }
 
-int do_osl(const kcs_geometry& g, const Schedule& S, const kcs_prior& p, bool kp, const float* sino, const float* params,
-           int32_t q, int32_t Q, float* x, void* d_work, hipStream_t st) {
+// Model TACs of the maps into the workspace (read by every OSL update of the pass).
+int do_model_pass(const kcs_geometry& g, const Schedule& S, const float* params, void* d_work, int32_t Q,
+                  hipStream_t st) {
+    const Layout L = layout(&g, S.fr.M, Q);
+    const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+    return launched(timed(KCS_T_MODEL, st,
+                          [&] {
+                              return launch_model(S.fr.M, at<KinTab>(d_work, L.kin), S.fr, params, N,
+                                                  at<float>(d_work, L.F), nullptr, st);
+                          }),
+                    "model pass");
+}
+
+int do_osl(const kcs_geometry& g, const Schedule& S, const kcs_prior& p, bool kp, const float* sino, int32_t q,
+           int32_t Q, float* x, void* d_work, hipStream_t st) {
     const Layout L = layout(&g, S.fr.M, Q);
     OslArgs a{};
     a.g = proj_args(g, S.fr, q, Q);
@@ -347,11 +386,16 @@ int do_osl(const kcs_geometry& g, const Schedule& S, const kcs_prior& p, bool kp
     a.eps_F = (float)p.eps_F;
     a.kp = kp ? 1 : 0;
     float* ratio = at<float>(d_work, L.ratio);
-    KCS_TRY(launched(timed(KCS_T_PROJECT, st, [&] { return launch_project(S.fr.M, x, sino, ratio, a.g, true, st); }),
+    const int T = projector_tile(g, S.fr.M);
+    float* psum = at<float>(d_work, L.psum);
+    KCS_TRY(launched(timed(KCS_T_PROJECT, st,
+                           [&] {
+                               return T ? launch_project_tiled(S.fr.M, T, x, sino, ratio, psum, a.g, true, st)
+                                        : launch_project(S.fr.M, x, sino, ratio, a.g, true, st);
+                           }),
                      "forward projection"));
-    return launched(
-        timed(KCS_T_OSL, st, [&] { return launch_osl(S.fr.M, ratio, params, at<KinTab>(d_work, L.kin), x, a, st); }),
-        "OSL update");
+    const float* Fm = at<float>(d_work, L.F);
+    return launched(timed(KCS_T_OSL, st, [&] { return launch_osl(S.fr.M, ratio, Fm, x, a, st); }), "OSL update");
 }
 
 int do_lm(const kcs_geometry& g, const Schedule& S, const kcs_prior& p, const kcs_lm_opts& o, const float* x,
@@ -509,8 +553,11 @@ int kcs_osl_update(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetic
     KCS_TRY(check_work(g, f->n_frames, Q, d_work, work_bytes));
     const Schedule S = make_schedule(*f, k);
     g_err.clear();
-    if (p->kp_on) KCS_TRY(do_setup(S, d_work, stream));
-    return do_osl(*g, S, *p, p->kp_on != 0, d_sino, d_params, q, Q, d_x, d_work, stream);
+    if (p->kp_on) {
+        KCS_TRY(do_setup(S, d_work, stream));
+        KCS_TRY(do_model_pass(*g, S, d_params, d_work, Q, stream));
+    }
+    return do_osl(*g, S, *p, p->kp_on != 0, d_sino, q, Q, d_x, d_work, stream);
 }
 
 int kcs_lm_fit(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics* k, const kcs_prior* p,
@@ -569,7 +616,8 @@ int kcs_icm_sweep(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics
     g_err.clear();
     KCS_TRY(do_setup(S, d_work, stream));
     const bool kp = p->kp_on != 0 && sweep_idx > 0;
-    for (int32_t q = 0; q < Q; ++q) KCS_TRY(do_osl(*g, S, *p, kp, d_sino, d_params, q, Q, d_x, d_work, stream));
+    if (kp) KCS_TRY(do_model_pass(*g, S, d_params, d_work, Q, stream));
+    for (int32_t q = 0; q < Q; ++q) KCS_TRY(do_osl(*g, S, *p, kp, d_sino, q, Q, d_x, d_work, stream));
     return do_lm(*g, S, *p, *lm, d_x, d_params, d_lambda, d_work, Q, true, stream);
 }
 

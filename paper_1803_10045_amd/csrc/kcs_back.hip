@@ -9,9 +9,10 @@
 // OSL update (Eq. 2 with the kinetics-derived potential of Eq. 3, sigma^2 = F / n):
 //   x_new = x * b / D,  b = E_m sum_d p_vd q_dm,  D = n_m (1 + beta (x - F) / max(F, eps_F)),
 //   n_m = E_m sum_d p_vd;  E_m cancels between b and D.  x is kept where sum_d p_vd = 0.
+// F, the model TAC of the current kinetic maps, does not change during an OSL pass; it is
+// evaluated once per pass (kcs_model pass) and read here.
 #include "kcs_device.h"
 #include "kcs_launch.h"
-#include "kcs_model.h"
 
 namespace kcs {
 
@@ -81,10 +82,12 @@ __host__ __device__ __forceinline__ void backproject_voxel(const AngleRec* sA, c
     if (sens_out) sens_out[v] = sens;
 }
 
+// OSL-KP update of voxel (i, j, z).  Fm: model TACs of the current maps [N][M] (only read when
+// the prior is on).
 template <int M>
 __host__ __device__ __forceinline__ void osl_voxel(const AngleRec* sA, const OslArgs& a, const float* __restrict__ ratio,
-                                                   const float* __restrict__ params, const KinTab& K,
-                                                   float* __restrict__ x, int i, int j, int z) {
+                                                   const float* __restrict__ Fm, float* __restrict__ x, int i, int j,
+                                                   int z) {
     const ProjArgs& p = a.g;
     float acc[M], sens;
     gather<M>(sA, p, ratio, i, j, z, acc, sens);
@@ -94,12 +97,13 @@ __host__ __device__ __forceinline__ void osl_voxel(const AngleRec* sA, const Osl
     load_record<M>(x + v * M, xv);
     const float inv_sens = 1.0f / sens;
     if (a.kp) {
-        const size_t N = (size_t)p.nx * p.ny * p.nz;
-        const float K1 = params[v], k2 = params[N + v], k3 = params[2 * N + v];
-        model_frames<M, false>(p.fr, K, K1, k2, k3, [&](int m, float F, float, float, float) {
-            const float d = fmaf(a.beta_kp, (xv[m] - F) / fmaxf(F, a.eps_F), 1.0f);
+        float F[M];
+        load_record<M>(Fm + v * M, F);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const float d = fmaf(a.beta_kp, (xv[m] - F[m]) / fmaxf(F[m], a.eps_F), 1.0f);
             xv[m] = xv[m] * acc[m] * inv_sens / d;
-        });
+        }
     } else {
 #pragma unroll
         for (int m = 0; m < M; ++m) xv[m] = xv[m] * acc[m] * inv_sens;
@@ -118,13 +122,13 @@ __global__ __launch_bounds__(256) void kback_kernel(const float* __restrict__ y,
 }
 
 template <int M>
-__global__ __launch_bounds__(256) void kosl_kernel(const float* __restrict__ ratio, const float* __restrict__ params,
-                                                   const KinTab* __restrict__ K, float* __restrict__ x, OslArgs a) {
+__global__ __launch_bounds__(256) void kosl_kernel(const float* __restrict__ ratio, const float* __restrict__ Fm,
+                                                   float* __restrict__ x, OslArgs a) {
     extern __shared__ AngleRec sA[];
     subset_angles_to_lds(sA, a.g);
     const TileIdx t = tile_voxel(a.g.nx, a.g.ny, a.g.nz);
     if (!t.valid) return;
-    osl_voxel<M>(sA, a, ratio, params, *K, x, t.i, t.j, t.z);
+    osl_voxel<M>(sA, a, ratio, Fm, x, t.i, t.j, t.z);
 }
 
 template <int M>
@@ -146,22 +150,20 @@ hipError_t launch_backproject(int M, const float* y, float* b, float* sens, cons
 }
 
 template <int M>
-static hipError_t launch_osl_m(const float* ratio, const float* params, const KinTab* K, float* x, const OslArgs& a,
-                               hipStream_t st) {
+static hipError_t launch_osl_m(const float* ratio, const float* Fm, float* x, const OslArgs& a, hipStream_t st) {
     const ProjArgs& p = a.g;
     hipLaunchKernelGGL((kosl_kernel<M>), dim3(tile_blocks(p.nx, p.ny, p.nz)), dim3(kTileX * kTileY), p.A_q * sizeof(AngleRec), st, ratio,
-                       params, K, x, a);
+                       Fm, x, a);
     return hipGetLastError();
 }
 
-hipError_t launch_osl(int M, const float* ratio, const float* params, const KinTab* K, float* x, const OslArgs& a,
-                      hipStream_t st) {
+hipError_t launch_osl(int M, const float* ratio, const float* Fm, float* x, const OslArgs& a, hipStream_t st) {
     if (a.g.A_q > kMaxSubsetAngles) return hipErrorInvalidValue;
     switch (M) {
-        case 8: return launch_osl_m<8>(ratio, params, K, x, a, st);
-        case 16: return launch_osl_m<16>(ratio, params, K, x, a, st);
-        case 24: return launch_osl_m<24>(ratio, params, K, x, a, st);
-        case 32: return launch_osl_m<32>(ratio, params, K, x, a, st);
+        case 8: return launch_osl_m<8>(ratio, Fm, x, a, st);
+        case 16: return launch_osl_m<16>(ratio, Fm, x, a, st);
+        case 24: return launch_osl_m<24>(ratio, Fm, x, a, st);
+        case 32: return launch_osl_m<32>(ratio, Fm, x, a, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -79,17 +79,15 @@ __host__ __device__ __forceinline__ float pixel_chord(const AngleRec& A, float t
     return in ? A.m : 0.0f;
 }
 
-// Incremental Siddon traversal of ray (A, u) through an nx x ny grid of h-pixels centred on the
-// origin: calls visit(i, j, len) for every pixel the ray crosses, in order, with the exact
-// intersection length.  Coordinates are in pixel units, X = (x + nx h / 2) / h, and the point
-// at parameter lam (pixel units of length along the ray) is (Xc - lam s, Yc + lam c).  The
+// Incremental Siddon traversal of a ray through an nx x ny box of pixels: calls
+// visit(i, j, len) for every pixel the ray crosses, in order, with the exact intersection length
+// (mm).  Coordinates are in pixel units relative to the box corner; (Xc, Yc) is the ray's foot
+// point and the point at parameter lam (pixel units of length) is (Xc - lam s, Yc + lam c).  The
 // crossing parameters are re-derived from the grid-line index at each step, so the rounding
 // error does not accumulate along the ray.  At most nx + ny + 2 steps.
 template <class Visit>
-__host__ __device__ __forceinline__ void siddon_traverse(const AngleRec& A, float u, int nx, int ny, float h,
-                                                         float inv_h, Visit&& visit) {
-    const float Xc = u * A.c * inv_h + 0.5f * (float)nx;
-    const float Yc = u * A.s * inv_h + 0.5f * (float)ny;
+__host__ __device__ __forceinline__ void siddon_traverse_box(const AngleRec& A, float Xc, float Yc, int nx, int ny,
+                                                             float h, Visit&& visit) {
     float lin = -3.0e38f, lout = 3.0e38f;
     bool hit = true;
     if (A.s != 0.0f) {
@@ -150,6 +148,30 @@ __host__ __device__ __forceinline__ void siddon_traverse(const AngleRec& A, floa
         if (i < 0 || i >= nx || j < 0 || j >= ny) break;
         lcur = lnext;
     }
+}
+
+// Ray (A, u) through the whole nx x ny grid of h-pixels centred on the origin.
+template <class Visit>
+__host__ __device__ __forceinline__ void siddon_traverse(const AngleRec& A, float u, int nx, int ny, float h,
+                                                         float inv_h, Visit&& visit) {
+    const float Xc = u * A.c * inv_h + 0.5f * (float)nx;
+    const float Yc = u * A.s * inv_h + 0.5f * (float)ny;
+    siddon_traverse_box(A, Xc, Yc, nx, ny, h, visit);
+}
+
+// Bins whose rays can meet the pixel box [i0, i0+w) x [j0, j0+hgt) of an nx x ny grid: the
+// box's corners projected on the detector, widened by a hundredth of a bin so that rounding can
+// only add rays (a ray that misses the box contributes exactly 0).  Producer and consumer of
+// per-tile partial sums call this same function, so they agree on the set.
+__host__ __device__ __forceinline__ void box_bins(const AngleRec& A, int i0, int j0, int w, int hgt, int nx, int ny,
+                                                  float h, float inv_du, int n_bin, int& b0, int& b1) {
+    const float xl = ((float)i0 - 0.5f * (float)nx) * h, xr = xl + (float)w * h;
+    const float yl = ((float)j0 - 0.5f * (float)ny) * h, yr = yl + (float)hgt * h;
+    const float u0 = xl * A.c, u1 = xr * A.c, v0 = yl * A.s, v1 = yr * A.s;
+    const float umin = fminf(u0, u1) + fminf(v0, v1), umax = fmaxf(u0, u1) + fmaxf(v0, v1);
+    const float bc = 0.5f * (float)(n_bin - 1);
+    b0 = max((int)ceilf(fmaf(umin, inv_du, bc) - 0.01f), 0);
+    b1 = min((int)floorf(fmaf(umax, inv_du, bc) + 0.01f), n_bin - 1);
 }
 
 // Bins whose rays cross the pixel centred at (xc, yc): calls visit(b, len) with the chord.

@@ -46,9 +46,11 @@ struct SetupArgs {
 hipError_t launch_setup(const SetupArgs& s, KinTab* K, hipStream_t st);
 hipError_t launch_project(int M, const float* x, const float* sino, float* out, const ProjArgs& p, bool ratio,
                           hipStream_t st);
+hipError_t launch_project_tiled(int M, int T, const float* x, const float* sino, float* out, float* psum,
+                                const ProjArgs& p, bool ratio, hipStream_t st);
+size_t tile_partial_bytes(int T, const ProjArgs& p, int M);
 hipError_t launch_backproject(int M, const float* y, float* b, float* sens, const ProjArgs& p, hipStream_t st);
-hipError_t launch_osl(int M, const float* ratio, const float* params, const KinTab* K, float* x, const OslArgs& a,
-                      hipStream_t st);
+hipError_t launch_osl(int M, const float* ratio, const float* Fm, float* x, const OslArgs& a, hipStream_t st);
 hipError_t launch_lm(int M, const KinTab* K, const float* x, const float* xi_in, float* xi_out, float* lam,
                      const LmArgs& a, hipStream_t st);
 hipError_t launch_model(int M, const KinTab* K, const FrameTab& fr, const float* params, int64_t n, float* F, float* J,

@@ -7,6 +7,13 @@
 // each thread writes its M-frame record, so the write stream is dense.
 // In ratio mode the thread also forms ybar = E_m * sum + r_m and writes s / ybar (the
 // measured-to-expected ratio that the OSL back projection consumes).
+//
+// Tiled variant (large images): the image of one plane does not fit in an XCD's L2, so the
+// ray-driven kernel re-reads it once per angle.  kproj_tile_kernel instead stages one T x T
+// tile (all M frames) in LDS per workgroup and traverses, inside the tile, every subset ray that
+// can meet it, writing one partial line integral per (tile, ray).  kproj_reduce_kernel adds the
+// partials of each ray over the tiles in a fixed order (deterministic, no atomics) and applies
+// the same epilogue.  The image then crosses HBM once per subset.
 #include "kcs_device.h"
 #include "kcs_launch.h"
 
@@ -60,6 +67,133 @@ __global__ __launch_bounds__(256) void kproj_kernel(const float* __restrict__ x,
     project_ray<M, RATIO>(p, x, sino, out, z, al, ray - al * p.n_bin);
 }
 
+// Slots reserved per (tile, angle) for the rays that can meet a T x T tile.
+__host__ __device__ inline int tile_slots(int T, float h, float du) {
+    return (int)floorf((float)T * h * 1.41421357f / du) + 3;
+}
+
+template <int M, int T>
+__global__ __launch_bounds__(256) void kproj_tile_kernel(const float* __restrict__ x, float* __restrict__ psum,
+                                                         ProjArgs p, int slots) {
+    extern __shared__ float4 lds4[];
+    AngleRec* sA = reinterpret_cast<AngleRec*>(lds4 + T * T * M / 4);
+    const int ntx = (p.nx + T - 1) / T, nty = (p.ny + T - 1) / T;
+    const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
+    const int z = w / (ntx * nty);
+    if (z >= p.nz) return;  // whole workgroup
+    const int tr = w % (ntx * nty), ty = tr / ntx, tx = tr % ntx;
+    const int i0 = tx * T, j0 = ty * T, tw = min(T, p.nx - i0), th = min(T, p.ny - j0);
+    // stage the tile: row r of the tile is tw * M contiguous floats of the image
+    const int row4 = tw * M / 4;
+    const float4* src = reinterpret_cast<const float4*>(x) + (((size_t)z * p.ny + j0) * p.nx + i0) * (M / 4);
+    for (int e = threadIdx.x; e < th * row4; e += blockDim.x) {
+        const int r = e / row4, c = e - r * row4;
+        lds4[r * (T * M / 4) + c] = src[(size_t)r * p.nx * (M / 4) + c];
+    }
+    for (int al = threadIdx.x; al < p.A_q; al += blockDim.x) sA[al] = make_angle(p.q + al * p.Q, p.n_ang, p.ang0, p.h);
+    __syncthreads();
+    const float bc = 0.5f * (float)(p.n_bin - 1);
+    const float* tile = reinterpret_cast<const float*>(lds4);
+    float* out = psum + (((size_t)z * nty + ty) * ntx + tx) * (size_t)p.A_q * slots * M;
+    for (int it = threadIdx.x; it < p.A_q * slots; it += blockDim.x) {
+        const int al = it / slots, slot = it - al * slots;
+        const AngleRec A = sA[al];
+        int b0, b1;
+        box_bins(A, i0, j0, tw, th, p.nx, p.ny, p.h, p.inv_du, p.n_bin, b0, b1);
+        const int b = b0 + slot;
+        if (b > b1) continue;
+        float acc[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) acc[m] = 0.0f;
+        const float u = ((float)b - bc) * p.du;
+        const float Xc = u * A.c * p.inv_h + 0.5f * (float)p.nx - (float)i0;
+        const float Yc = u * A.s * p.inv_h + 0.5f * (float)p.ny - (float)j0;
+        siddon_traverse_box(A, Xc, Yc, tw, th, p.h, [&](int i, int j, float len) {
+            float v[M];
+            load_record<M>(tile + (j * T + i) * M, v);
+#pragma unroll
+            for (int m = 0; m < M; ++m) acc[m] = fmaf(len, v[m], acc[m]);
+        });
+        store_record<M>(out + (size_t)it * M, acc);
+    }
+}
+
+template <int M, int T, bool RATIO>
+__global__ __launch_bounds__(256) void kproj_reduce_kernel(const float* __restrict__ psum,
+                                                           const float* __restrict__ sino, float* __restrict__ out,
+                                                           ProjArgs p, int slots) {
+    const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
+    const uint32_t blocks_per_plane = (p.rays_per_plane + 255u) / 256u;
+    const uint32_t z = w / blocks_per_plane;
+    if (z >= (uint32_t)p.nz) return;
+    const uint32_t ray = (w % blocks_per_plane) * 256u + threadIdx.x;
+    if (ray >= (uint32_t)p.rays_per_plane) return;
+    const int al = ray / p.n_bin;
+    const int b = ray - al * p.n_bin;
+    const int a = p.q + al * p.Q;
+    const AngleRec A = make_angle(a, p.n_ang, p.ang0, p.h);
+    const int ntx = (p.nx + T - 1) / T, nty = (p.ny + T - 1) / T;
+    float acc[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) acc[m] = 0.0f;
+    const float* pz = psum + (size_t)z * nty * ntx * p.A_q * slots * M;
+    for (int ty = 0; ty < nty; ++ty) {
+        for (int tx = 0; tx < ntx; ++tx) {
+            const int i0 = tx * T, j0 = ty * T;
+            int b0, b1;
+            box_bins(A, i0, j0, min(T, p.nx - i0), min(T, p.ny - j0), p.nx, p.ny, p.h, p.inv_du, p.n_bin, b0, b1);
+            if (b < b0 || b > b1 || b - b0 >= slots) continue;
+            float v[M];
+            load_record<M>(pz + (((size_t)(ty * ntx + tx) * p.A_q + al) * slots + (b - b0)) * M, v);
+#pragma unroll
+            for (int m = 0; m < M; ++m) acc[m] += v[m];
+        }
+    }
+    const size_t o = (((size_t)z * p.A_q + al) * p.n_bin + b) * M;
+    float y[M];
+    if (RATIO) {
+        float s[M];
+        load_record<M>(sino + (((size_t)z * p.n_ang + a) * p.n_bin + b) * M, s);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const float yb = fmaf(p.fr.E[m], acc[m], p.fr.r[m]);
+            y[m] = yb > 0.0f ? s[m] / yb : 0.0f;
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < M; ++m) y[m] = fmaf(p.fr.E[m], acc[m], p.fr.r[m]);
+    }
+    store_record<M>(out + o, y);
+}
+
+size_t tile_partial_bytes(int T, const ProjArgs& p, int M) {
+    const size_t ntx = (p.nx + T - 1) / T, nty = (p.ny + T - 1) / T;
+    return (size_t)p.nz * ntx * nty * p.A_q * tile_slots(T, p.h, p.du) * M * sizeof(float);
+}
+
+template <int M, int T>
+static hipError_t launch_proj_tiled(const float* x, const float* sino, float* out, float* psum, const ProjArgs& p,
+                                    bool ratio, hipStream_t st) {
+    const int slots = tile_slots(T, p.h, p.du);
+    const int ntx = (p.nx + T - 1) / T, nty = (p.ny + T - 1) / T;
+    const uint32_t nt = xcd_round_up((uint32_t)(ntx * nty * p.nz));
+    const size_t lds = (size_t)T * T * M * sizeof(float) + (size_t)p.A_q * sizeof(AngleRec);
+    static bool attr_set = false;  // the tile may exceed the default 64 KB of dynamic LDS
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&kproj_tile_kernel<M, T>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((kproj_tile_kernel<M, T>), dim3(nt), dim3(256), lds, st, x, psum, p, slots);
+    const uint32_t bpp = (p.rays_per_plane + 255u) / 256u;
+    const uint32_t nr = xcd_round_up(bpp * (uint32_t)p.nz);
+    if (ratio)
+        hipLaunchKernelGGL((kproj_reduce_kernel<M, T, true>), dim3(nr), dim3(256), 0, st, psum, sino, out, p, slots);
+    else
+        hipLaunchKernelGGL((kproj_reduce_kernel<M, T, false>), dim3(nr), dim3(256), 0, st, psum, sino, out, p, slots);
+    return hipGetLastError();
+}
+
 template <int M>
 static hipError_t launch_proj_m(const float* x, const float* sino, float* out, const ProjArgs& p, bool ratio,
                                 hipStream_t st) {
@@ -79,6 +213,28 @@ hipError_t launch_project(int M, const float* x, const float* sino, float* out, 
         case 16: return launch_proj_m<16>(x, sino, out, p, ratio, st);
         case 24: return launch_proj_m<24>(x, sino, out, p, ratio, st);
         case 32: return launch_proj_m<32>(x, sino, out, p, ratio, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int M>
+static hipError_t launch_tiled_m(int T, const float* x, const float* sino, float* out, float* psum, const ProjArgs& p,
+                                 bool ratio, hipStream_t st) {
+    switch (T) {
+        case 16: return launch_proj_tiled<M, 16>(x, sino, out, psum, p, ratio, st);
+        case 32: return launch_proj_tiled<M, 32>(x, sino, out, psum, p, ratio, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_project_tiled(int M, int T, const float* x, const float* sino, float* out, float* psum,
+                                const ProjArgs& p, bool ratio, hipStream_t st) {
+    if (M == 32 && T == 32) return hipErrorInvalidValue;  // tile would exceed the LDS
+    switch (M) {
+        case 8: return launch_tiled_m<8>(T, x, sino, out, psum, p, ratio, st);
+        case 16: return launch_tiled_m<16>(T, x, sino, out, psum, p, ratio, st);
+        case 24: return launch_tiled_m<24>(T, x, sino, out, psum, p, ratio, st);
+        case 32: return launch_tiled_m<32>(T, x, sino, out, psum, p, ratio, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -257,3 +257,30 @@ def test_icm_full_size_sampled_planes(cfg_name, n_sweeps):
         assert np.array_equal(gx[zz], gx[0]) and np.array_equal(gp[:, zz], gp[:, 0])
     ox, op, ol = oracle.icm(st.geom, st.frames, st.kin, st.prior, st.lm, st.sino.astype(np.float64), cfg.Q, n_sweeps)
     compare_icm(gx[:1], gp[:, :1], gl[:1], ox, op, ol, st.frames, f"{cfg_name} full size, plane 0, {n_sweeps} sweeps")
+
+
+@pytest.mark.parametrize("tile", ["0", "16", "32"])
+def test_osl_update_projector_variants(tile, monkeypatch):
+    """The OSL update with each forward-projector variant (ray-driven, LDS tiles of 16 or 32
+    pixels with partial sums) on a geometry with ragged edge tiles and uneven subsets."""
+    monkeypatch.setenv("KCS_PROJ_TILE", tile)
+    nx, ny, nz, h, na, nb, du, Q = 150, 130, 2, 2.0, 100, 160, 1.8, 7
+    og, kg = geometry_pair(nx, ny, nz, h, na, nb, du, 0.02)
+    fr = default_frames(seed=3)
+    rng = np.random.default_rng(7)
+    x0 = make_image(nz, ny, nx, M, seed=8)
+    sino = rng.poisson(fr.E * oracle.forward(og, x0) + fr.r).astype(np.float32).astype(np.float64)
+    maps = np.stack([np.full((nz, ny, nx), v) for v in inputs.GRAY])
+    prior = oracle.Prior(beta_kp=0.1, eps_F=0.01, beta_h=0.1, delta=(1e-3,) * 3, kp_on=False)
+    kp = kcs.Prior(0.1, 0.01, 0.1, (1e-3,) * 3, False)
+    kk = kcs.Kinetics(KIN.A1, KIN.A2, KIN.A3, KIN.l1, KIN.l2, KIN.l3, KIN.vb)
+    work = kcs.alloc_workspace(kg, M, Q, DEV)
+    xd = dev(x0)
+    ox = x0.copy()
+    for q in range(Q):
+        kcs.kcs_osl_update(kg, kframes(fr), kk, kp, dev(sino), dev(maps), q, Q, xd, work)
+        ox = oracle.osl_update(og, fr, KIN, prior, sino, maps, ox, q, Q, False)
+    torch.cuda.synchronize()
+    err = rel_l2(xd.cpu().numpy(), ox)
+    print(f"projector tile {tile}: OSL pass relL2 {err:.2e}")
+    assert err < 1e-5
