@@ -21,16 +21,18 @@ __host__ __device__ __forceinline__ float huber(float t, float d) {
     return at <= d ? 0.5f * t * t : d * at - 0.5f * d * d;
 }
 
+// F0 (the model at the current parameters) is kept in a per-thread strip `F0` of M floats with
+// stride `fs` (LDS on the device), so the frame loops can stay rolled.
 template <int M>
 __host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, const float* __restrict__ x,
                                                   const float* __restrict__ xi_in, float* __restrict__ xi_out,
-                                                  float* __restrict__ lam_io, const LmArgs& a, int i, int j, int z) {
+                                                  float* __restrict__ lam_io, const LmArgs& a, int i, int j, int z,
+                                                  float* F0, int fs) {
     const size_t plane = (size_t)a.nx * a.ny;
     const size_t N = plane * a.nz;
     const size_t v = (size_t)z * plane + (size_t)j * a.nx + i;
 
-    float xv[M];
-    load_record<M>(x + v * M, xv);
+    const float* xv = x + v * M;
     const float p0 = xi_in[v], p1 = xi_in[N + v], p2 = xi_in[2 * N + v];
 
     // neighbours from the previous maps
@@ -62,10 +64,9 @@ __host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, 
     }
 
     // model, Jacobian and normal equations at the current parameters
-    float F0[M];
     float A00 = 0, A01 = 0, A02 = 0, A11 = 0, A12 = 0, A22 = 0, g0 = 0, g1 = 0, g2 = 0, rr = 0;
-    model_frames<M, true>(a.fr, *K, p0, p1, p2, [&](int m, float F, float j0, float j1, float j2) {
-        F0[m] = F;
+    model_frames<M, true, false>(a.fr, *K, p0, p1, p2, [&](int m, float F, float j0, float j1, float j2) {
+        F0[m * fs] = F;
         const float r = xv[m] - F;
         A00 = fmaf(j0, j0, A00);
         A01 = fmaf(j0, j1, A01);
@@ -112,9 +113,10 @@ __host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, 
                        huber(q2 - nb[k][2], a.delta[2]));
 
     float dphi = 0.0f;
-    model_frames<M, false>(a.fr, *K, q0, q1, q2, [&](int m, float F, float, float, float) {
-        const float df = F0[m] - F;
-        dphi = fmaf(0.5f * df, 2.0f * xv[m] - F0[m] - F, dphi);
+    model_frames<M, false, false>(a.fr, *K, q0, q1, q2, [&](int m, float F, float, float, float) {
+        const float f0 = F0[m * fs];
+        const float df = f0 - F;
+        dphi = fmaf(0.5f * df, 2.0f * xv[m] - f0 - F, dphi);
     });
     dphi = fmaf(a.beta_h, e1 - e0, dphi);
 
@@ -137,7 +139,8 @@ __global__ __launch_bounds__(256) void klm_kernel(const KinTab* __restrict__ K, 
     const int j = (rr / tx) * kLmTileY + threadIdx.x / kLmTileX;
     const int i = (rr % tx) * kLmTileX + threadIdx.x % kLmTileX;
     if (z >= a.nz || i >= a.nx || j >= a.ny) return;
-    lm_voxel<M>(K, x, xi_in, xi_out, lam_io, a, i, j, z);
+    __shared__ float sF0[M * kLmTileX * kLmTileY];
+    lm_voxel<M>(K, x, xi_in, xi_out, lam_io, a, i, j, z, sF0 + threadIdx.x, kLmTileX * kLmTileY);
 }
 
 template <int M>

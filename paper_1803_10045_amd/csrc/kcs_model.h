@@ -128,13 +128,15 @@ __host__ __device__ __forceinline__ void boundary_J(const KinTab& K, const Bound
 }
 
 // Calls sink(m, F_m, dF/dK1, dF/dk2, dF/dk3) for every frame m (derivatives 0 when !DERIV).
-template <int M, bool DERIV, class Sink>
+// UNROLL = false keeps the frame loop rolled (small code, few registers; the sink then sees a
+// run-time frame index and must not index register arrays with it).
+template <int M, bool DERIV, bool UNROLL = true, class Sink>
 __host__ __device__ __forceinline__ void model_frames(const FrameTab& FT, const KinTab& K, float K1, float k2, float k3,
                                              Sink&& sink) {
     const VoxelRates R = voxel_rates(K, k2, k3);
     const float g = FT.one_minus_vb;
     float Jprev = 0.0f, dJprev = 0.0f;
-#pragma unroll
+#pragma unroll(UNROLL ? M : 1)
     for (int m = 0; m < M; ++m) {
         if (m == 0 || !FT.contiguous) boundary_J<DERIV>(K, K.b[K.i0[m]], R, Jprev, dJprev);
         float J1, dJ1 = 0.0f;
