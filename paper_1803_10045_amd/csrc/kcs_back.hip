@@ -24,8 +24,7 @@ struct TileIdx {
     bool valid;
 };
 
-__device__ __forceinline__ TileIdx tile_voxel(int nx, int ny, int nz) {
-    const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
+__device__ __forceinline__ TileIdx tile_voxel(uint32_t w, int nx, int ny, int nz) {
     const uint32_t tx = (nx + kTileX - 1) / kTileX, ty = (ny + kTileY - 1) / kTileY;
     TileIdx t;
     t.z = w / (tx * ty);
@@ -36,9 +35,9 @@ __device__ __forceinline__ TileIdx tile_voxel(int nx, int ny, int nz) {
     return t;
 }
 
-__host__ inline uint32_t tile_blocks(int nx, int ny, int nz) {
+uint32_t voxel_tile_groups(int nx, int ny, int nz) {
     const uint32_t tx = (nx + kTileX - 1) / kTileX, ty = (ny + kTileY - 1) / kTileY;
-    return xcd_round_up(tx * ty * (uint32_t)nz);
+    return tx * ty * (uint32_t)nz;
 }
 
 // Builds the subset's angle constants in LDS; all threads of the block take part.
@@ -111,61 +110,74 @@ __host__ __device__ __forceinline__ void osl_voxel(const AngleRec* sA, const Osl
     store_record<M>(x + v * M, xv);
 }
 
-template <int M>
-__global__ __launch_bounds__(256) void kback_kernel(const float* __restrict__ y, float* __restrict__ bout,
-                                                    float* __restrict__ sens_out, ProjArgs p) {
+template <int M, class Src>
+__global__ __launch_bounds__(256) void kback_kernel(Src src) {
     extern __shared__ AngleRec sA[];
-    subset_angles_to_lds(sA, p);
-    const TileIdx t = tile_voxel(p.nx, p.ny, p.nz);
+    const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
+    const BackJob& J = src.find(w);
+    subset_angles_to_lds(sA, J.p);
+    const TileIdx t = tile_voxel(w - J.w0, J.p.nx, J.p.ny, J.p.nz);
     if (!t.valid) return;
-    backproject_voxel<M>(sA, p, y, bout, sens_out, t.i, t.j, t.z);
+    backproject_voxel<M>(sA, J.p, J.y, J.b, J.sens, t.i, t.j, t.z);
 }
 
-template <int M>
-__global__ __launch_bounds__(256) void kosl_kernel(const float* __restrict__ ratio, const float* __restrict__ Fm,
-                                                   float* __restrict__ x, OslArgs a) {
+template <int M, class Src>
+__global__ __launch_bounds__(256) void kosl_kernel(Src src) {
     extern __shared__ AngleRec sA[];
-    subset_angles_to_lds(sA, a.g);
-    const TileIdx t = tile_voxel(a.g.nx, a.g.ny, a.g.nz);
+    const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
+    const OslJob& J = src.find(w);
+    subset_angles_to_lds(sA, J.a.g);
+    const TileIdx t = tile_voxel(w - J.w0, J.a.g.nx, J.a.g.ny, J.a.g.nz);
     if (!t.valid) return;
-    osl_voxel<M>(sA, a, ratio, Fm, x, t.i, t.j, t.z);
+    osl_voxel<M>(sA, J.a, J.ratio, J.Fm, J.x, t.i, t.j, t.z);
 }
 
-template <int M>
-static hipError_t launch_back_m(const float* y, float* b, float* sens, const ProjArgs& p, hipStream_t st) {
-    hipLaunchKernelGGL((kback_kernel<M>), dim3(tile_blocks(p.nx, p.ny, p.nz)), dim3(kTileX * kTileY), p.A_q * sizeof(AngleRec), st, y, b,
-                       sens, p);
+template <int M, class Src>
+static hipError_t launch_back_m(Src src, uint32_t groups, int max_angles, hipStream_t st) {
+    hipLaunchKernelGGL((kback_kernel<M, Src>), dim3(xcd_round_up(groups)), dim3(kTileX * kTileY),
+                       max_angles * sizeof(AngleRec), st, src);
+    return hipGetLastError();
+}
+
+template <int M, class Src>
+static hipError_t launch_osl_m(Src src, uint32_t groups, int max_angles, hipStream_t st) {
+    hipLaunchKernelGGL((kosl_kernel<M, Src>), dim3(xcd_round_up(groups)), dim3(kTileX * kTileY),
+                       max_angles * sizeof(AngleRec), st, src);
     return hipGetLastError();
 }
 
 hipError_t launch_backproject(int M, const float* y, float* b, float* sens, const ProjArgs& p, hipStream_t st) {
     if (p.A_q > kMaxSubsetAngles) return hipErrorInvalidValue;
+    OneJob<BackJob> src{BackJob{p, y, b, sens, 0}};
+    const uint32_t g = voxel_tile_groups(p.nx, p.ny, p.nz);
     switch (M) {
-        case 8: return launch_back_m<8>(y, b, sens, p, st);
-        case 16: return launch_back_m<16>(y, b, sens, p, st);
-        case 24: return launch_back_m<24>(y, b, sens, p, st);
-        case 32: return launch_back_m<32>(y, b, sens, p, st);
+        case 8: return launch_back_m<8>(src, g, p.A_q, st);
+        case 16: return launch_back_m<16>(src, g, p.A_q, st);
+        case 24: return launch_back_m<24>(src, g, p.A_q, st);
+        case 32: return launch_back_m<32>(src, g, p.A_q, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <int M>
-static hipError_t launch_osl_m(const float* ratio, const float* Fm, float* x, const OslArgs& a, hipStream_t st) {
-    const ProjArgs& p = a.g;
-    hipLaunchKernelGGL((kosl_kernel<M>), dim3(tile_blocks(p.nx, p.ny, p.nz)), dim3(kTileX * kTileY), p.A_q * sizeof(AngleRec), st, ratio,
-                       Fm, x, a);
-    return hipGetLastError();
+template <class Src>
+static hipError_t dispatch_osl(int M, Src src, uint32_t groups, int max_angles, hipStream_t st) {
+    if (max_angles > kMaxSubsetAngles) return hipErrorInvalidValue;
+    switch (M) {
+        case 8: return launch_osl_m<8>(src, groups, max_angles, st);
+        case 16: return launch_osl_m<16>(src, groups, max_angles, st);
+        case 24: return launch_osl_m<24>(src, groups, max_angles, st);
+        case 32: return launch_osl_m<32>(src, groups, max_angles, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_osl(int M, const float* ratio, const float* Fm, float* x, const OslArgs& a, hipStream_t st) {
-    if (a.g.A_q > kMaxSubsetAngles) return hipErrorInvalidValue;
-    switch (M) {
-        case 8: return launch_osl_m<8>(ratio, Fm, x, a, st);
-        case 16: return launch_osl_m<16>(ratio, Fm, x, a, st);
-        case 24: return launch_osl_m<24>(ratio, Fm, x, a, st);
-        case 32: return launch_osl_m<32>(ratio, Fm, x, a, st);
-        default: return hipErrorInvalidValue;
-    }
+    OneJob<OslJob> src{OslJob{a, ratio, Fm, x, 0}};
+    return dispatch_osl(M, src, voxel_tile_groups(a.g.nx, a.g.ny, a.g.nz), a.g.A_q, st);
+}
+
+hipError_t launch_osl_jobs(int M, const OslJob* jobs, int n, uint32_t groups, int max_angles, hipStream_t st) {
+    return dispatch_osl(M, JobTable<OslJob>{jobs, n}, groups, max_angles, st);
 }
 
 }  // namespace kcs

@@ -43,6 +43,93 @@ struct SetupArgs {
     int32_t i0[kMaxFrames], i1[kMaxFrames];
 };
 
+// ---------------------------------------------------------------------------------------------
+// Jobs.  Every kernel processes a list of jobs (one per study); its workgroups are numbered over
+// the concatenated work lists (after the XCD remap) and each finds its job by the first work
+// index w0.  A single-study call passes one job by value; a batched plan passes a device table.
+struct ProjJob {
+    ProjArgs p;
+    const float* x;
+    const float* sino;
+    float* out;
+    float* psum;
+    int32_t slots;
+    uint32_t w0;
+};
+struct OslJob {
+    OslArgs a;
+    const float* ratio;
+    const float* Fm;
+    float* x;
+    uint32_t w0;
+};
+struct BackJob {
+    ProjArgs p;
+    const float* y;
+    float* b;
+    float* sens;
+    uint32_t w0;
+};
+struct LmJob {
+    LmArgs a;
+    const KinTab* K;
+    const float* x;
+    const float* xi_in;
+    float* xi_out;
+    float* lam;
+    uint32_t w0;
+};
+struct ModelJob {
+    FrameTab fr;
+    const KinTab* K;
+    const float* params;
+    int64_t n;
+    float* F;
+    float* J;
+    uint32_t w0;
+};
+struct CopyJob {
+    const float* src;
+    float* dst;
+    int64_t n;
+    uint32_t w0;
+};
+
+template <class J>
+struct OneJob {
+    J job;
+    __device__ __forceinline__ const J& find(uint32_t) const { return job; }
+};
+
+template <class J>
+struct JobTable {
+    const J* jobs;
+    int32_t n;
+    __device__ __forceinline__ const J& find(uint32_t w) const {
+        int k = n - 1;
+        while (k > 0 && jobs[k].w0 > w) --k;
+        return jobs[k];
+    }
+};
+
+// Workgroups each job needs.
+uint32_t proj_direct_groups(const ProjArgs& p);
+uint32_t proj_tile_groups(const ProjArgs& p, int T);
+uint32_t voxel_tile_groups(int nx, int ny, int nz);
+uint32_t lm_groups(int nx, int ny, int nz);
+uint32_t model_groups(int64_t n);
+uint32_t copy_groups(int64_t n);
+
+// Launchers over job tables (device pointer to n jobs covering `groups` workgroups in total).
+hipError_t launch_project_jobs(int M, int T, const ProjJob* jobs, int n, uint32_t groups, int max_angles, bool ratio,
+                               hipStream_t st);
+hipError_t launch_project_reduce_jobs(int M, int T, const ProjJob* jobs, int n, uint32_t groups, bool ratio,
+                                      hipStream_t st);
+hipError_t launch_osl_jobs(int M, const OslJob* jobs, int n, uint32_t groups, int max_angles, hipStream_t st);
+hipError_t launch_lm_jobs(int M, const LmJob* jobs, int n, uint32_t groups, hipStream_t st);
+hipError_t launch_model_jobs(int M, const ModelJob* jobs, int n, uint32_t groups, hipStream_t st);
+hipError_t launch_copy_jobs(const CopyJob* jobs, int n, uint32_t groups, hipStream_t st);
+
 hipError_t launch_setup(const SetupArgs& s, KinTab* K, hipStream_t st);
 hipError_t launch_project(int M, const float* x, const float* sino, float* out, const ProjArgs& p, bool ratio,
                           hipStream_t st);

@@ -128,39 +128,47 @@ __host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, 
     lam_io[v] = accept ? fmaxf(lam * 0.1f, a.lam_min) : fminf(lam * 10.0f, a.lam_max);
 }
 
-template <int M>
-__global__ __launch_bounds__(256) void klm_kernel(const KinTab* __restrict__ K, const float* __restrict__ x,
-                                                  const float* __restrict__ xi_in, float* __restrict__ xi_out,
-                                                  float* __restrict__ lam_io, LmArgs a) {
+uint32_t lm_groups(int nx, int ny, int nz) {
+    return (uint32_t)((nx + kLmTileX - 1) / kLmTileX) * ((ny + kLmTileY - 1) / kLmTileY) * nz;
+}
+
+template <int M, class Src>
+__global__ __launch_bounds__(256) void klm_kernel(Src src) {
     const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
+    const LmJob& J = src.find(w);
+    const LmArgs& a = J.a;
+    const uint32_t lw = w - J.w0;
     const uint32_t tx = (a.nx + kLmTileX - 1) / kLmTileX, ty = (a.ny + kLmTileY - 1) / kLmTileY;
-    const int z = w / (tx * ty);
-    const uint32_t rr = w % (tx * ty);
+    const int z = lw / (tx * ty);
+    const uint32_t rr = lw % (tx * ty);
     const int j = (rr / tx) * kLmTileY + threadIdx.x / kLmTileX;
     const int i = (rr % tx) * kLmTileX + threadIdx.x % kLmTileX;
     if (z >= a.nz || i >= a.nx || j >= a.ny) return;
     __shared__ float sF0[M * kLmTileX * kLmTileY];
-    lm_voxel<M>(K, x, xi_in, xi_out, lam_io, a, i, j, z, sF0 + threadIdx.x, kLmTileX * kLmTileY);
+    lm_voxel<M>(J.K, J.x, J.xi_in, J.xi_out, J.lam, a, i, j, z, sF0 + threadIdx.x, kLmTileX * kLmTileY);
 }
 
-template <int M>
-static hipError_t launch_lm_m(const KinTab* K, const float* x, const float* xi_in, float* xi_out, float* lam,
-                              const LmArgs& a, hipStream_t st) {
-    const uint32_t tx = (a.nx + kLmTileX - 1) / kLmTileX, ty = (a.ny + kLmTileY - 1) / kLmTileY;
-    const uint32_t n = xcd_round_up(tx * ty * (uint32_t)a.nz);
-    hipLaunchKernelGGL((klm_kernel<M>), dim3(n), dim3(kLmTileX * kLmTileY), 0, st, K, x, xi_in, xi_out, lam, a);
+template <class Src>
+static hipError_t dispatch_lm(int M, Src src, uint32_t groups, hipStream_t st) {
+    const dim3 g(xcd_round_up(groups)), b(kLmTileX * kLmTileY);
+    switch (M) {
+        case 8: hipLaunchKernelGGL((klm_kernel<8, Src>), g, b, 0, st, src); break;
+        case 16: hipLaunchKernelGGL((klm_kernel<16, Src>), g, b, 0, st, src); break;
+        case 24: hipLaunchKernelGGL((klm_kernel<24, Src>), g, b, 0, st, src); break;
+        case 32: hipLaunchKernelGGL((klm_kernel<32, Src>), g, b, 0, st, src); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_lm(int M, const KinTab* K, const float* x, const float* xi_in, float* xi_out, float* lam,
                      const LmArgs& a, hipStream_t st) {
-    switch (M) {
-        case 8: return launch_lm_m<8>(K, x, xi_in, xi_out, lam, a, st);
-        case 16: return launch_lm_m<16>(K, x, xi_in, xi_out, lam, a, st);
-        case 24: return launch_lm_m<24>(K, x, xi_in, xi_out, lam, a, st);
-        case 32: return launch_lm_m<32>(K, x, xi_in, xi_out, lam, a, st);
-        default: return hipErrorInvalidValue;
-    }
+    OneJob<LmJob> src{LmJob{a, K, x, xi_in, xi_out, lam, 0}};
+    return dispatch_lm(M, src, lm_groups(a.nx, a.ny, a.nz), st);
+}
+
+hipError_t launch_lm_jobs(int M, const LmJob* jobs, int n, uint32_t groups, hipStream_t st) {
+    return dispatch_lm(M, JobTable<LmJob>{jobs, n}, groups, st);
 }
 
 }  // namespace kcs

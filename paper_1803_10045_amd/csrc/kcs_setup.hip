@@ -33,48 +33,80 @@ hipError_t launch_setup(const SetupArgs& s, KinTab* K, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------------------------
-template <int M, bool JAC>
-__global__ __launch_bounds__(256) void kmodel_kernel(const KinTab* __restrict__ K, FrameTab fr,
-                                                     const float* __restrict__ params, int64_t n, float* __restrict__ F,
-                                                     float* __restrict__ J) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+uint32_t model_groups(int64_t n) { return (uint32_t)((n + 255) / 256); }
+
+template <int M, bool JAC, class Src>
+__global__ __launch_bounds__(256) void kmodel_kernel(Src src) {
+    const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
+    const ModelJob& Jb = src.find(w);
+    const int64_t n = Jb.n;
+    const int64_t v = (int64_t)(w - Jb.w0) * 256 + threadIdx.x;
     if (v >= n) return;
-    float f[M], jac[3 * M];
-    model_frames<M, JAC>(fr, *K, params[v], params[n + v], params[2 * n + v], [&](int m, float Fm, float a, float b, float c) {
-        f[m] = Fm;
-        if (JAC) {
-            jac[3 * m] = a;
-            jac[3 * m + 1] = b;
-            jac[3 * m + 2] = c;
-        }
-    });
-    store_record<M>(F + v * M, f);
+    const float* params = Jb.params;
+    float f[M], jac[JAC ? 3 * M : 1];
+    model_frames<M, JAC>(Jb.fr, *Jb.K, params[v], params[n + v], params[2 * n + v],
+                         [&](int m, float Fm, float a, float b, float c) {
+                             f[m] = Fm;
+                             if (JAC) {
+                                 jac[3 * m] = a;
+                                 jac[3 * m + 1] = b;
+                                 jac[3 * m + 2] = c;
+                             }
+                         });
+    store_record<M>(Jb.F + v * M, f);
     if (JAC) {
 #pragma unroll
-        for (int k = 0; k < 3 * M; ++k) J[v * 3 * M + k] = jac[k];
+        for (int k = 0; k < 3 * M; ++k) Jb.J[v * 3 * M + k] = jac[k];
     }
 }
 
-template <int M>
-static hipError_t launch_model_m(const KinTab* K, const FrameTab& fr, const float* params, int64_t n, float* F, float* J,
-                                 hipStream_t st) {
-    const uint32_t blocks = (uint32_t)((n + 255) / 256);
-    if (J)
-        hipLaunchKernelGGL((kmodel_kernel<M, true>), dim3(blocks), dim3(256), 0, st, K, fr, params, n, F, J);
-    else
-        hipLaunchKernelGGL((kmodel_kernel<M, false>), dim3(blocks), dim3(256), 0, st, K, fr, params, n, F, J);
+template <class Src>
+static hipError_t dispatch_model(int M, bool jac, Src src, uint32_t groups, hipStream_t st) {
+    const dim3 g(xcd_round_up(groups)), b(256);
+#define KCS_MODEL_CASE(MM)                                                                   \
+    case MM:                                                                                 \
+        if (jac)                                                                             \
+            hipLaunchKernelGGL((kmodel_kernel<MM, true, Src>), g, b, 0, st, src);            \
+        else                                                                                 \
+            hipLaunchKernelGGL((kmodel_kernel<MM, false, Src>), g, b, 0, st, src);           \
+        break;
+    switch (M) {
+        KCS_MODEL_CASE(8)
+        KCS_MODEL_CASE(16)
+        KCS_MODEL_CASE(24)
+        KCS_MODEL_CASE(32)
+        default: return hipErrorInvalidValue;
+    }
+#undef KCS_MODEL_CASE
     return hipGetLastError();
 }
 
 hipError_t launch_model(int M, const KinTab* K, const FrameTab& fr, const float* params, int64_t n, float* F, float* J,
                         hipStream_t st) {
-    switch (M) {
-        case 8: return launch_model_m<8>(K, fr, params, n, F, J, st);
-        case 16: return launch_model_m<16>(K, fr, params, n, F, J, st);
-        case 24: return launch_model_m<24>(K, fr, params, n, F, J, st);
-        case 32: return launch_model_m<32>(K, fr, params, n, F, J, st);
-        default: return hipErrorInvalidValue;
+    OneJob<ModelJob> src{ModelJob{fr, K, params, n, F, J, 0}};
+    return dispatch_model(M, J != nullptr, src, model_groups(n), st);
+}
+
+hipError_t launch_model_jobs(int M, const ModelJob* jobs, int n, uint32_t groups, hipStream_t st) {
+    return dispatch_model(M, false, JobTable<ModelJob>{jobs, n}, groups, st);
+}
+
+// Batched device-to-device copies (the kinetic maps before an odd number of LM iterations).
+uint32_t copy_groups(int64_t n) { return (uint32_t)((n + 1023) / 1024); }
+
+__global__ __launch_bounds__(256) void kcopy_kernel(JobTable<CopyJob> src) {
+    const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
+    const CopyJob& J = src.find(w);
+    const int64_t base = (int64_t)(w - J.w0) * 1024 + threadIdx.x;
+    for (int k = 0; k < 4; ++k) {
+        const int64_t e = base + k * 256;
+        if (e < J.n) J.dst[e] = J.src[e];
     }
+}
+
+hipError_t launch_copy_jobs(const CopyJob* jobs, int n, uint32_t groups, hipStream_t st) {
+    hipLaunchKernelGGL(kcopy_kernel, dim3(xcd_round_up(groups)), dim3(256), 0, st, JobTable<CopyJob>{jobs, n});
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------------
