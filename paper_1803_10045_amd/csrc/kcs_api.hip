@@ -98,6 +98,8 @@ int check_subset(const kcs_geometry* g, int32_t q, int32_t Q) {
     if (Q < 1 || Q > g->n_ang) return fail(KCS_EINVAL, "need 1 <= Q <= n_ang");
     if (q < 0 || q >= Q) return fail(KCS_EINVAL, "need 0 <= q < Q");
     if ((g->n_ang + Q - 1) / Q > 1024) return fail(KCS_ESHAPE, "more than 1024 angles in a subset");
+    if (!staged_fits(kMaxFrames, (float)g->pixel_mm, (float)g->bin_mm))
+        return fail(KCS_ESHAPE, "bins more than 16 times narrower than pixels are not supported");
     return KCS_OK;
 }
 
@@ -266,8 +268,7 @@ int projector_tile(const kcs_geometry& g, int M) {
         if (t == 0 || t == 16 || (t == 32 && M <= 24)) return t;
     }
     const double plane_bytes = (double)g.nx * g.ny * M * 4.0;
-    if (plane_bytes < 2.0 * 1024 * 1024) return 0;
-    return M <= 24 ? 32 : 16;
+    return plane_bytes < 2.0 * 1024 * 1024 ? 0 : 16;
 }
 
 // Offsets of the workspace regions.  The model TACs of the maps and the ratio buffer (the

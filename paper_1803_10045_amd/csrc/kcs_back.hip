@@ -4,7 +4,9 @@
 // covers at most ceil(2 w1 / du) + 1 bins; the exact intersection length of each bin's ray with
 // the voxel square (the pixel chord, identical to the Siddon length of that ray in that pixel)
 // weights the bin's M-frame record.  The gather needs no atomics and no transposed system
-// matrix; the subset's angle constants are built once per workgroup in LDS.
+// matrix.  A workgroup covers a 16 x 16 voxel tile: for a chunk of the subset's angles it stages
+// in LDS the records of every bin whose ray can meet the tile (at most tile_slots(16) per
+// angle), then each voxel gathers from LDS.
 //
 // OSL update (Eq. 2 with the kinetics-derived potential of Eq. 3, sigma^2 = F / n):
 //   x_new = x * b / D,  b = E_m sum_d p_vd q_dm,  D = n_m (1 + beta (x - F) / max(F, eps_F)),
@@ -84,24 +86,22 @@ __host__ __device__ __forceinline__ void backproject_voxel(const AngleRec* sA, c
 // OSL-KP update of voxel (i, j, z).  Fm: model TACs of the current maps [N][M] (only read when
 // the prior is on).
 template <int M>
-__host__ __device__ __forceinline__ void osl_voxel(const AngleRec* sA, const OslArgs& a, const float* __restrict__ ratio,
-                                                   const float* __restrict__ Fm, float* __restrict__ x, int i, int j,
-                                                   int z) {
-    const ProjArgs& p = a.g;
-    float acc[M], sens;
-    gather<M>(sA, p, ratio, i, j, z, acc, sens);
+__host__ __device__ __forceinline__ void osl_finish(const OslArgs& a, const float* __restrict__ Fm,
+                                                    float* __restrict__ x, size_t v, const float (&acc)[M],
+                                                    float sens) {
     if (!(sens > 0.0f)) return;  // no ray of this subset sees the voxel: keep x
-    const size_t v = ((size_t)z * p.ny + j) * p.nx + i;
     float xv[M];
     load_record<M>(x + v * M, xv);
     const float inv_sens = 1.0f / sens;
     if (a.kp) {
+        // x b / (n (1 + beta (x - F) / Fe)) = x (acc / sens) Fe / (Fe + beta (x - F)),  Fe = max(F, eps_F)
         float F[M];
         load_record<M>(Fm + v * M, F);
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            const float d = fmaf(a.beta_kp, (xv[m] - F[m]) / fmaxf(F[m], a.eps_F), 1.0f);
-            xv[m] = xv[m] * acc[m] * inv_sens / d;
+            const float fe = fmaxf(F[m], a.eps_F);
+            const float den = fmaf(a.beta_kp, xv[m] - F[m], fe);
+            xv[m] = fast_div(xv[m] * acc[m] * inv_sens * fe, den);
         }
     } else {
 #pragma unroll
@@ -110,46 +110,165 @@ __host__ __device__ __forceinline__ void osl_voxel(const AngleRec* sA, const Osl
     store_record<M>(x + v * M, xv);
 }
 
+template <int M>
+__host__ __device__ __forceinline__ void osl_voxel(const AngleRec* sA, const OslArgs& a, const float* __restrict__ ratio,
+                                                   const float* __restrict__ Fm, float* __restrict__ x, int i, int j,
+                                                   int z) {
+    const ProjArgs& p = a.g;
+    float acc[M], sens;
+    gather<M>(sA, p, ratio, i, j, z, acc, sens);
+    osl_finish<M>(a, Fm, x, ((size_t)z * p.ny + j) * p.nx + i, acc, sens);
+}
+
+constexpr int kST = 16;               // staged voxel tile: kST x kST voxels, one per thread
+constexpr int kStageBytes = 40 * 1024;  // LDS for the staged bin records of one angle chunk
+
+bool staged_fits(int M, float h, float du) { return tile_slots(kST, h, du) * M * (int)sizeof(float) <= kStageBytes; }
+
+uint32_t staged_tile_groups(int nx, int ny, int nz) {
+    return (uint32_t)(((nx + kST - 1) / kST) * ((ny + kST - 1) / kST)) * nz;
+}
+
+// Angles per staging chunk for this geometry.
+__host__ __device__ inline int stage_chunk(int M, int slots, int A_q) {
+    const int c = kStageBytes / (slots * M * (int)sizeof(float));
+    return max(1, min(c, A_q));
+}
+
+// acc_m = sum_{d in S_q} p_vd y_dm and sens for the voxel of this thread in the staged tile
+// (i0, j0) of plane z; all threads of the workgroup must call it (it synchronises).
+template <int M>
+__device__ __forceinline__ void staged_gather(const AngleRec* sA, float4* sR, const ProjArgs& p,
+                                              const float* __restrict__ y, int i0, int j0, int z, bool valid, int i,
+                                              int j, float (&acc)[M], float& sens) {
+    const int tw = min(kST, p.nx - i0), th = min(kST, p.ny - j0);
+    const int slots = tile_slots(kST, p.h, p.du);
+    const int chunk = stage_chunk(M, slots, p.A_q);
+    const float xc = ((float)i - 0.5f * (float)(p.nx - 1)) * p.h;
+    const float yc = ((float)j - 0.5f * (float)(p.ny - 1)) * p.h;
+#pragma unroll
+    for (int m = 0; m < M; ++m) acc[m] = 0.0f;
+    sens = 0.0f;
+    const float4* yz = reinterpret_cast<const float4*>(y) + (size_t)z * p.A_q * p.n_bin * (M / 4);
+    for (int c0 = 0; c0 < p.A_q; c0 += chunk) {
+        const int na = min(chunk, p.A_q - c0);
+        __syncthreads();  // previous chunk consumed
+        for (int e = threadIdx.x; e < na * slots * (M / 4); e += blockDim.x) {
+            const int k = e % (M / 4), rec = e / (M / 4), al = c0 + rec / slots, slot = rec % slots;
+            int b0, b1;
+            box_bins(sA[al], i0, j0, tw, th, p.nx, p.ny, p.h, p.inv_du, p.n_bin, b0, b1);
+            const int b = b0 + slot;
+            if (b <= b1) sR[e] = yz[((size_t)al * p.n_bin + b) * (M / 4) + k];
+        }
+        __syncthreads();
+        if (!valid) continue;
+        for (int ac = 0; ac < na; ++ac) {
+            const int al = c0 + ac;
+            const AngleRec A = sA[al];
+            int b0, b1;
+            box_bins(A, i0, j0, tw, th, p.nx, p.ny, p.h, p.inv_du, p.n_bin, b0, b1);
+            const float* ra = reinterpret_cast<const float*>(sR) + (size_t)ac * slots * M;
+            pixel_footprint(A, xc, yc, p.n_bin, p.du, p.inv_du, [&](int b, float len) {
+                if (b < b0 || b > b1) return;  // cannot happen: box_bins is a superset
+                float v[M];
+                load_record<M>(ra + (b - b0) * M, v);
+#pragma unroll
+                for (int m = 0; m < M; ++m) acc[m] = fmaf(len, v[m], acc[m]);
+                sens += len;
+            });
+        }
+    }
+}
+
+struct StagedTile {
+    int i0, j0, z, i, j;
+    bool valid;
+};
+
+__device__ __forceinline__ StagedTile staged_tile(uint32_t w, int nx, int ny, int nz) {
+    const int ntx = (nx + kST - 1) / kST, nty = (ny + kST - 1) / kST;
+    StagedTile t;
+    t.z = w / (ntx * nty);
+    const int r = w % (ntx * nty);
+    t.j0 = (r / ntx) * kST;
+    t.i0 = (r % ntx) * kST;
+    t.i = t.i0 + (int)(threadIdx.x % kST);
+    t.j = t.j0 + (int)(threadIdx.x / kST);
+    t.valid = t.z < nz && t.i < nx && t.j < ny;
+    return t;
+}
+
 template <int M, class Src>
 __global__ __launch_bounds__(256) void kback_kernel(Src src) {
-    extern __shared__ AngleRec sA[];
+    extern __shared__ float4 lds[];
     const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
     const BackJob& J = src.find(w);
-    subset_angles_to_lds(sA, J.p);
-    const TileIdx t = tile_voxel(w - J.w0, J.p.nx, J.p.ny, J.p.nz);
+    const ProjArgs& p = J.p;
+    const StagedTile t = staged_tile(w - J.w0, p.nx, p.ny, p.nz);
+    if (t.z >= p.nz) return;  // whole workgroup
+    AngleRec* sA = reinterpret_cast<AngleRec*>(lds);
+    float4* sR = lds + (p.A_q * sizeof(AngleRec) + 15) / 16;
+    subset_angles_to_lds(sA, p);
+    float acc[M], sens;
+    staged_gather<M>(sA, sR, p, J.y, t.i0, t.j0, t.z, t.valid, t.i, t.j, acc, sens);
     if (!t.valid) return;
-    backproject_voxel<M>(sA, J.p, J.y, J.b, J.sens, t.i, t.j, t.z);
+    const size_t v = ((size_t)t.z * p.ny + t.j) * p.nx + t.i;
+#pragma unroll
+    for (int m = 0; m < M; ++m) acc[m] *= p.fr.E[m];
+    store_record<M>(J.b + v * M, acc);
+    if (J.sens) J.sens[v] = sens;
 }
 
 template <int M, class Src>
 __global__ __launch_bounds__(256) void kosl_kernel(Src src) {
-    extern __shared__ AngleRec sA[];
+    extern __shared__ float4 lds[];
     const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
     const OslJob& J = src.find(w);
-    subset_angles_to_lds(sA, J.a.g);
-    const TileIdx t = tile_voxel(w - J.w0, J.a.g.nx, J.a.g.ny, J.a.g.nz);
+    const OslArgs& a = J.a;
+    const ProjArgs& p = a.g;
+    const StagedTile t = staged_tile(w - J.w0, p.nx, p.ny, p.nz);
+    if (t.z >= p.nz) return;  // whole workgroup
+    AngleRec* sA = reinterpret_cast<AngleRec*>(lds);
+    float4* sR = lds + (p.A_q * sizeof(AngleRec) + 15) / 16;
+    subset_angles_to_lds(sA, p);
+    float acc[M], sens;
+    staged_gather<M>(sA, sR, p, J.ratio, t.i0, t.j0, t.z, t.valid, t.i, t.j, acc, sens);
     if (!t.valid) return;
-    osl_voxel<M>(sA, J.a, J.ratio, J.Fm, J.x, t.i, t.j, t.z);
+    osl_finish<M>(a, J.Fm, J.x, ((size_t)t.z * p.ny + t.j) * p.nx + t.i, acc, sens);
+}
+
+static size_t staged_lds_bytes(int max_angles) {
+    return (max_angles * sizeof(AngleRec) + 15) / 16 * 16 + kStageBytes;
+}
+
+template <class K>
+static void allow_large_lds(K kernel) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
 }
 
 template <int M, class Src>
 static hipError_t launch_back_m(Src src, uint32_t groups, int max_angles, hipStream_t st) {
-    hipLaunchKernelGGL((kback_kernel<M, Src>), dim3(xcd_round_up(groups)), dim3(kTileX * kTileY),
-                       max_angles * sizeof(AngleRec), st, src);
+    static bool once = (allow_large_lds(&kback_kernel<M, Src>), true);
+    (void)once;
+    hipLaunchKernelGGL((kback_kernel<M, Src>), dim3(xcd_round_up(groups)), dim3(kST * kST),
+                       staged_lds_bytes(max_angles), st, src);
     return hipGetLastError();
 }
 
 template <int M, class Src>
 static hipError_t launch_osl_m(Src src, uint32_t groups, int max_angles, hipStream_t st) {
-    hipLaunchKernelGGL((kosl_kernel<M, Src>), dim3(xcd_round_up(groups)), dim3(kTileX * kTileY),
-                       max_angles * sizeof(AngleRec), st, src);
+    static bool once = (allow_large_lds(&kosl_kernel<M, Src>), true);
+    (void)once;
+    hipLaunchKernelGGL((kosl_kernel<M, Src>), dim3(xcd_round_up(groups)), dim3(kST * kST),
+                       staged_lds_bytes(max_angles), st, src);
     return hipGetLastError();
 }
 
 hipError_t launch_backproject(int M, const float* y, float* b, float* sens, const ProjArgs& p, hipStream_t st) {
     if (p.A_q > kMaxSubsetAngles) return hipErrorInvalidValue;
     OneJob<BackJob> src{BackJob{p, y, b, sens, 0}};
-    const uint32_t g = voxel_tile_groups(p.nx, p.ny, p.nz);
+    const uint32_t g = staged_tile_groups(p.nx, p.ny, p.nz);
     switch (M) {
         case 8: return launch_back_m<8>(src, g, p.A_q, st);
         case 16: return launch_back_m<16>(src, g, p.A_q, st);
@@ -173,7 +292,7 @@ static hipError_t dispatch_osl(int M, Src src, uint32_t groups, int max_angles, 
 
 hipError_t launch_osl(int M, const float* ratio, const float* Fm, float* x, const OslArgs& a, hipStream_t st) {
     OneJob<OslJob> src{OslJob{a, ratio, Fm, x, 0}};
-    return dispatch_osl(M, src, voxel_tile_groups(a.g.nx, a.g.ny, a.g.nz), a.g.A_q, st);
+    return dispatch_osl(M, src, staged_tile_groups(a.g.nx, a.g.ny, a.g.nz), a.g.A_q, st);
 }
 
 hipError_t launch_osl_jobs(int M, const OslJob* jobs, int n, uint32_t groups, int max_angles, hipStream_t st) {

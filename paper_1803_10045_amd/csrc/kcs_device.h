@@ -65,6 +65,15 @@ __host__ __device__ inline AngleRec make_angle(int a, int n_ang, double ang0, fl
     return A;
 }
 
+// a / b with one reciprocal (about 2 ulp): ratios in the update steps.
+__host__ __device__ __forceinline__ float fast_div(float a, float b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __fdividef(a, b);
+#else
+    return a / b;
+#endif
+}
+
 // Chord of a ray through a pixel square: the exact intersection length as a function of the
 // signed distance t between the ray and the pixel centre, measured along the detector.
 __host__ __device__ __forceinline__ float pixel_chord(const AngleRec& A, float t) {
@@ -157,6 +166,12 @@ __host__ __device__ __forceinline__ void siddon_traverse(const AngleRec& A, floa
     const float Xc = u * A.c * inv_h + 0.5f * (float)nx;
     const float Yc = u * A.s * inv_h + 0.5f * (float)ny;
     siddon_traverse_box(A, Xc, Yc, nx, ny, h, visit);
+}
+
+// Slots reserved per (tile, angle) for the bins whose rays can meet a T x T pixel tile:
+// b1 - b0 <= T h sqrt(2) / du + 0.02 for every angle (see box_bins).
+__host__ __device__ inline int tile_slots(int T, float h, float du) {
+    return (int)floorf((float)T * h * 1.41421357f / du) + 3;
 }
 
 // Bins whose rays can meet the pixel box [i0, i0+w) x [j0, j0+hgt) of an nx x ny grid: the

@@ -116,6 +116,8 @@ struct JobTable {
 uint32_t proj_direct_groups(const ProjArgs& p);
 uint32_t proj_tile_groups(const ProjArgs& p, int T);
 uint32_t voxel_tile_groups(int nx, int ny, int nz);
+uint32_t staged_tile_groups(int nx, int ny, int nz);
+bool staged_fits(int M, float h, float du);  // one angle's staged bin records fit in the LDS
 uint32_t lm_groups(int nx, int ny, int nz);
 uint32_t model_groups(int64_t n);
 uint32_t copy_groups(int64_t n);

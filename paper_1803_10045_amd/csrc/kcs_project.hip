@@ -81,11 +81,6 @@ __global__ __launch_bounds__(256) void kproj_kernel(Src src) {
     project_ray<M, RATIO>(p, J.x, J.sino, J.out, z, al, ray - al * p.n_bin);
 }
 
-// Slots reserved per (tile, angle) for the rays that can meet a T x T tile.
-__host__ __device__ inline int tile_slots(int T, float h, float du) {
-    return (int)floorf((float)T * h * 1.41421357f / du) + 3;
-}
-
 uint32_t proj_tile_groups(const ProjArgs& p, int T) {
     return (uint32_t)(((p.nx + T - 1) / T) * ((p.ny + T - 1) / T)) * p.nz;
 }
