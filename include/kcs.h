@@ -152,6 +152,56 @@ int kcs_icm_sweep(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics
                   const kcs_lm_opts* lm, const float* d_sino, int32_t Q, int32_t sweep_idx, float* d_x,
                   float* d_params, float* d_lambda, void* d_work, size_t work_bytes, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------------------------
+ * Batched execution.  A plan runs ICM sweeps of many independent studies (uneven sizes, subset
+ * counts and schedules) together: every phase of a sweep (model pass, forward projection,
+ * OSL update of subset slot q, map copy, MAP-LM iteration i) is one kernel launch over the
+ * concatenated work lists of all studies that take part in it, so small studies fill the GPU
+ * together.  Studies are independent: each result equals the single-study calls on the same
+ * study up to the projector variant chosen for it (rounding-level differences).
+ *
+ * kcs_study holds one study's arguments as for kcs_icm_sweep: sweeps sweep_begin..sweep_end-1
+ * are run (sweep 0 has the kinetics-derived prior off); d_work is that study's own workspace of
+ * kcs_workspace_bytes(&g, M, Q) bytes.  Host arrays in f are only read by kcs_plan_create.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct kcs_study {
+    kcs_geometry g;
+    kcs_frames f;
+    kcs_kinetics k;
+    kcs_prior p;
+    kcs_lm_opts lm;
+    int32_t Q, sweep_begin, sweep_end;
+    const float* d_sino;
+    float* d_x;
+    float* d_params;
+    float* d_lambda;
+    void* d_work;
+    size_t work_bytes;
+} kcs_study;
+
+typedef struct kcs_plan kcs_plan;
+
+enum {
+    KCS_PLAN_GRAPH = 1,   /* capture the whole schedule in one HIP graph; kcs_plan_run launches it */
+    KCS_PLAN_AUTOTUNE = 2 /* time the projector variants (ray-driven, 16 or 32 pixel tiles) per shape
+                             class on these studies and keep the fastest; results are cached in the
+                             file named by KCS_TUNE_CACHE when that variable is set */
+};
+
+/* Validates every study, builds the per-study constant tables (on `stream`, in each workspace) and
+ * the job tables (library-owned device memory), optionally autotunes and captures, then waits for
+ * `stream`.  The studies' device buffers must stay valid until kcs_plan_destroy. */
+int kcs_plan_create(const kcs_study* studies, int32_t n, int32_t flags, hipStream_t stream, kcs_plan** out);
+
+/* Enqueues the whole schedule of the plan on `stream` (asynchronous). */
+int kcs_plan_run(kcs_plan* plan, hipStream_t stream);
+
+/* Writes a one-line summary (studies, launches, graph, projector variant per study) into buf. */
+int kcs_plan_describe(const kcs_plan* plan, char* buf, size_t len);
+
+/* Frees the plan's device memory and graph.  NULL is ignored. */
+void kcs_plan_destroy(kcs_plan* plan);
+
 /* Kernel timing for measurement harnesses.  While enabled, every kernel or copy the library
  * launches is bracketed by a pair of HIP events recorded on the call's stream (the events are
  * created by the library and reused).  kcs_timing_collect waits for the recorded events, adds

@@ -1,13 +1,16 @@
 // Host side of libkcs: argument validation, FP64 constants, workspace layout and the C ABI.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <string>
 #include <vector>
 
+#include "kcs_device.h"
 #include "kcs_launch.h"
 
 namespace kcs {
@@ -441,10 +444,343 @@ int do_lm(const kcs_geometry& g, const Schedule& S, const kcs_prior& p, const kc
     return KCS_OK;
 }
 
+
+// ---------------------------------------------------------------------------------------------
+// Batched plans
+
+enum PhaseKind { PH_MODEL, PH_PROJ, PH_REDUCE, PH_OSL, PH_COPY, PH_LM };
+
+struct PlanPhase {
+    int kind, M, T;
+    size_t off;  // byte offset of the job table in the plan's device buffer
+    int n;       // jobs
+    uint32_t groups;
+    int max_angles;
+};
+
+struct StudyPrep {
+    const kcs_study* s;
+    Schedule S;
+    Layout L;
+    int T;  // forward projector variant
+};
+
+// Host image of the job tables: phases append their jobs (w0 = running work index).
+struct TableBuilder {
+    std::vector<char> buf;
+    std::vector<PlanPhase> phases;
+
+    template <class Job>
+    void add(int kind, int M, int T, std::vector<Job>& jobs, const std::vector<uint32_t>& groups, int max_angles) {
+        if (jobs.empty()) return;
+        uint32_t w = 0;
+        for (size_t k = 0; k < jobs.size(); ++k) {
+            jobs[k].w0 = w;
+            w += groups[k];
+        }
+        const size_t off = align_up(buf.size(), 256);
+        buf.resize(off + jobs.size() * sizeof(Job));
+        memcpy(buf.data() + off, jobs.data(), jobs.size() * sizeof(Job));
+        phases.push_back(PlanPhase{kind, M, T, off, (int)jobs.size(), w, max_angles});
+    }
+};
+
+int check_study(const kcs_study& st) {
+    KCS_TRY(check_geometry(&st.g));
+    KCS_TRY(check_frames(&st.f));
+    KCS_TRY(check_kinetics(&st.k));
+    KCS_TRY(check_prior(&st.p));
+    KCS_TRY(check_lm(&st.lm));
+    KCS_TRY(check_subset(&st.g, 0, st.Q));
+    if (st.sweep_begin < 0 || st.sweep_end < st.sweep_begin) return fail(KCS_EINVAL, "need 0 <= sweep_begin <= sweep_end");
+    if (!st.d_sino || !st.d_x || !st.d_params || !st.d_lambda) return fail(KCS_EINVAL, "study pointers must not be NULL");
+    return check_work(&st.g, st.f.n_frames, st.Q, st.d_work, st.work_bytes);
+}
+
+ProjJob proj_job(const StudyPrep& P, int q) {
+    const kcs_study& s = *P.s;
+    ProjJob j{};
+    j.p = proj_args(s.g, P.S.fr, q, s.Q);
+    j.x = s.d_x;
+    j.sino = s.d_sino;
+    j.out = at<float>(s.d_work, P.L.ratio);
+    j.psum = at<float>(s.d_work, P.L.psum);
+    j.slots = P.T ? tile_slots(P.T, j.p.h, j.p.du) : 0;
+    return j;
+}
+
+LmArgs lm_args(const StudyPrep& P) {
+    const kcs_study& s = *P.s;
+    LmArgs a{};
+    a.nx = s.g.nx;
+    a.ny = s.g.ny;
+    a.nz = s.g.nz;
+    a.fr = P.S.fr;
+    a.beta_h = (float)s.p.beta_h;
+    for (int i = 0; i < 3; ++i) {
+        a.delta[i] = (float)s.p.delta[i];
+        a.lo[i] = (float)s.lm.lo[i];
+        a.hi[i] = (float)s.lm.hi[i];
+    }
+    a.tau = (float)s.lm.tau;
+    a.eta = (float)s.lm.eta;
+    a.lam_min = (float)s.lm.lam_min;
+    a.lam_max = (float)s.lm.lam_max;
+    return a;
+}
+
+// Forward projections of subset slot q for the studies in `ps` (grouped by frame count and
+// projector variant): tile step and reduce step for tiled studies, one launch otherwise.
+void add_projection(TableBuilder& tb, const std::vector<const StudyPrep*>& ps, int q) {
+    std::vector<std::pair<int, int>> keys;
+    for (const StudyPrep* P : ps)
+        if (std::find(keys.begin(), keys.end(), std::make_pair(P->S.fr.M, P->T)) == keys.end())
+            keys.push_back({P->S.fr.M, P->T});
+    for (const auto& key : keys) {
+        std::vector<ProjJob> jobs, red;
+        std::vector<uint32_t> g, gr;
+        int max_a = 1;
+        for (const StudyPrep* P : ps) {
+            if (P->S.fr.M != key.first || P->T != key.second) continue;
+            ProjJob j = proj_job(*P, q);
+            max_a = std::max(max_a, (int)j.p.A_q);
+            jobs.push_back(j);
+            g.push_back(key.second ? proj_tile_groups(j.p, key.second) : proj_direct_groups(j.p));
+            red.push_back(j);
+            gr.push_back(proj_direct_groups(j.p));
+        }
+        tb.add(PH_PROJ, key.first, key.second, jobs, g, max_a);
+        if (key.second) tb.add(PH_REDUCE, key.first, key.second, red, gr, max_a);
+    }
+}
+
+std::vector<int> frame_counts(const std::vector<const StudyPrep*>& ps) {
+    std::vector<int> Ms;
+    for (const StudyPrep* P : ps)
+        if (std::find(Ms.begin(), Ms.end(), P->S.fr.M) == Ms.end()) Ms.push_back(P->S.fr.M);
+    return Ms;
+}
+
+void build_schedule(TableBuilder& tb, std::vector<StudyPrep>& preps) {
+    int s0 = INT32_MAX, s1 = 0;
+    for (const StudyPrep& P : preps) {
+        if (P.s->sweep_end <= P.s->sweep_begin) continue;
+        s0 = std::min(s0, P.s->sweep_begin);
+        s1 = std::max(s1, P.s->sweep_end);
+    }
+    for (int sw = s0; sw < s1; ++sw) {
+        std::vector<const StudyPrep*> act;
+        for (const StudyPrep& P : preps)
+            if (sw >= P.s->sweep_begin && sw < P.s->sweep_end) act.push_back(&P);
+        // model TACs of the maps for the studies whose prior is on in this sweep
+        for (int M : frame_counts(act)) {
+            std::vector<ModelJob> jobs;
+            std::vector<uint32_t> g;
+            for (const StudyPrep* P : act) {
+                if (P->S.fr.M != M || !(P->s->p.kp_on && sw > 0)) continue;
+                const kcs_study& s = *P->s;
+                const int64_t N = (int64_t)s.g.nx * s.g.ny * s.g.nz;
+                jobs.push_back(ModelJob{P->S.fr, at<KinTab>(s.d_work, P->L.kin), s.d_params, N,
+                                        at<float>(s.d_work, P->L.F), nullptr, 0});
+                g.push_back(model_groups(N));
+            }
+            tb.add(PH_MODEL, M, 0, jobs, g, 0);
+        }
+        int qmax = 0;
+        for (const StudyPrep* P : act) qmax = std::max(qmax, (int)P->s->Q);
+        for (int q = 0; q < qmax; ++q) {
+            std::vector<const StudyPrep*> sub;
+            for (const StudyPrep* P : act)
+                if (q < P->s->Q) sub.push_back(P);
+            add_projection(tb, sub, q);
+            for (int M : frame_counts(sub)) {
+                std::vector<OslJob> jobs;
+                std::vector<uint32_t> g;
+                int max_a = 1;
+                for (const StudyPrep* P : sub) {
+                    if (P->S.fr.M != M) continue;
+                    const kcs_study& s = *P->s;
+                    OslJob j{};
+                    j.a.g = proj_args(s.g, P->S.fr, q, s.Q);
+                    j.a.beta_kp = (float)s.p.beta_kp;
+                    j.a.eps_F = (float)s.p.eps_F;
+                    j.a.kp = (s.p.kp_on && sw > 0) ? 1 : 0;
+                    j.ratio = at<float>(s.d_work, P->L.ratio);
+                    j.Fm = at<float>(s.d_work, P->L.F);
+                    j.x = s.d_x;
+                    max_a = std::max(max_a, (int)j.a.g.A_q);
+                    jobs.push_back(j);
+                    g.push_back(staged_tile_groups(s.g.nx, s.g.ny, s.g.nz));
+                }
+                tb.add(PH_OSL, M, 0, jobs, g, max_a);
+            }
+        }
+        // MAP-LM: maps ping-pong between d_params and the workspace so the last iteration writes
+        // d_params; an odd iteration count starts with a copy
+        std::vector<CopyJob> cj;
+        std::vector<uint32_t> cg;
+        int itmax = 0;
+        for (const StudyPrep* P : act) {
+            itmax = std::max(itmax, (int)P->s->lm.n_iter);
+            if (P->s->lm.n_iter % 2 == 1) {
+                const kcs_study& s = *P->s;
+                const int64_t n3 = 3LL * s.g.nx * s.g.ny * s.g.nz;
+                cj.push_back(CopyJob{s.d_params, at<float>(s.d_work, P->L.xi), n3, 0});
+                cg.push_back(copy_groups(n3));
+            }
+        }
+        tb.add(PH_COPY, 0, 0, cj, cg, 0);
+        for (int it = 0; it < itmax; ++it) {
+            for (int M : frame_counts(act)) {
+                std::vector<LmJob> jobs;
+                std::vector<uint32_t> g;
+                for (const StudyPrep* P : act) {
+                    const kcs_study& s = *P->s;
+                    if (P->S.fr.M != M || it >= s.lm.n_iter) continue;
+                    float* other = at<float>(s.d_work, P->L.xi);
+                    const bool odd = s.lm.n_iter % 2 == 1;
+                    const bool even_it = it % 2 == 0;
+                    // odd count: it0 other->params, it1 params->other, ...; even: params->other first
+                    const float* src = (odd == even_it) ? other : s.d_params;
+                    float* dst = (odd == even_it) ? s.d_params : other;
+                    LmArgs a = lm_args(*P);
+                    a.reset_lambda = it == 0 ? 1 : 0;
+                    jobs.push_back(LmJob{a, at<KinTab>(s.d_work, P->L.kin), s.d_x, src, dst, s.d_lambda, 0});
+                    g.push_back(lm_groups(s.g.nx, s.g.ny, s.g.nz));
+                }
+                tb.add(PH_LM, M, 0, jobs, g, 0);
+            }
+        }
+    }
+}
+
+hipError_t run_phase(const PlanPhase& ph, const char* base, hipStream_t st) {
+    const void* t = base + ph.off;
+    switch (ph.kind) {
+        case PH_MODEL: return launch_model_jobs(ph.M, (const ModelJob*)t, ph.n, ph.groups, st);
+        case PH_PROJ:
+            return launch_project_jobs(ph.M, ph.T, (const ProjJob*)t, ph.n, ph.groups, ph.max_angles, true, st);
+        case PH_REDUCE: return launch_project_reduce_jobs(ph.M, ph.T, (const ProjJob*)t, ph.n, ph.groups, true, st);
+        case PH_OSL: return launch_osl_jobs(ph.M, (const OslJob*)t, ph.n, ph.groups, ph.max_angles, st);
+        case PH_COPY: return launch_copy_jobs((const CopyJob*)t, ph.n, ph.groups, st);
+        case PH_LM: return launch_lm_jobs(ph.M, (const LmJob*)t, ph.n, ph.groups, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ----- projector autotuning: time each variant on the studies of one shape class -----
+struct TuneKey {
+    int nx, ny, n_bin, A_q, M;
+    float hdu;
+    bool operator==(const TuneKey& o) const {
+        return nx == o.nx && ny == o.ny && n_bin == o.n_bin && A_q == o.A_q && M == o.M && hdu == o.hdu;
+    }
+};
+
+std::mutex g_tune_mu;
+
+int cached_tile(const TuneKey& k) {
+    const char* path = getenv("KCS_TUNE_CACHE");
+    if (!path) return -1;
+    FILE* f = fopen(path, "r");
+    if (!f) return -1;
+    int nx, ny, nb, aq, M, T;
+    float hdu, ms;
+    int found = -1;
+    while (fscanf(f, "%d %d %d %d %d %f %d %f", &nx, &ny, &nb, &aq, &M, &hdu, &T, &ms) == 8)
+        if (TuneKey{nx, ny, nb, aq, M, hdu} == k) found = T;
+    fclose(f);
+    return found;
+}
+
+void store_tile(const TuneKey& k, int T, float ms) {
+    const char* path = getenv("KCS_TUNE_CACHE");
+    if (!path) return;
+    if (FILE* f = fopen(path, "a")) {
+        fprintf(f, "%d %d %d %d %d %.6g %d %.6g\n", k.nx, k.ny, k.n_bin, k.A_q, k.M, k.hdu, T, ms);
+        fclose(f);
+    }
+}
+
+int autotune(std::vector<StudyPrep>& preps, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::vector<TuneKey> keys;
+    for (const StudyPrep& P : preps) {
+        const kcs_study& s = *P.s;
+        TuneKey k{s.g.nx, s.g.ny, s.g.n_bin, subset_size(s.g, 0, s.Q), s.f.n_frames,
+                  (float)(s.g.pixel_mm / s.g.bin_mm)};
+        if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
+    }
+    void* dtab = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(KCS_EHIP, "tuning events");
+    int rc = KCS_OK;
+    for (const TuneKey& k : keys) {
+        std::vector<StudyPrep*> cls;
+        for (StudyPrep& P : preps) {
+            const kcs_study& s = *P.s;
+            if (TuneKey{s.g.nx, s.g.ny, s.g.n_bin, subset_size(s.g, 0, s.Q), s.f.n_frames,
+                        (float)(s.g.pixel_mm / s.g.bin_mm)} == k)
+                cls.push_back(&P);
+        }
+        int best = cached_tile(k);
+        if (best < 0) {
+            float best_ms = 1e30f;
+            for (int T : {0, 16, 32}) {
+                if (T == 32 && k.M > 24) continue;
+                for (StudyPrep* P : cls) P->T = T;
+                TableBuilder tb;
+                std::vector<const StudyPrep*> ps(cls.begin(), cls.end());
+                add_projection(tb, ps, 0);
+                if (hipMalloc(&dtab, std::max<size_t>(tb.buf.size(), 256)) != hipSuccess) {
+                    rc = fail(KCS_EHIP, "tuning table");
+                    break;
+                }
+                hipError_t e = hipMemcpy(dtab, tb.buf.data(), tb.buf.size(), hipMemcpyHostToDevice);
+                float ms = 0.0f;
+                for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {  // rep 0 warms up
+                    if (rep == 1) e = hipEventRecord(e0, st);
+                    for (const PlanPhase& ph : tb.phases)
+                        if (e == hipSuccess) e = run_phase(ph, (const char*)dtab, st);
+                }
+                if (e == hipSuccess) e = hipEventRecord(e1, st);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                (void)hipFree(dtab);
+                dtab = nullptr;
+                if (e != hipSuccess) {
+                    rc = hip_fail(e, "projector tuning");
+                    break;
+                }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = T;
+                }
+            }
+            if (rc != KCS_OK) break;
+            store_tile(k, best, best_ms / 3.0f);
+        }
+        for (StudyPrep* P : cls) P->T = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
 }  // namespace
 }  // namespace kcs
 
 using namespace kcs;
+
+struct kcs_plan {
+    std::vector<PlanPhase> phases;
+    std::vector<int> tiles;
+    int n_studies = 0;
+    void* d_tables = nullptr;
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
 
 extern "C" {
 
@@ -620,6 +956,78 @@ int kcs_icm_sweep(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics
     if (kp) KCS_TRY(do_model_pass(*g, S, d_params, d_work, Q, stream));
     for (int32_t q = 0; q < Q; ++q) KCS_TRY(do_osl(*g, S, *p, kp, d_sino, q, Q, d_x, d_work, stream));
     return do_lm(*g, S, *p, *lm, d_x, d_params, d_lambda, d_work, Q, true, stream);
+}
+
+int kcs_plan_create(const kcs_study* studies, int32_t n, int32_t flags, hipStream_t stream, kcs_plan** out) {
+    if (!out) return fail(KCS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !studies) return fail(KCS_EINVAL, "need at least one study");
+    std::vector<StudyPrep> preps(n);
+    for (int i = 0; i < n; ++i) {
+        const int rc = check_study(studies[i]);
+        if (rc != KCS_OK) return fail(rc, "study %d: %s", i, g_err.c_str());
+        preps[i].s = &studies[i];
+        preps[i].S = make_schedule(studies[i].f, &studies[i].k);
+        preps[i].L = layout(&studies[i].g, studies[i].f.n_frames, studies[i].Q);
+        preps[i].T = projector_tile(studies[i].g, studies[i].f.n_frames);
+    }
+    g_err.clear();
+    for (const StudyPrep& P : preps) KCS_TRY(do_setup(P.S, P.s->d_work, stream));
+    if (flags & KCS_PLAN_AUTOTUNE) KCS_TRY(autotune(preps, stream));
+    TableBuilder tb;
+    build_schedule(tb, preps);
+    kcs_plan* plan = new kcs_plan();
+    plan->phases = tb.phases;
+    for (const StudyPrep& P : preps) plan->tiles.push_back(P.T);
+    plan->n_studies = n;
+    hipError_t e = hipMalloc(&plan->d_tables, std::max<size_t>(tb.buf.size(), 256));
+    if (e == hipSuccess) e = hipMemcpy(plan->d_tables, tb.buf.data(), tb.buf.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && (flags & KCS_PLAN_GRAPH)) {
+        e = hipStreamCreateWithFlags(&plan->capture, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(plan->capture, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t le = hipSuccess;
+            for (const PlanPhase& ph : plan->phases)
+                if (le == hipSuccess) le = run_phase(ph, (const char*)plan->d_tables, plan->capture);
+            e = hipStreamEndCapture(plan->capture, &plan->graph);
+            if (le != hipSuccess) e = le;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        kcs_plan_destroy(plan);
+        return hip_fail(e, "plan creation");
+    }
+    *out = plan;
+    return KCS_OK;
+}
+
+int kcs_plan_run(kcs_plan* plan, hipStream_t stream) {
+    if (!plan) return fail(KCS_EINVAL, "plan is NULL");
+    g_err.clear();
+    if (plan->exec) return launched(hipGraphLaunch(plan->exec, stream), "graph launch");
+    for (const PlanPhase& ph : plan->phases)
+        KCS_TRY(launched(run_phase(ph, (const char*)plan->d_tables, stream), "plan phase"));
+    return KCS_OK;
+}
+
+int kcs_plan_describe(const kcs_plan* plan, char* buf, size_t len) {
+    if (!plan || !buf || len == 0) return fail(KCS_EINVAL, "bad arguments");
+    std::string t = "studies=" + std::to_string(plan->n_studies) + " launches=" + std::to_string(plan->phases.size()) +
+                    " graph=" + (plan->exec ? "yes" : "no") + " tiles=";
+    for (size_t i = 0; i < plan->tiles.size(); ++i) t += (i ? "," : "") + std::to_string(plan->tiles[i]);
+    snprintf(buf, len, "%s", t.c_str());
+    return KCS_OK;
+}
+
+void kcs_plan_destroy(kcs_plan* plan) {
+    if (!plan) return;
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->capture) (void)hipStreamDestroy(plan->capture);
+    if (plan->d_tables) (void)hipFree(plan->d_tables);
+    delete plan;
 }
 
 }  // extern "C"

@@ -21,7 +21,10 @@ KCS_OK, KCS_EINVAL, KCS_ESHAPE, KCS_EWORKSPACE, KCS_EHIP = 0, -1, -2, -3, -4
 # Entry points declared in include/kcs.h (checked against the header by the tests).
 ENTRY_POINTS = ("kcs_workspace_bytes", "kcs_study_footprint_bytes", "kcs_project", "kcs_backproject",
                 "kcs_model_tac", "kcs_osl_update", "kcs_lm_fit", "kcs_init_state", "kcs_icm_sweep",
+                "kcs_plan_create", "kcs_plan_run", "kcs_plan_describe", "kcs_plan_destroy",
                 "kcs_timing_enable", "kcs_timing_collect", "kcs_last_error")
+
+KCS_PLAN_GRAPH, KCS_PLAN_AUTOTUNE = 1, 2
 
 TIMING_KINDS = ("setup", "project", "back", "osl", "lm", "model", "init", "copy")
 
@@ -60,6 +63,13 @@ class c_lm_opts(ctypes.Structure):
                 ("eta", ctypes.c_double)]
 
 
+class c_study(ctypes.Structure):
+    _fields_ = [("g", c_geometry), ("f", c_frames), ("k", c_kinetics), ("p", c_prior), ("lm", c_lm_opts),
+                ("Q", ctypes.c_int32), ("sweep_begin", ctypes.c_int32), ("sweep_end", ctypes.c_int32),
+                ("d_sino", ctypes.c_void_p), ("d_x", ctypes.c_void_p), ("d_params", ctypes.c_void_p),
+                ("d_lambda", ctypes.c_void_p), ("d_work", ctypes.c_void_p), ("work_bytes", ctypes.c_size_t)]
+
+
 @lru_cache(maxsize=1)
 def lib() -> ctypes.CDLL:
     if not os.path.exists(_LIB_PATH):
@@ -85,6 +95,14 @@ def lib() -> ctypes.CDLL:
     for name in ("kcs_project", "kcs_backproject", "kcs_model_tac", "kcs_osl_update", "kcs_lm_fit",
                  "kcs_init_state", "kcs_icm_sweep"):
         getattr(L, name).restype = ctypes.c_int
+    L.kcs_plan_create.argtypes = [P(c_study), i32, i32, vp, P(vp)]
+    L.kcs_plan_create.restype = ctypes.c_int
+    L.kcs_plan_run.argtypes = [vp, vp]
+    L.kcs_plan_run.restype = ctypes.c_int
+    L.kcs_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
+    L.kcs_plan_describe.restype = ctypes.c_int
+    L.kcs_plan_destroy.argtypes = [vp]
+    L.kcs_plan_destroy.restype = None
     L.kcs_timing_enable.argtypes = [i32]
     L.kcs_timing_enable.restype = ctypes.c_int
     L.kcs_timing_collect.argtypes = [P(ctypes.c_double), P(ctypes.c_int64)]
@@ -302,6 +320,71 @@ def kcs_icm_sweep(g: Geometry, f: Frames, k: Kinetics, p: Prior, lm: LMOptions, 
                                ctypes.byref(lc), _ptr(sino, (g.nz, g.n_ang, g.n_bin, f.M), "sino"), Q, sweep_idx,
                                _ptr(x, (g.nz, g.ny, g.nx, f.M), "x"), _ptr(params, (3, g.nz, g.ny, g.nx), "params"),
                                _ptr(lam, (g.nz, g.ny, g.nx), "lambda"), wp, wn, _stream(stream)))
+
+
+@dataclass
+class Study:
+    """One study of a batched plan: its constants, its sweep range and its device buffers
+    (sino (nz, n_ang, n_bin, M), x (nz, ny, nx, M), params (3, nz, ny, nx), lam (nz, ny, nx),
+    work: uint8 workspace of kcs_workspace_bytes(g, M, Q) bytes)."""
+    g: Geometry
+    f: Frames
+    k: Kinetics
+    p: Prior
+    lm: LMOptions
+    Q: int
+    sweep_begin: int
+    sweep_end: int
+    sino: object
+    x: object
+    params: object
+    lam: object
+    work: object
+
+    def c(self) -> c_study:
+        g, M = self.g, self.f.M
+        wp, wn = _work(self.work)
+        return c_study(g.c(), self.f.c(), self.k.c(), self.p.c(), self.lm.c(), self.Q, self.sweep_begin,
+                       self.sweep_end, _ptr(self.sino, (g.nz, g.n_ang, g.n_bin, M), "sino"),
+                       _ptr(self.x, (g.nz, g.ny, g.nx, M), "x"), _ptr(self.params, (3, g.nz, g.ny, g.nx), "params"),
+                       _ptr(self.lam, (g.nz, g.ny, g.nx), "lambda"), wp, wn)
+
+
+class Plan:
+    """Handle of a kcs_plan; keeps the studies' tensors alive until kcs_plan_destroy."""
+
+    def __init__(self, handle: ctypes.c_void_p, studies):
+        self.handle = handle
+        self.studies = list(studies)
+
+    def __del__(self):
+        kcs_plan_destroy(self)
+
+
+def kcs_plan_create(studies: Sequence[Study], flags: int = 0, stream=None) -> Plan:
+    arr = (c_study * len(studies))(*[s.c() for s in studies])
+    h = ctypes.c_void_p()
+    _check(lib().kcs_plan_create(arr, len(studies), flags, _stream(stream), ctypes.byref(h)))
+    return Plan(h, studies)
+
+
+def kcs_plan_run(plan: Plan, stream=None):
+    if plan.handle is None:
+        raise ValueError("plan was destroyed")
+    _check(lib().kcs_plan_run(plan.handle, _stream(stream)))
+
+
+def kcs_plan_describe(plan: Plan) -> str:
+    buf = ctypes.create_string_buffer(4096)
+    _check(lib().kcs_plan_describe(plan.handle, buf, len(buf)))
+    return buf.value.decode()
+
+
+def kcs_plan_destroy(plan: Plan):
+    if plan.handle is not None:
+        lib().kcs_plan_destroy(plan.handle)
+        plan.handle = None
+        plan.studies = []
 
 
 def kcs_timing_enable(on: bool):
