@@ -188,18 +188,24 @@ enum {
                              file named by KCS_TUNE_CACHE when that variable is set */
 };
 
-/* Validates every study, builds the per-study constant tables (on `stream`, in each workspace) and
- * the job tables (library-owned device memory), optionally autotunes and captures, then waits for
- * `stream`.  The studies' device buffers must stay valid until kcs_plan_destroy. */
+/* Validates every study (on failure: KCS_EINVAL / KCS_EWORKSPACE naming the study, nothing is
+ * launched), enqueues the per-study constant tables (in each workspace) and the upload of the job
+ * tables (library-owned device memory) on `stream` without waiting for them, and optionally
+ * autotunes (this waits for `stream`) and captures.  The studies' device buffers must stay valid
+ * and keep their roles until kcs_plan_destroy; a plan may be run any number of times, and each
+ * run repeats the same sweeps (the prior is on for sweep indices above 0). */
 int kcs_plan_create(const kcs_study* studies, int32_t n, int32_t flags, hipStream_t stream, kcs_plan** out);
 
-/* Enqueues the whole schedule of the plan on `stream` (asynchronous). */
+/* Enqueues the whole schedule of the plan on `stream` (asynchronous; ordered after the plan's
+ * creation work when that went to another stream).  Runs of plans that share a study must not
+ * overlap. */
 int kcs_plan_run(kcs_plan* plan, hipStream_t stream);
 
 /* Writes a one-line summary (studies, launches, graph, projector variant per study) into buf. */
 int kcs_plan_describe(const kcs_plan* plan, char* buf, size_t len);
 
-/* Frees the plan's device memory and graph.  NULL is ignored. */
+/* Waits for the plan's last run and its creation work, then frees its device memory, staging
+ * buffer and graph.  NULL is ignored. */
 void kcs_plan_destroy(kcs_plan* plan);
 
 /* Kernel timing for measurement harnesses.  While enabled, every kernel or copy the library

@@ -777,6 +777,9 @@ struct kcs_plan {
     std::vector<int> tiles;
     int n_studies = 0;
     void* d_tables = nullptr;
+    void* h_tables = nullptr;  // pinned staging of the tables (the upload is asynchronous)
+    hipEvent_t ready = nullptr;  // recorded on the creation stream after setup and upload
+    hipEvent_t done = nullptr;   // recorded after each run; destruction waits for it
     hipStream_t capture = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -980,8 +983,16 @@ int kcs_plan_create(const kcs_study* studies, int32_t n, int32_t flags, hipStrea
     plan->phases = tb.phases;
     for (const StudyPrep& P : preps) plan->tiles.push_back(P.T);
     plan->n_studies = n;
-    hipError_t e = hipMalloc(&plan->d_tables, std::max<size_t>(tb.buf.size(), 256));
-    if (e == hipSuccess) e = hipMemcpy(plan->d_tables, tb.buf.data(), tb.buf.size(), hipMemcpyHostToDevice);
+    const size_t tbytes = std::max<size_t>(tb.buf.size(), 256);
+    hipError_t e = hipMalloc(&plan->d_tables, tbytes);
+    if (e == hipSuccess) e = hipHostMalloc(&plan->h_tables, tbytes, hipHostMallocDefault);
+    if (e == hipSuccess) {
+        memcpy(plan->h_tables, tb.buf.data(), tb.buf.size());
+        e = hipMemcpyAsync(plan->d_tables, plan->h_tables, tb.buf.size(), hipMemcpyHostToDevice, stream);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(plan->ready, stream);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->done, hipEventDisableTiming);
     if (e == hipSuccess && (flags & KCS_PLAN_GRAPH)) {
         e = hipStreamCreateWithFlags(&plan->capture, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamBeginCapture(plan->capture, hipStreamCaptureModeThreadLocal);
@@ -994,7 +1005,6 @@ int kcs_plan_create(const kcs_study* studies, int32_t n, int32_t flags, hipStrea
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
         kcs_plan_destroy(plan);
         return hip_fail(e, "plan creation");
@@ -1006,10 +1016,16 @@ int kcs_plan_create(const kcs_study* studies, int32_t n, int32_t flags, hipStrea
 int kcs_plan_run(kcs_plan* plan, hipStream_t stream) {
     if (!plan) return fail(KCS_EINVAL, "plan is NULL");
     g_err.clear();
-    if (plan->exec) return launched(hipGraphLaunch(plan->exec, stream), "graph launch");
-    for (const PlanPhase& ph : plan->phases)
-        KCS_TRY(launched(run_phase(ph, (const char*)plan->d_tables, stream), "plan phase"));
-    return KCS_OK;
+    // order the run after the plan's setup and table upload when it goes on another stream
+    if (hipEventQuery(plan->ready) != hipSuccess)
+        KCS_TRY(launched(hipStreamWaitEvent(stream, plan->ready, 0), "wait for plan setup"));
+    if (plan->exec) {
+        KCS_TRY(launched(hipGraphLaunch(plan->exec, stream), "graph launch"));
+    } else {
+        for (const PlanPhase& ph : plan->phases)
+            KCS_TRY(launched(run_phase(ph, (const char*)plan->d_tables, stream), "plan phase"));
+    }
+    return launched(hipEventRecord(plan->done, stream), "plan completion event");
 }
 
 int kcs_plan_describe(const kcs_plan* plan, char* buf, size_t len) {
@@ -1023,10 +1039,16 @@ int kcs_plan_describe(const kcs_plan* plan, char* buf, size_t len) {
 
 void kcs_plan_destroy(kcs_plan* plan) {
     if (!plan) return;
+    // the tables may still be read by a run in flight, and the upload may still be pending
+    if (plan->done) (void)hipEventSynchronize(plan->done);
+    if (plan->ready) (void)hipEventSynchronize(plan->ready);
     if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     if (plan->capture) (void)hipStreamDestroy(plan->capture);
     if (plan->d_tables) (void)hipFree(plan->d_tables);
+    if (plan->h_tables) (void)hipHostFree(plan->h_tables);
+    if (plan->ready) (void)hipEventDestroy(plan->ready);
+    if (plan->done) (void)hipEventDestroy(plan->done);
     delete plan;
 }
 

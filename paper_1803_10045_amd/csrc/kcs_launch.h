@@ -105,10 +105,16 @@ template <class J>
 struct JobTable {
     const J* jobs;
     int32_t n;
+    // The table is read-only while a kernel runs, so it is read through the constant address
+    // space: the job fields become scalar loads (the index is uniform per workgroup) and the
+    // buffer pointers stored in the jobs are known to be global, which keeps the data accesses
+    // on global (not flat) loads and stores.
     __device__ __forceinline__ const J& find(uint32_t w) const {
+        using CJ = const __attribute__((address_space(4))) J;
+        CJ* t = (CJ*)jobs;
         int k = n - 1;
-        while (k > 0 && jobs[k].w0 > w) --k;
-        return jobs[k];
+        while (k > 0 && t[k].w0 > w) --k;
+        return *(const J*)&t[k];
     }
 };
 

@@ -1,0 +1,292 @@
+"""Continuous-batching reconstruction server on one GPU.
+
+Requests (dynamic studies) arrive over time.  A request is admitted when its HBM footprint
+(measured sinogram, image, three kinetic maps, lambda, workspace: kcs_study_footprint_bytes)
+fits under the budget next to the studies already resident, in arrival order.  Its state stays
+on the device until its last ICM sweep.  The GPU advances in ticks: one tick runs one ICM sweep of
+every resident study as one batched plan (a launch per phase over all studies' work lists), so
+studies that arrive while others are on the GPU join at the next tick and share its launches.
+Plans are cached by the resident set: while the set does not change, the same captured graph is
+replayed every tick.
+
+The scheduling logic (:class:`Scheduler`) is plain Python with no device code, so it can be
+tested on the CPU with a fake executor; :class:`GpuExecutor` owns the device state and the plans.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
+
+from . import kcs
+
+
+@dataclass(eq=False)
+class Request:
+    """One reconstruction: constants, schedule and a loader that produces the measured sinogram
+    (nz, n_ang, n_bin, M) as an FP32 device tensor on the current stream."""
+    rid: int
+    arrival: float  # seconds after the start of serving
+    g: kcs.Geometry
+    f: kcs.Frames
+    k: kcs.Kinetics
+    p: kcs.Prior
+    lm: kcs.LMOptions
+    Q: int
+    n_sweeps: int
+    load: Callable[[], object]
+    xi0: Tuple[float, float, float] = (0.08, 0.12, 0.05)
+
+    def footprint(self) -> int:
+        return kcs.kcs_study_footprint_bytes(self.g, self.f.M, self.Q)
+
+
+@dataclass(eq=False)
+class Slot:
+    req: Request
+    nbytes: int
+    sweep: int = 0  # next sweep to run
+    admitted_at: float = 0.0
+    state: object = None  # executor-owned device state
+
+
+class Scheduler:
+    """Admission by footprint (first come, first served: a request that does not fit blocks the
+    ones behind it, so large studies cannot starve) and sweep-granular batching."""
+
+    def __init__(self, budget_bytes: int):
+        self.budget = int(budget_bytes)
+        self.used = 0
+        self.queue: collections.deque = collections.deque()
+        self.active: List[Slot] = []
+
+    def arrive(self, req: Request):
+        nbytes = req.footprint()
+        if nbytes > self.budget:
+            raise ValueError(f"request {req.rid} needs {nbytes} bytes, more than the whole budget {self.budget}")
+        self.queue.append(req)
+
+    def admit(self, now: float) -> List[Slot]:
+        out = []
+        while self.queue and self.used + self.queue[0].footprint() <= self.budget:
+            req = self.queue.popleft()
+            s = Slot(req, req.footprint(), admitted_at=now)
+            self.used += s.nbytes
+            self.active.append(s)
+            out.append(s)
+        return out
+
+    def tick(self) -> List[Slot]:
+        """The slots that take part in the next tick (every resident study runs its next sweep)."""
+        return list(self.active)
+
+    def advance(self, ran: Sequence[Slot]) -> List[Slot]:
+        """After a tick: move the slots on by one sweep; returns the slots that finished (they
+        leave the active set; their bytes are returned by release())."""
+        done = []
+        for s in ran:
+            s.sweep += 1
+            if s.sweep >= s.req.n_sweeps:
+                done.append(s)
+        self.active = [s for s in self.active if s not in done]
+        return done
+
+    def release(self, slot: Slot):
+        self.used -= slot.nbytes
+
+    @property
+    def idle(self) -> bool:
+        return not self.queue and not self.active
+
+
+class GpuExecutor:
+    """Device state of the resident studies and the batched plans that advance them."""
+
+    def __init__(self, device="cuda", flags: int = kcs.KCS_PLAN_GRAPH):
+        import torch
+        self.torch = torch
+        self.dev = torch.device(device)
+        self.flags = flags
+        self.plans: Dict[tuple, kcs.Plan] = {}
+        self.retired: List[kcs.Plan] = []
+
+    def load(self, slot: Slot):
+        torch = self.torch
+        r = slot.req
+        g, M = r.g, r.f.M
+        sino = r.load()
+        x = torch.empty((g.nz, g.ny, g.nx, M), device=self.dev)
+        params = torch.empty((3, g.nz, g.ny, g.nx), device=self.dev)
+        lam = torch.empty((g.nz, g.ny, g.nx), device=self.dev)
+        work = kcs.alloc_workspace(g, M, r.Q, self.dev)
+        kcs.kcs_init_state(g, r.f, sino, r.xi0, x, params, lam, work)
+        slot.state = dict(sino=sino, x=x, params=params, lam=lam, work=work)
+
+    def _study(self, slot: Slot) -> kcs.Study:
+        r, st = slot.req, slot.state
+        return kcs.Study(r.g, r.f, r.k, r.p, r.lm, r.Q, slot.sweep, slot.sweep + 1, st["sino"], st["x"],
+                         st["params"], st["lam"], st["work"])
+
+    def run_tick(self, slots: Sequence[Slot]):
+        # a plan depends on the studies and on whether each one's prior is on (sweep > 0)
+        key = tuple((s.req.rid, s.sweep > 0) for s in slots)
+        plan = self.plans.get(key)
+        if plan is None:
+            plan = kcs.kcs_plan_create([self._study(s) for s in slots], self.flags)
+            self.plans[key] = plan
+        kcs.kcs_plan_run(plan)
+
+    def release(self, slot: Slot, keep_result: bool):
+        """Drops the plans that involve the study (destroyed later, at a quiet point) and returns
+        the results (x, params, lam) if asked; the device buffers go back to torch's allocator."""
+        rid = slot.req.rid
+        for key in [k for k in self.plans if any(r == rid for r, _ in k)]:
+            plan = self.plans.pop(key)
+            plan.studies = []  # never run again: its studies' buffers may go back to the allocator
+            self.retired.append(plan)
+        st = slot.state
+        slot.state = None
+        return (st["x"], st["params"], st["lam"]) if keep_result else None
+
+    # --- clock: completion times come from events on the GPU stream, relative to start() ---
+    def start(self):
+        self.torch.cuda.synchronize()
+        self.start_ev = self.torch.cuda.Event(enable_timing=True)
+        self.start_ev.record()
+
+    def mark(self):
+        ev = self.torch.cuda.Event(enable_timing=True)
+        ev.record()
+        return ev
+
+    def wait(self, ev) -> float:
+        ev.synchronize()
+        return self.start_ev.elapsed_time(ev) * 1e-3
+
+    def finish(self):
+        self.torch.cuda.synchronize()
+
+    def collect_retired(self):
+        for p in self.retired:
+            kcs.kcs_plan_destroy(p)
+        self.retired = []
+
+    def close(self):
+        for p in self.plans.values():
+            kcs.kcs_plan_destroy(p)
+        self.plans = {}
+        self.collect_retired()
+
+
+@dataclass
+class Completion:
+    rid: int
+    arrival: float
+    admitted: float
+    finished: float
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+def serve(requests: Sequence[Request], budget_bytes: int, executor, keep_results: bool = False,
+          max_in_flight: int = 2, log: Optional[Callable[[str], None]] = None):
+    """Serves `requests` in real time (arrival times in seconds from the start).  Returns
+    (completions, results, makespan_s, ticks); completion times come from the executor's clock
+    (GPU events on the stream).  At most `max_in_flight` ticks are enqueued ahead of the GPU;
+    a finished study's memory returns to the budget once its last tick has completed."""
+    sched = Scheduler(budget_bytes)
+    pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+    executor.start()
+    t0 = time.perf_counter()
+    in_flight: collections.deque = collections.deque()  # (token, finished slots)
+    completions: List[Completion] = []
+    results: Dict[int, tuple] = {}
+    ticks = 0
+
+    def retire_oldest():
+        token, finished = in_flight.popleft()
+        t_done = executor.wait(token)
+        for s in finished:
+            res = executor.release(s, keep_results)
+            if keep_results:
+                results[s.req.rid] = res
+            sched.release(s)
+            completions.append(Completion(s.req.rid, s.req.arrival, s.admitted_at, t_done))
+
+    while pending or not sched.idle or in_flight:
+        now = time.perf_counter() - t0
+        while pending and pending[0].arrival <= now:
+            sched.arrive(pending.popleft())
+        for s in sched.admit(now):
+            executor.load(s)
+        slots = sched.tick()
+        if slots:
+            executor.run_tick(slots)
+            in_flight.append((executor.mark(), sched.advance(slots)))
+            ticks += 1
+            if len(in_flight) >= max_in_flight:
+                retire_oldest()
+        elif in_flight:
+            retire_oldest()  # nothing to enqueue: let finished studies free their memory
+        elif pending:
+            time.sleep(max(0.0, min(pending[0].arrival - (time.perf_counter() - t0), 0.05)))
+        if sched.idle and not in_flight:
+            executor.collect_retired()
+    executor.finish()
+    executor.collect_retired()
+    makespan = max((c.finished for c in completions), default=0.0) - min((r.arrival for r in requests), default=0.0)
+    if log:
+        log(f"served {len(completions)} requests in {ticks} ticks")
+    return completions, results, makespan, ticks
+
+
+def serve_serial(requests: Sequence[Request], log: Optional[Callable[[str], None]] = None,
+                 keep_results: bool = False):
+    """Baseline: the plain per-study loop, one study at a time in arrival order (each study's
+    sweeps are kcs_icm_sweep calls).  Same outputs as serve()."""
+    import torch
+    pending = sorted(requests, key=lambda r: r.arrival)
+    start_ev = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start_ev.record()
+    done_events = []
+    results = {}
+    for r in pending:
+        wait = r.arrival - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        admitted = time.perf_counter() - t0
+        sino = r.load()
+        g, M = r.g, r.f.M
+        dev = sino.device
+        x = torch.empty((g.nz, g.ny, g.nx, M), device=dev)
+        params = torch.empty((3, g.nz, g.ny, g.nx), device=dev)
+        lam = torch.empty((g.nz, g.ny, g.nx), device=dev)
+        work = kcs.alloc_workspace(g, M, r.Q, dev)
+        kcs.kcs_init_state(g, r.f, sino, r.xi0, x, params, lam, work)
+        for s in range(r.n_sweeps):
+            kcs.kcs_icm_sweep(g, r.f, r.k, r.p, r.lm, sino, r.Q, s, x, params, lam, work)
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record()
+        done_events.append((r, admitted, ev))
+        if keep_results:
+            results[r.rid] = (x, params, lam)
+        if len(done_events) > 2:  # bound the host's lead over the GPU
+            done_events[-3][2].synchronize()
+    torch.cuda.synchronize()
+    completions = [Completion(r.rid, r.arrival, adm, start_ev.elapsed_time(ev) * 1e-3) for r, adm, ev in done_events]
+    makespan = max(c.finished for c in completions) - min(r.arrival for r in requests)
+    if log:
+        log(f"served {len(completions)} requests one at a time")
+    return completions, results, makespan
+
+
+def latency_summary(completions: Sequence[Completion]) -> dict:
+    import numpy as np
+    lat = np.array([c.latency for c in completions])
+    return {"p50_s": round(float(np.percentile(lat, 50)), 4), "p99_s": round(float(np.percentile(lat, 99)), 4),
+            "mean_s": round(float(lat.mean()), 4), "max_s": round(float(lat.max()), 4)}

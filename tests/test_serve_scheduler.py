@@ -1,0 +1,120 @@
+"""Serving loop on the CPU with a fake executor: admission by footprint in arrival order, the
+budget is never exceeded, every study runs exactly its sweeps in consecutive ticks starting at
+the tick after its admission, finished studies free their memory."""
+import time
+
+import pytest
+
+from paper_1803_10045_amd import serve
+
+
+class FakeRequest(serve.Request):
+    def __init__(self, rid, arrival, n_sweeps, nbytes):
+        self.rid, self.arrival, self.n_sweeps, self._nbytes = rid, arrival, n_sweeps, nbytes
+
+    def footprint(self):
+        return self._nbytes
+
+
+class FakeExecutor:
+    """Records every tick; time advances by a fixed amount per tick."""
+
+    def __init__(self, tick_s=0.001):
+        self.tick_s = tick_s
+        self.ticks = []  # list of [(rid, sweep)]
+        self.loaded = []
+        self.released = []
+        self.resident = {}
+        self.max_resident = 0
+        self.clock = 0.0
+
+    def start(self):
+        self.clock = 0.0
+
+    def load(self, slot):
+        self.loaded.append(slot.req.rid)
+        self.resident[slot.req.rid] = slot.nbytes
+        slot.state = "state"
+
+    def run_tick(self, slots):
+        self.ticks.append([(s.req.rid, s.sweep) for s in slots])
+        self.max_resident = max(self.max_resident, sum(self.resident.values()))
+        self.clock += self.tick_s
+
+    def mark(self):
+        return self.clock
+
+    def wait(self, token):
+        return token
+
+    def release(self, slot, keep):
+        self.released.append(slot.req.rid)
+        del self.resident[slot.req.rid]
+        return ("result", slot.req.rid) if keep else None
+
+    def collect_retired(self):
+        pass
+
+    def finish(self):
+        pass
+
+
+def run(reqs, budget):
+    ex = FakeExecutor()
+    comp, results, makespan, ticks = serve.serve(reqs, budget, ex, keep_results=True)
+    return ex, comp, results, ticks
+
+
+def test_every_study_runs_its_sweeps_in_consecutive_ticks():
+    reqs = [FakeRequest(i, 0.002 * i, n_sweeps=3 + i % 4, nbytes=10) for i in range(12)]
+    ex, comp, results, ticks = run(reqs, budget=1000)
+    assert sorted(c.rid for c in comp) == list(range(12))
+    assert set(results) == set(range(12))
+    for r in reqs:
+        seen = [(t, sw) for t, tick in enumerate(ex.ticks) for rid, sw in tick if rid == r.rid]
+        assert [sw for _, sw in seen] == list(range(r.n_sweeps))
+        ts = [t for t, _ in seen]
+        assert ts == list(range(ts[0], ts[0] + r.n_sweeps))  # consecutive ticks, no gaps
+    assert ticks == len(ex.ticks)
+
+
+def test_admission_respects_budget_and_arrival_order():
+    sizes = [60, 30, 50, 20, 70, 10, 40]
+    reqs = [FakeRequest(i, 0.0, n_sweeps=2 + i % 3, nbytes=s) for i, s in enumerate(sizes)]
+    ex, comp, _, _ = run(reqs, budget=100)
+    assert ex.max_resident <= 100
+    assert ex.loaded == list(range(len(sizes)))  # first come, first served
+    assert sorted(ex.released) == list(range(len(sizes)))
+    # studies overlap on the device: some tick holds more than one study
+    assert max(len(t) for t in ex.ticks) > 1
+
+
+def test_late_arrivals_join_running_ticks():
+    reqs = [FakeRequest(0, 0.0, n_sweeps=400, nbytes=10), FakeRequest(1, 0.05, n_sweeps=3, nbytes=10)]
+    ex = FakeExecutor()
+    # slow ticks so that study 0 is still running when study 1 arrives
+    orig = ex.run_tick
+
+    def slow(slots):
+        time.sleep(0.0005)
+        orig(slots)
+
+    ex.run_tick = slow
+    comp, _, _, _ = serve.serve(reqs, 100, ex)
+    both = [t for t in ex.ticks if {rid for rid, _ in t} == {0, 1}]
+    assert len(both) == 3  # study 1 ran all its sweeps next to study 0
+    done = {c.rid: c for c in comp}
+    assert done[1].finished < done[0].finished
+
+
+def test_request_larger_than_budget_is_rejected():
+    with pytest.raises(ValueError, match="more than the whole budget"):
+        run([FakeRequest(0, 0.0, 1, 500)], budget=100)
+
+
+def test_latency_summary():
+    comp = [serve.Completion(i, 0.0, 0.0, float(i + 1)) for i in range(100)]
+    s = serve.latency_summary(comp)
+    assert s["p50_s"] == pytest.approx(50.5)
+    assert s["p99_s"] == pytest.approx(99.01)
+    assert s["max_s"] == 100.0
