@@ -452,8 +452,9 @@ enum PhaseKind { PH_MODEL, PH_PROJ, PH_REDUCE, PH_OSL, PH_COPY, PH_LM };
 
 struct PlanPhase {
     int kind, M, T;
-    size_t off;  // byte offset of the job table in the plan's device buffer
-    int n;       // jobs
+    size_t off;         // byte offset of the job table in the plan's device buffer
+    size_t starts_off;  // byte offset of the packed first-workgroup indices of the jobs
+    int n;              // jobs
     uint32_t groups;
     int max_angles;
 };
@@ -478,10 +479,12 @@ struct TableBuilder {
             jobs[k].w0 = w;
             w += groups[k];
         }
-        const size_t off = align_up(buf.size(), 256);
+        const size_t soff = align_up(buf.size(), 256);
+        const size_t off = align_up(soff + jobs.size() * sizeof(uint32_t), 256);
         buf.resize(off + jobs.size() * sizeof(Job));
+        for (size_t k = 0; k < jobs.size(); ++k) memcpy(buf.data() + soff + 4 * k, &jobs[k].w0, 4);
         memcpy(buf.data() + off, jobs.data(), jobs.size() * sizeof(Job));
-        phases.push_back(PlanPhase{kind, M, T, off, (int)jobs.size(), w, max_angles});
+        phases.push_back(PlanPhase{kind, M, T, off, soff, (int)jobs.size(), w, max_angles});
     }
 };
 
@@ -654,16 +657,21 @@ void build_schedule(TableBuilder& tb, std::vector<StudyPrep>& preps) {
     }
 }
 
+template <class J>
+JobTable<J> table(const PlanPhase& ph, const char* base) {
+    return JobTable<J>{reinterpret_cast<const J*>(base + ph.off), reinterpret_cast<const uint32_t*>(base + ph.starts_off),
+                       ph.n};
+}
+
 hipError_t run_phase(const PlanPhase& ph, const char* base, hipStream_t st) {
-    const void* t = base + ph.off;
     switch (ph.kind) {
-        case PH_MODEL: return launch_model_jobs(ph.M, (const ModelJob*)t, ph.n, ph.groups, st);
+        case PH_MODEL: return launch_model_jobs(ph.M, table<ModelJob>(ph, base), ph.groups, st);
         case PH_PROJ:
-            return launch_project_jobs(ph.M, ph.T, (const ProjJob*)t, ph.n, ph.groups, ph.max_angles, true, st);
-        case PH_REDUCE: return launch_project_reduce_jobs(ph.M, ph.T, (const ProjJob*)t, ph.n, ph.groups, true, st);
-        case PH_OSL: return launch_osl_jobs(ph.M, (const OslJob*)t, ph.n, ph.groups, ph.max_angles, st);
-        case PH_COPY: return launch_copy_jobs((const CopyJob*)t, ph.n, ph.groups, st);
-        case PH_LM: return launch_lm_jobs(ph.M, (const LmJob*)t, ph.n, ph.groups, st);
+            return launch_project_jobs(ph.M, ph.T, table<ProjJob>(ph, base), ph.groups, ph.max_angles, true, st);
+        case PH_REDUCE: return launch_project_reduce_jobs(ph.M, ph.T, table<ProjJob>(ph, base), ph.groups, true, st);
+        case PH_OSL: return launch_osl_jobs(ph.M, table<OslJob>(ph, base), ph.groups, ph.max_angles, st);
+        case PH_COPY: return launch_copy_jobs(table<CopyJob>(ph, base), ph.groups, st);
+        case PH_LM: return launch_lm_jobs(ph.M, table<LmJob>(ph, base), ph.groups, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -295,8 +295,8 @@ hipError_t launch_osl(int M, const float* ratio, const float* Fm, float* x, cons
     return dispatch_osl(M, src, staged_tile_groups(a.g.nx, a.g.ny, a.g.nz), a.g.A_q, st);
 }
 
-hipError_t launch_osl_jobs(int M, const OslJob* jobs, int n, uint32_t groups, int max_angles, hipStream_t st) {
-    return dispatch_osl(M, JobTable<OslJob>{jobs, n}, groups, max_angles, st);
+hipError_t launch_osl_jobs(int M, JobTable<OslJob> jobs, uint32_t groups, int max_angles, hipStream_t st) {
+    return dispatch_osl(M, jobs, groups, max_angles, st);
 }
 
 }  // namespace kcs

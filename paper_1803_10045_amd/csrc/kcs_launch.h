@@ -104,17 +104,26 @@ struct OneJob {
 template <class J>
 struct JobTable {
     const J* jobs;
+    const uint32_t* starts;  // starts[k] = jobs[k].w0, ascending, packed for the search
     int32_t n;
-    // The table is read-only while a kernel runs, so it is read through the constant address
+    // The tables are read-only while a kernel runs, so they are read through the constant address
     // space: the job fields become scalar loads (the index is uniform per workgroup) and the
-    // buffer pointers stored in the jobs are known to be global, which keeps the data accesses
-    // on global (not flat) loads and stores.
+    // buffer pointers stored in the jobs are known to be global, which keeps the data accesses on
+    // global (not flat) loads and stores.  The job is found by binary search over `starts`.
     __device__ __forceinline__ const J& find(uint32_t w) const {
         using CJ = const __attribute__((address_space(4))) J;
+        using CU = const __attribute__((address_space(4))) uint32_t;
         CJ* t = (CJ*)jobs;
-        int k = n - 1;
-        while (k > 0 && t[k].w0 > w) --k;
-        return *(const J*)&t[k];
+        CU* s = (CU*)starts;
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s[mid] <= w)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        return *(const J*)&t[lo];
     }
 };
 
@@ -128,15 +137,15 @@ uint32_t lm_groups(int nx, int ny, int nz);
 uint32_t model_groups(int64_t n);
 uint32_t copy_groups(int64_t n);
 
-// Launchers over job tables (device pointer to n jobs covering `groups` workgroups in total).
-hipError_t launch_project_jobs(int M, int T, const ProjJob* jobs, int n, uint32_t groups, int max_angles, bool ratio,
+// Launchers over job tables (device tables of n jobs covering `groups` workgroups in total).
+hipError_t launch_project_jobs(int M, int T, JobTable<ProjJob> jobs, uint32_t groups, int max_angles, bool ratio,
                                hipStream_t st);
-hipError_t launch_project_reduce_jobs(int M, int T, const ProjJob* jobs, int n, uint32_t groups, bool ratio,
+hipError_t launch_project_reduce_jobs(int M, int T, JobTable<ProjJob> jobs, uint32_t groups, bool ratio,
                                       hipStream_t st);
-hipError_t launch_osl_jobs(int M, const OslJob* jobs, int n, uint32_t groups, int max_angles, hipStream_t st);
-hipError_t launch_lm_jobs(int M, const LmJob* jobs, int n, uint32_t groups, hipStream_t st);
-hipError_t launch_model_jobs(int M, const ModelJob* jobs, int n, uint32_t groups, hipStream_t st);
-hipError_t launch_copy_jobs(const CopyJob* jobs, int n, uint32_t groups, hipStream_t st);
+hipError_t launch_osl_jobs(int M, JobTable<OslJob> jobs, uint32_t groups, int max_angles, hipStream_t st);
+hipError_t launch_lm_jobs(int M, JobTable<LmJob> jobs, uint32_t groups, hipStream_t st);
+hipError_t launch_model_jobs(int M, JobTable<ModelJob> jobs, uint32_t groups, hipStream_t st);
+hipError_t launch_copy_jobs(JobTable<CopyJob> jobs, uint32_t groups, hipStream_t st);
 
 hipError_t launch_setup(const SetupArgs& s, KinTab* K, hipStream_t st);
 hipError_t launch_project(int M, const float* x, const float* sino, float* out, const ProjArgs& p, bool ratio,

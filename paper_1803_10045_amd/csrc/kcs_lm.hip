@@ -167,8 +167,8 @@ hipError_t launch_lm(int M, const KinTab* K, const float* x, const float* xi_in,
     return dispatch_lm(M, src, lm_groups(a.nx, a.ny, a.nz), st);
 }
 
-hipError_t launch_lm_jobs(int M, const LmJob* jobs, int n, uint32_t groups, hipStream_t st) {
-    return dispatch_lm(M, JobTable<LmJob>{jobs, n}, groups, st);
+hipError_t launch_lm_jobs(int M, JobTable<LmJob> jobs, uint32_t groups, hipStream_t st) {
+    return dispatch_lm(M, jobs, groups, st);
 }
 
 }  // namespace kcs

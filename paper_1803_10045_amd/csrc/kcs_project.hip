@@ -254,14 +254,14 @@ hipError_t launch_project_tiled(int M, int T, const float* x, const float* sino,
 
 // Batched: a device table of jobs.  For T > 0 the tile step and the reduce step are separate
 // launches with separate tables (their work lists differ); max_angles bounds A_q over the jobs.
-hipError_t launch_project_jobs(int M, int T, const ProjJob* jobs, int n, uint32_t groups, int max_angles, bool ratio,
+hipError_t launch_project_jobs(int M, int T, JobTable<ProjJob> jobs, uint32_t groups, int max_angles, bool ratio,
                                hipStream_t st) {
-    return dispatch_project(M, T, JobTable<ProjJob>{jobs, n}, groups, max_angles, ratio, false, st);
+    return dispatch_project(M, T, jobs, groups, max_angles, ratio, false, st);
 }
 
-hipError_t launch_project_reduce_jobs(int M, int T, const ProjJob* jobs, int n, uint32_t groups, bool ratio,
+hipError_t launch_project_reduce_jobs(int M, int T, JobTable<ProjJob> jobs, uint32_t groups, bool ratio,
                                       hipStream_t st) {
-    return dispatch_project(M, T, JobTable<ProjJob>{jobs, n}, groups, 0, ratio, true, st);
+    return dispatch_project(M, T, jobs, groups, 0, ratio, true, st);
 }
 
 }  // namespace kcs

@@ -87,8 +87,8 @@ hipError_t launch_model(int M, const KinTab* K, const FrameTab& fr, const float*
     return dispatch_model(M, J != nullptr, src, model_groups(n), st);
 }
 
-hipError_t launch_model_jobs(int M, const ModelJob* jobs, int n, uint32_t groups, hipStream_t st) {
-    return dispatch_model(M, false, JobTable<ModelJob>{jobs, n}, groups, st);
+hipError_t launch_model_jobs(int M, JobTable<ModelJob> jobs, uint32_t groups, hipStream_t st) {
+    return dispatch_model(M, false, jobs, groups, st);
 }
 
 // Batched device-to-device copies (the kinetic maps before an odd number of LM iterations).
@@ -104,8 +104,8 @@ __global__ __launch_bounds__(256) void kcopy_kernel(JobTable<CopyJob> src) {
     }
 }
 
-hipError_t launch_copy_jobs(const CopyJob* jobs, int n, uint32_t groups, hipStream_t st) {
-    hipLaunchKernelGGL(kcopy_kernel, dim3(xcd_round_up(groups)), dim3(256), 0, st, JobTable<CopyJob>{jobs, n});
+hipError_t launch_copy_jobs(JobTable<CopyJob> jobs, uint32_t groups, hipStream_t st) {
+    hipLaunchKernelGGL(kcopy_kernel, dim3(xcd_round_up(groups)), dim3(256), 0, st, jobs);
     return hipGetLastError();
 }
 

@@ -9,6 +9,11 @@ studies that arrive while others are on the GPU join at the next tick and share 
 Plans are cached by the resident set: while the set does not change, the same captured graph is
 replayed every tick.
 
+Studies are split into lanes by the HBM traffic of one of their sweeps; each lane has its own
+stream and its own ticks, so the short sweeps of small studies run next to the long sweeps of
+large ones (the hardware interleaves their workgroups) instead of waiting for them.  Loading (the
+sinogram, the initial state) runs on a stream of its own.
+
 The scheduling logic (:class:`Scheduler`) is plain Python with no device code, so it can be
 tested on the CPU with a fake executor; :class:`GpuExecutor` owns the device state and the plans.
 """
@@ -48,18 +53,35 @@ class Slot:
     nbytes: int
     sweep: int = 0  # next sweep to run
     admitted_at: float = 0.0
+    lane: int = 0
     state: object = None  # executor-owned device state
+
+
+def sweep_bytes(g: kcs.Geometry, M: int, Q: int) -> int:
+    """HBM bytes one ICM sweep must move at least: per subset the forward projection (image, the
+    subset's sinogram read, ratio written) and the OSL update (ratio, image in and out, maps), then
+    five MAP-LM iterations (image, maps in and out, lambda)."""
+    N = g.nx * g.ny * g.nz
+    image = N * M * 4
+    sub = g.nz * (g.n_ang / Q) * g.n_bin * M * 4
+    return int(Q * ((image + 2 * sub) + (2 * image + sub + 12 * N)) + 5 * (image + 32 * N))
+
+
+def lane_by_traffic(threshold_bytes: float = 10e9) -> Callable[[Request], int]:
+    """Lane 1 for studies whose sweep moves more than `threshold_bytes`, lane 0 otherwise."""
+    return lambda r: 1 if sweep_bytes(r.g, r.f.M, r.Q) > threshold_bytes else 0
 
 
 class Scheduler:
     """Admission by footprint (first come, first served: a request that does not fit blocks the
-    ones behind it, so large studies cannot starve) and sweep-granular batching."""
+    ones behind it, so large studies cannot starve) and sweep-granular batching per lane."""
 
-    def __init__(self, budget_bytes: int):
+    def __init__(self, budget_bytes: int, lane_of: Callable[[Request], int] = lambda r: 0, n_lanes: int = 1):
         self.budget = int(budget_bytes)
         self.used = 0
         self.queue: collections.deque = collections.deque()
-        self.active: List[Slot] = []
+        self.active: List[List[Slot]] = [[] for _ in range(n_lanes)]
+        self.lane_of = lane_of
 
     def arrive(self, req: Request):
         nbytes = req.footprint()
@@ -71,15 +93,15 @@ class Scheduler:
         out = []
         while self.queue and self.used + self.queue[0].footprint() <= self.budget:
             req = self.queue.popleft()
-            s = Slot(req, req.footprint(), admitted_at=now)
+            s = Slot(req, req.footprint(), admitted_at=now, lane=self.lane_of(req))
             self.used += s.nbytes
-            self.active.append(s)
+            self.active[s.lane].append(s)
             out.append(s)
         return out
 
-    def tick(self) -> List[Slot]:
-        """The slots that take part in the next tick (every resident study runs its next sweep)."""
-        return list(self.active)
+    def tick(self, lane: int = 0) -> List[Slot]:
+        """The slots of `lane` that take part in its next tick (each runs its next sweep)."""
+        return list(self.active[lane])
 
     def advance(self, ran: Sequence[Slot]) -> List[Slot]:
         """After a tick: move the slots on by one sweep; returns the slots that finished (they
@@ -89,7 +111,8 @@ class Scheduler:
             s.sweep += 1
             if s.sweep >= s.req.n_sweeps:
                 done.append(s)
-        self.active = [s for s in self.active if s not in done]
+        for lane in range(len(self.active)):
+            self.active[lane] = [s for s in self.active[lane] if not any(s is d for d in done)]
         return done
 
     def release(self, slot: Slot):
@@ -97,30 +120,40 @@ class Scheduler:
 
     @property
     def idle(self) -> bool:
-        return not self.queue and not self.active
+        return not self.queue and not any(self.active)
 
 
 class GpuExecutor:
-    """Device state of the resident studies and the batched plans that advance them."""
+    """Device state of the resident studies and the batched plans that advance them: one stream
+    per lane for the ticks, one stream for loading."""
 
-    def __init__(self, device="cuda", flags: int = kcs.KCS_PLAN_GRAPH):
+    def __init__(self, device="cuda", flags: int = kcs.KCS_PLAN_GRAPH, n_lanes: int = 1):
         import torch
         self.torch = torch
         self.dev = torch.device(device)
         self.flags = flags
+        self.lanes = [torch.cuda.Stream(device=self.dev) for _ in range(n_lanes)]
+        self.load_stream = torch.cuda.Stream(device=self.dev)
         self.plans: Dict[tuple, kcs.Plan] = {}
         self.retired: List[kcs.Plan] = []
 
     def load(self, slot: Slot):
         torch = self.torch
         r = slot.req
-        g, M = r.g, r.f.M
-        sino = r.load()
-        x = torch.empty((g.nz, g.ny, g.nx, M), device=self.dev)
-        params = torch.empty((3, g.nz, g.ny, g.nx), device=self.dev)
-        lam = torch.empty((g.nz, g.ny, g.nx), device=self.dev)
-        work = kcs.alloc_workspace(g, M, r.Q, self.dev)
-        kcs.kcs_init_state(g, r.f, sino, r.xi0, x, params, lam, work)
+        lane = self.lanes[slot.lane]
+        with torch.cuda.stream(self.load_stream):
+            sino = r.load()
+            g, M = r.g, r.f.M
+            x = torch.empty((g.nz, g.ny, g.nx, M), device=self.dev)
+            params = torch.empty((3, g.nz, g.ny, g.nx), device=self.dev)
+            lam = torch.empty((g.nz, g.ny, g.nx), device=self.dev)
+            work = kcs.alloc_workspace(g, M, r.Q, self.dev)
+            kcs.kcs_init_state(g, r.f, sino, r.xi0, x, params, lam, work)
+            ready = torch.cuda.Event()
+            ready.record()
+        lane.wait_event(ready)
+        for t in (sino, x, params, lam, work):
+            t.record_stream(lane)  # the buffers are used on the lane's stream from now on
         slot.state = dict(sino=sino, x=x, params=params, lam=lam, work=work)
 
     def _study(self, slot: Slot) -> kcs.Study:
@@ -128,20 +161,22 @@ class GpuExecutor:
         return kcs.Study(r.g, r.f, r.k, r.p, r.lm, r.Q, slot.sweep, slot.sweep + 1, st["sino"], st["x"],
                          st["params"], st["lam"], st["work"])
 
-    def run_tick(self, slots: Sequence[Slot]):
+    def run_tick(self, slots: Sequence[Slot], lane: int = 0):
         # a plan depends on the studies and on whether each one's prior is on (sweep > 0)
-        key = tuple((s.req.rid, s.sweep > 0) for s in slots)
-        plan = self.plans.get(key)
-        if plan is None:
-            plan = kcs.kcs_plan_create([self._study(s) for s in slots], self.flags)
-            self.plans[key] = plan
-        kcs.kcs_plan_run(plan)
+        key = (lane,) + tuple((s.req.rid, s.sweep > 0) for s in slots)
+        stream = self.lanes[lane]
+        with self.torch.cuda.stream(stream):
+            plan = self.plans.get(key)
+            if plan is None:
+                plan = kcs.kcs_plan_create([self._study(s) for s in slots], self.flags)
+                self.plans[key] = plan
+            kcs.kcs_plan_run(plan)
 
     def release(self, slot: Slot, keep_result: bool):
         """Drops the plans that involve the study (destroyed later, at a quiet point) and returns
         the results (x, params, lam) if asked; the device buffers go back to torch's allocator."""
         rid = slot.req.rid
-        for key in [k for k in self.plans if any(r == rid for r, _ in k)]:
+        for key in [k for k in self.plans if any(r == rid for r, _ in k[1:])]:
             plan = self.plans.pop(key)
             plan.studies = []  # never run again: its studies' buffers may go back to the allocator
             self.retired.append(plan)
@@ -149,16 +184,19 @@ class GpuExecutor:
         slot.state = None
         return (st["x"], st["params"], st["lam"]) if keep_result else None
 
-    # --- clock: completion times come from events on the GPU stream, relative to start() ---
+    # --- clock: completion times come from events on the lane streams, relative to start() ---
     def start(self):
         self.torch.cuda.synchronize()
         self.start_ev = self.torch.cuda.Event(enable_timing=True)
         self.start_ev.record()
 
-    def mark(self):
+    def mark(self, lane: int = 0):
         ev = self.torch.cuda.Event(enable_timing=True)
-        ev.record()
+        ev.record(self.lanes[lane])
         return ev
+
+    def done(self, ev) -> bool:
+        return ev.query()
 
     def wait(self, ev) -> float:
         ev.synchronize()
@@ -167,10 +205,11 @@ class GpuExecutor:
     def finish(self):
         self.torch.cuda.synchronize()
 
-    def collect_retired(self):
-        for p in self.retired:
-            kcs.kcs_plan_destroy(p)
-        self.retired = []
+    def collect_retired(self, force: bool = True):
+        if force or len(self.retired) > 64:
+            for p in self.retired:
+                kcs.kcs_plan_destroy(p)
+            self.retired = []
 
     def close(self):
         for p in self.plans.values():
@@ -192,22 +231,27 @@ class Completion:
 
 
 def serve(requests: Sequence[Request], budget_bytes: int, executor, keep_results: bool = False,
-          max_in_flight: int = 2, log: Optional[Callable[[str], None]] = None):
+          max_in_flight: int = 2, lane_of: Optional[Callable[[Request], int]] = None,
+          log: Optional[Callable[[str], None]] = None):
     """Serves `requests` in real time (arrival times in seconds from the start).  Returns
     (completions, results, makespan_s, ticks); completion times come from the executor's clock
-    (GPU events on the stream).  At most `max_in_flight` ticks are enqueued ahead of the GPU;
-    a finished study's memory returns to the budget once its last tick has completed."""
-    sched = Scheduler(budget_bytes)
+    (GPU events on the lane streams).  Each lane keeps at most `max_in_flight` ticks enqueued
+    ahead of the GPU; a finished study's memory returns to the budget once its last tick has
+    completed."""
+    n_lanes = len(getattr(executor, "lanes", [None]))
+    if lane_of is None:
+        lane_of = lane_by_traffic() if n_lanes > 1 else (lambda r: 0)
+    sched = Scheduler(budget_bytes, lane_of, n_lanes)
     pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
     executor.start()
     t0 = time.perf_counter()
-    in_flight: collections.deque = collections.deque()  # (token, finished slots)
+    in_flight = [collections.deque() for _ in range(n_lanes)]  # per lane: (token, finished slots)
     completions: List[Completion] = []
     results: Dict[int, tuple] = {}
     ticks = 0
 
-    def retire_oldest():
-        token, finished = in_flight.popleft()
+    def retire(lane):
+        token, finished = in_flight[lane].popleft()
         t_done = executor.wait(token)
         for s in finished:
             res = executor.release(s, keep_results)
@@ -216,25 +260,30 @@ def serve(requests: Sequence[Request], budget_bytes: int, executor, keep_results
             sched.release(s)
             completions.append(Completion(s.req.rid, s.req.arrival, s.admitted_at, t_done))
 
-    while pending or not sched.idle or in_flight:
+    while pending or not sched.idle or any(in_flight):
         now = time.perf_counter() - t0
         while pending and pending[0].arrival <= now:
             sched.arrive(pending.popleft())
         for s in sched.admit(now):
             executor.load(s)
-        slots = sched.tick()
-        if slots:
-            executor.run_tick(slots)
-            in_flight.append((executor.mark(), sched.advance(slots)))
-            ticks += 1
-            if len(in_flight) >= max_in_flight:
-                retire_oldest()
-        elif in_flight:
-            retire_oldest()  # nothing to enqueue: let finished studies free their memory
-        elif pending:
-            time.sleep(max(0.0, min(pending[0].arrival - (time.perf_counter() - t0), 0.05)))
-        if sched.idle and not in_flight:
-            executor.collect_retired()
+        progressed = False
+        for lane in range(n_lanes):
+            while in_flight[lane] and executor.done(in_flight[lane][0][0]):
+                retire(lane)
+            if len(in_flight[lane]) >= max_in_flight:
+                continue
+            slots = sched.tick(lane)
+            if slots:
+                executor.run_tick(slots, lane)
+                in_flight[lane].append((executor.mark(lane), sched.advance(slots)))
+                ticks += 1
+                progressed = True
+        if not progressed:
+            if any(in_flight):
+                time.sleep(0.0002)  # every lane is full or idle: poll the GPU
+            elif pending:
+                time.sleep(max(0.0, min(pending[0].arrival - (time.perf_counter() - t0), 0.05)))
+        executor.collect_retired(force=sched.idle and not any(in_flight))
     executor.finish()
     executor.collect_retired()
     makespan = max((c.finished for c in completions), default=0.0) - min((r.arrival for r in requests), default=0.0)

@@ -51,11 +51,12 @@ def alone(r):
     return x, params, lam
 
 
-@pytest.mark.parametrize("flags", [0, kcs.KCS_PLAN_GRAPH])
-def test_served_results_equal_alone(flags):
+@pytest.mark.parametrize("flags,lanes", [(0, 1), (kcs.KCS_PLAN_GRAPH, 1), (kcs.KCS_PLAN_GRAPH, 2)])
+def test_served_results_equal_alone(flags, lanes):
     reqs = small_stream()
-    ex = serve.GpuExecutor(DEV, flags)
-    comp, results, makespan, ticks = serve.serve(reqs, 1 << 40, ex, keep_results=True)
+    ex = serve.GpuExecutor(DEV, flags, n_lanes=lanes)
+    comp, results, makespan, ticks = serve.serve(reqs, 1 << 40, ex, keep_results=True,
+                                                 lane_of=lambda r: r.rid % lanes)
     ex.close()
     assert sorted(c.rid for c in comp) == list(range(len(reqs)))
     assert ticks < sum(r.n_sweeps for r in reqs)  # studies shared ticks
@@ -71,8 +72,8 @@ def test_served_under_tight_budget():
     reqs = small_stream()
     sizes = sorted(r.footprint() for r in reqs)
     budget = sizes[-1] + sizes[-2]
-    ex = serve.GpuExecutor(DEV)
-    comp, results, _, _ = serve.serve(reqs, budget, ex, keep_results=True)
+    ex = serve.GpuExecutor(DEV, n_lanes=2)
+    comp, results, _, _ = serve.serve(reqs, budget, ex, keep_results=True, lane_of=lambda r: r.rid % 2)
     ex.close()
     assert len(comp) == len(reqs)
     for r in reqs[:3]:

@@ -36,13 +36,16 @@ class FakeExecutor:
         self.resident[slot.req.rid] = slot.nbytes
         slot.state = "state"
 
-    def run_tick(self, slots):
+    def run_tick(self, slots, lane=0):
         self.ticks.append([(s.req.rid, s.sweep) for s in slots])
         self.max_resident = max(self.max_resident, sum(self.resident.values()))
         self.clock += self.tick_s
 
-    def mark(self):
+    def mark(self, lane=0):
         return self.clock
+
+    def done(self, token):
+        return True
 
     def wait(self, token):
         return token
@@ -52,7 +55,7 @@ class FakeExecutor:
         del self.resident[slot.req.rid]
         return ("result", slot.req.rid) if keep else None
 
-    def collect_retired(self):
+    def collect_retired(self, force=True):
         pass
 
     def finish(self):
@@ -95,9 +98,9 @@ def test_late_arrivals_join_running_ticks():
     # slow ticks so that study 0 is still running when study 1 arrives
     orig = ex.run_tick
 
-    def slow(slots):
+    def slow(slots, lane=0):
         time.sleep(0.0005)
-        orig(slots)
+        orig(slots, lane)
 
     ex.run_tick = slow
     comp, _, _, _ = serve.serve(reqs, 100, ex)
@@ -118,3 +121,28 @@ def test_latency_summary():
     assert s["p50_s"] == pytest.approx(50.5)
     assert s["p99_s"] == pytest.approx(99.01)
     assert s["max_s"] == 100.0
+
+
+class TwoLaneExecutor(FakeExecutor):
+    lanes = [None, None]
+
+
+def test_lanes_run_independently():
+    """Large studies (lane 1) never share a tick with small ones (lane 0), and a small study that
+    arrives after a large one finishes first."""
+    reqs = [FakeRequest(0, 0.0, n_sweeps=300, nbytes=50), FakeRequest(1, 0.02, n_sweeps=3, nbytes=10),
+            FakeRequest(2, 0.02, n_sweeps=4, nbytes=10)]
+    ex = TwoLaneExecutor()
+    orig = ex.run_tick
+
+    def slow(slots, lane=0):
+        time.sleep(0.0002 if lane == 0 else 0.0005)
+        orig(slots, lane)
+
+    ex.run_tick = slow
+    comp, _, _, _ = serve.serve(reqs, 100, ex, lane_of=lambda r: 1 if r.rid == 0 else 0)
+    for t in ex.ticks:
+        rids = {rid for rid, _ in t}
+        assert rids == {0} or 0 not in rids
+    done = {c.rid: c for c in comp}
+    assert done[1].finished < done[0].finished and done[2].finished < done[0].finished
