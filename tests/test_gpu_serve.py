@@ -20,10 +20,10 @@ def small_stream():
     specs = [  # (matrix x, y, planes, angles, bins, subsets, sweeps, arrival s, seed)
         (64, 64, 1, 60, 64, 4, 4, 0.00, 21),
         (48, 40, 2, 50, 44, 5, 3, 0.00, 22),
-        (40, 40, 3, 36, 40, 3, 6, 0.02, 23),
-        (64, 64, 2, 72, 64, 6, 2, 0.03, 24),
-        (32, 32, 1, 30, 32, 2, 5, 0.05, 25),
-        (56, 56, 1, 48, 56, 4, 3, 0.08, 26),
+        (40, 40, 3, 36, 40, 3, 6, 0.00, 23),
+        (64, 64, 2, 72, 64, 6, 2, 0.00, 24),
+        (32, 32, 1, 30, 32, 2, 5, 0.01, 25),
+        (56, 56, 1, 48, 56, 4, 3, 0.02, 26),
     ]
     reqs = []
     for j, (nx, ny, nz, na, nb, Q, sw, t, seed) in enumerate(specs):
