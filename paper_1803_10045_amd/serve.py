@@ -76,8 +76,11 @@ class Scheduler:
     """Admission by footprint (first come, first served: a request that does not fit blocks the
     ones behind it, so large studies cannot starve) and sweep-granular batching per lane."""
 
-    def __init__(self, budget_bytes: int, lane_of: Callable[[Request], int] = lambda r: 0, n_lanes: int = 1):
+    def __init__(self, budget_bytes: int, lane_of: Callable[[Request], int] = lambda r: 0, n_lanes: int = 1,
+                 lane_batch: Optional[Sequence[int]] = None):
         self.budget = int(budget_bytes)
+        # most studies a tick of each lane advances, oldest first (0: no limit)
+        self.lane_batch = list(lane_batch) if lane_batch is not None else [0] * n_lanes
         self.used = 0
         self.queue: collections.deque = collections.deque()
         self.active: List[List[Slot]] = [[] for _ in range(n_lanes)]
@@ -100,8 +103,10 @@ class Scheduler:
         return out
 
     def tick(self, lane: int = 0) -> List[Slot]:
-        """The slots of `lane` that take part in its next tick (each runs its next sweep)."""
-        return list(self.active[lane])
+        """The slots of `lane` that take part in its next tick (each runs its next sweep): all
+        resident ones, or the oldest `lane_batch[lane]` of them."""
+        cap = self.lane_batch[lane]
+        return list(self.active[lane][:cap] if cap else self.active[lane])
 
     def advance(self, ran: Sequence[Slot]) -> List[Slot]:
         """After a tick: move the slots on by one sweep; returns the slots that finished (they
@@ -232,16 +237,21 @@ class Completion:
 
 def serve(requests: Sequence[Request], budget_bytes: int, executor, keep_results: bool = False,
           max_in_flight: int = 2, lane_of: Optional[Callable[[Request], int]] = None,
-          log: Optional[Callable[[str], None]] = None):
+          lane_batch: Optional[Sequence[int]] = None, log: Optional[Callable[[str], None]] = None):
     """Serves `requests` in real time (arrival times in seconds from the start).  Returns
     (completions, results, makespan_s, ticks); completion times come from the executor's clock
-    (GPU events on the lane streams).  Each lane keeps at most `max_in_flight` ticks enqueued
+    (GPU events on the lane streams).  `lane_batch[i]` caps the studies per tick of lane i (0: all
+    resident ones).  Each lane keeps at most `max_in_flight` ticks enqueued
     ahead of the GPU; a finished study's memory returns to the budget once its last tick has
     completed."""
     n_lanes = len(getattr(executor, "lanes", [None]))
     if lane_of is None:
         lane_of = lane_by_traffic() if n_lanes > 1 else (lambda r: 0)
-    sched = Scheduler(budget_bytes, lane_of, n_lanes)
+    if lane_batch is None:
+        # a large study fills the GPU by itself: the large lane runs its studies one at a time, in
+        # admission order, so that batching does not stretch each one's latency
+        lane_batch = [0] * n_lanes if n_lanes == 1 else [0] + [1] * (n_lanes - 1)
+    sched = Scheduler(budget_bytes, lane_of, n_lanes, lane_batch)
     pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
     executor.start()
     t0 = time.perf_counter()

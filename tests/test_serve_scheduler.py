@@ -146,3 +146,11 @@ def test_lanes_run_independently():
         assert rids == {0} or 0 not in rids
     done = {c.rid: c for c in comp}
     assert done[1].finished < done[0].finished and done[2].finished < done[0].finished
+
+
+def test_lane_batch_runs_oldest_first():
+    reqs = [FakeRequest(i, 0.0, n_sweeps=3, nbytes=10) for i in range(3)]
+    ex = TwoLaneExecutor()
+    comp, _, _, _ = serve.serve(reqs, 100, ex, lane_of=lambda r: 1, lane_batch=[0, 1])
+    assert all(len(t) == 1 for t in ex.ticks)
+    assert [t[0][0] for t in ex.ticks] == [0, 0, 0, 1, 1, 1, 2, 2, 2]
