@@ -134,9 +134,11 @@ def neighbour_terms(xi_eval: np.ndarray, xi_ref: np.ndarray, delta) -> Tuple[np.
 
 
 def lm_iteration(fr: Frames, kin: Kinetics, prior: Prior, opt: LMOptions, x: np.ndarray, params: np.ndarray,
-                 lam: np.ndarray):
+                 lam: np.ndarray, with_objective: bool = False):
     """One synchronous MAP-LM iteration over all voxels (Eq. 4).  x: (nz, ny, nx, M);
-    params: (3, nz, ny, nx); lam: (nz, ny, nx).  Returns new (params, lam)."""
+    params: (3, nz, ny, nx); lam: (nz, ny, nx).  Returns new (params, lam), followed by the
+    voxel objectives before and at the trial step (phi0, phi1), each (nz, ny, nx), when
+    `with_objective` is set."""
     shp = params.shape[1:]
     N = int(np.prod(shp))
     xv = x.reshape(N, -1)
@@ -159,7 +161,8 @@ def lm_iteration(fr: Frames, kin: Kinetics, prior: Prior, opt: LMOptions, x: np.
     accept = phi1 - phi0 < -opt.eta * phi0
     new = np.where(accept[:, None], trial, xi)
     lam = np.where(accept, np.maximum(lam / 10.0, opt.lam_min), np.minimum(lam * 10.0, opt.lam_max))
-    return new.T.reshape(params.shape).copy(), lam.reshape(shp)
+    out = (new.T.reshape(params.shape).copy(), lam.reshape(shp))
+    return out + (phi0.reshape(shp), phi1.reshape(shp)) if with_objective else out
 
 
 def lm_fit(fr, kin, prior, opt, x, params, lam):

@@ -284,3 +284,98 @@ def test_osl_update_projector_variants(tile, monkeypatch):
     err = rel_l2(xd.cpu().numpy(), ox)
     print(f"projector tile {tile}: OSL pass relL2 {err:.2e}")
     assert err < 1e-5
+
+
+# ---------------------------------------------------------------------------------------------
+# MAP-LM accept decisions.  The accept test compares the change of the voxel objective with a
+# fraction eta of it; where the two lie within the FP32 evaluation error of each other either
+# branch is a result of the method, and the voxel then follows another (equally valid) path.
+# The checks below (a) pin every decision that differs from the oracle's to such a near-tie and
+# (b) compare whole schedules over the voxels whose decisions agreed in every sweep, bounding
+# how many did not.
+
+def low_count_plane_state(n_iter_before=3):
+    """A mid-fit MAP-LM state on a low-count 128x128 plane (the batch recipe's counts per plane):
+    the oracle's image after one OS-EM pass and its maps and lambda after `n_iter_before` LM
+    iterations, all rounded to FP32."""
+    cfg = inputs.scaled(inputs.batch_configs()[3], nz=1, counts=4e5)
+    st = oracle.make_study(cfg)
+    sino = st.sino.astype(np.float64)
+    x, p0, lam0 = oracle.initial_state(st.geom, st.frames, sino)
+    for q in range(cfg.Q):
+        x = oracle.osl_update(st.geom, st.frames, st.kin, st.prior, sino, p0, x, q, cfg.Q, False)
+    x = x.astype(np.float32).astype(np.float64)
+    opt = oracle.LMOptions(n_iter_before, st.lm.tau, st.lm.lam_min, st.lm.lam_max, st.lm.lo, st.lm.hi, st.lm.eta)
+    p, lam = oracle.lm_fit(st.frames, st.kin, st.prior, opt, x, p0, np.zeros_like(lam0))
+    return st, x, p.astype(np.float32).astype(np.float64), lam.astype(np.float32).astype(np.float64)
+
+
+def test_lm_decisions_differ_only_at_near_ties():
+    st, x, p, lam = low_count_plane_state()
+    g, f, k, pr, lm = kcs_objects(st)
+    one = kcs.LMOptions(1, lm.tau, lm.lam_min, lm.lam_max, lm.lo, lm.hi, lm.eta)
+    work = kcs.alloc_workspace(g, M, 0, DEV)
+    pd, ld = dev(p), dev(lam)
+    kcs.kcs_lm_fit(g, f, k, pr, one, dev(x), pd, ld, work)
+    torch.cuda.synchronize()
+    opt1 = oracle.LMOptions(1, st.lm.tau, st.lm.lam_min, st.lm.lam_max, st.lm.lo, st.lm.hi, st.lm.eta)
+    op, ol, phi0, phi1 = oracle.lm_iteration(st.frames, st.kin, st.prior, opt1, x, p, lam, with_objective=True)
+    g_acc = ld.cpu().numpy() < lam
+    o_acc = ol < lam
+    differ = g_acc != o_acc
+    eta = st.lm.eta
+    margin = np.abs(phi1 - phi0 + eta * phi0) / (eta * phi0)
+    print(f"one LM iteration on {x.shape[1]}x{x.shape[2]}: {int(differ.sum())} of {differ.size} decisions differ; "
+          f"their oracle margins {np.sort(margin[differ])[:10]}")
+    assert differ.mean() < 1e-3
+    assert np.all(margin[differ] < 2e-2)
+    gp = pd.cpu().numpy()
+    same = ~differ
+    for i in range(3):
+        e = rel_l2(gp[i][same], op[i][same])
+        print(f"  map {i} over voxels with the same decision: relL2 {e:.2e}")
+        assert e < 1e-4
+
+
+def run_schedule_tracking_decisions(st, n_sweeps):
+    """Both sides sweep by sweep from their own initial states; a voxel whose final lambda of a
+    sweep differs from the oracle's took another accept/reject path in that sweep."""
+    cfg = st.cfg
+    g, f, k, p, lm = kcs_objects(st)
+    sino_d = dev(st.sino)
+    x = torch.empty((g.nz, g.ny, g.nx, M), device=DEV)
+    params = torch.empty((3, g.nz, g.ny, g.nx), device=DEV)
+    lamd = torch.empty((g.nz, g.ny, g.nx), device=DEV)
+    work = kcs.alloc_workspace(g, M, cfg.Q, DEV)
+    kcs.kcs_init_state(g, f, sino_d, inputs.XI0, x, params, lamd, work)
+    sino = st.sino.astype(np.float64)
+    ox, op, ol = oracle.initial_state(st.geom, st.frames, sino)
+    diverged = np.zeros(ol.shape, dtype=bool)
+    for s in range(n_sweeps):
+        kcs.kcs_icm_sweep(g, f, k, p, lm, sino_d, cfg.Q, s, x, params, lamd, work)
+        ox, op, ol = oracle.icm_sweep(st.geom, st.frames, st.kin, st.prior, st.lm, sino, ox, op, ol, cfg.Q, s)
+        diverged |= np.abs(lamd.cpu().numpy() / ol - 1.0) > 1e-3
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), params.cpu().numpy(), ox, op, diverged
+
+
+def test_icm_full_schedule_low_count_decision_consistent():
+    """10 sweeps on two 64x64 planes at the batch recipe's 4e5 counts per plane (noisier fits than
+    the 64x64 single-slice study, so more near-tie decisions)."""
+    cfg = inputs.StudyConfig("low_count_64x64x2", 64, 64, 2, 4.0, 4.0, 60, 64, 4.0, 8e5, 0.1, Q=6, n_sweeps=10,
+                             phantom="brain", n_lesions=3, seed=31)
+    st = oracle.make_study(cfg)
+    gx, gp, ox, op, diverged = run_schedule_tracking_decisions(st, cfg.n_sweeps)
+    act = (ox * (st.frames.t1 - st.frames.t0)).sum(axis=-1)
+    mask = act >= 0.1 * act.max()
+    keep = mask & ~diverged
+    ex = rel_l2(gx, ox)
+    all_maps = [rel_l2(gp[i][mask], op[i][mask]) for i in range(3)]
+    kept_maps = [rel_l2(gp[i][keep], op[i][keep]) for i in range(3)]
+    frac = diverged[mask].mean()
+    print(f"low-count 64x64x2, 10 sweeps: image {ex:.2e}; maps over active voxels {['%.2e' % e for e in all_maps]}; "
+          f"over decision-consistent voxels {['%.2e' % e for e in kept_maps]}; diverged {frac:.4f} of "
+          f"{int(mask.sum())} active voxels")
+    assert ex < 1e-3
+    assert frac < 0.02
+    assert max(kept_maps) < 1e-3
