@@ -90,6 +90,34 @@ def algorithmic_bytes(g, M, Q):
     return {"project": I + 2 * S_q, "osl": 2 * I + S_q + 12 * N, "lm": I + 32 * N}
 
 
+def kernel_source_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1803_10045_amd", "csrc", "*"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(cfg_name, kind):
+    """HBM bytes per launch of step `kind` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary of this workload (scaled by the copy reference), or None when there is none or the
+    kernel sources have changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"sweep_{cfg_name.split('_', 1)[1]}_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    try:
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (IndexError, ValueError):
+        return None
+    if blob.get("source") != kernel_source_hash():
+        return None
+    return blob.get("traffic_bytes_per_launch", {}).get(kind)
+
+
 def cpu_baseline(cfg):
     """The FP64 oracle on a bounded sample of the same workload, extrapolated to one sweep."""
     import numpy as np
@@ -316,12 +344,26 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def run_copy(args):
+    """A plain device-to-device copy of a known size (1 GiB read, 1 GiB written per launch), the
+    reference against which the HBM byte counters of a profiled run are scaled."""
+    import torch
+
+    n = 1 << 28  # FP32 elements: 1 GiB
+    a = torch.ones(n, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(args.steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": 4 * n, "launches": args.steps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--mode", default="sweep", choices=["sweep", "batched", "serve"])
+    ap.add_argument("--mode", default="sweep", choices=["sweep", "batched", "serve", "copy"])
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--rate", type=float, default=4.0)
     ap.add_argument("--budget-gb", type=float, default=250.0)
@@ -336,6 +378,10 @@ def main():
         sys.exit(2)
     if args.mode == "serve":
         run_serve(args)
+        return
+    if args.mode == "copy":
+        args.steps = 4 if args.steps is None else args.steps
+        run_copy(args)
         return
     if args.mode == "batched":
         args.steps = 2 if args.steps is None else args.steps
@@ -398,8 +444,11 @@ def main():
                          "alg_bytes_per_launch": int(nbytes[kind]), "alg_GBps": round(gbps, 1),
                          "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4)}
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_sweep"])
+    traffic = counter_traffic(cfg.name, dom)
     roof = {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["alg_GBps"], "peak": HBM_PEAK_GBPS,
-            "unit": "GB/s", "frac": kernels[dom]["hbm_frac"], "traffic": None}
+            "unit": "GB/s", "frac": kernels[dom]["hbm_frac"],
+            "traffic": None if traffic is None else round(traffic / (kernels[dom]["avg_ms"] * 1e-3) / 1e9, 1),
+            "traffic_bytes_per_launch": traffic, "alg_bytes_per_launch": kernels[dom]["alg_bytes_per_launch"]}
     value = args.steps / (elapsed_ms * 1e-3)
     out = {
         "metric": "ICM sweeps/s",

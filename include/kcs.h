@@ -183,7 +183,7 @@ typedef struct kcs_plan kcs_plan;
 
 enum {
     KCS_PLAN_GRAPH = 1,   /* capture the whole schedule in one HIP graph; kcs_plan_run launches it */
-    KCS_PLAN_AUTOTUNE = 2 /* time the projector variants (ray-driven, 16 or 32 pixel tiles) per shape
+    KCS_PLAN_AUTOTUNE = 2 /* time the projector variants (ray-driven, 16, 32 or 64 pixel tiles) per shape
                              class on these studies and keep the fastest; results are cached in the
                              file named by KCS_TUNE_CACHE when that variable is set */
 };

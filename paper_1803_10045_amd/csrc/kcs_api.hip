@@ -264,11 +264,11 @@ struct Layout {
 };
 
 // Forward projector variant for a geometry: 0 = ray-driven, T = LDS tiles of T x T pixels.
-// Images whose plane exceeds an XCD's L2 use tiles.  KCS_PROJ_TILE overrides (0, 16, 32).
+// Images whose plane exceeds an XCD's L2 use tiles.  KCS_PROJ_TILE overrides (0, 16, 32, 64).
 int projector_tile(const kcs_geometry& g, int M) {
     if (const char* e = getenv("KCS_PROJ_TILE")) {
         const int t = atoi(e);
-        if (t == 0 || t == 16 || (t == 32 && M <= 24)) return t;
+        if (t == 0 || t == 16 || t == 32 || t == 64) return t;
     }
     const double plane_bytes = (double)g.nx * g.ny * M * 4.0;
     return plane_bytes < 2.0 * 1024 * 1024 ? 0 : 16;
@@ -303,7 +303,9 @@ Layout layout(const kcs_geometry* g, int32_t M, int32_t Q) {
             pa.A_q = (int32_t)A_max;
             pa.h = (float)g->pixel_mm;
             pa.du = (float)g->bin_mm;
-            off = align_up(off + std::max(tile_partial_bytes(16, pa, M), tile_partial_bytes(32, pa, M)), 256);
+            off = align_up(off + std::max({tile_partial_bytes(16, pa, M), tile_partial_bytes(32, pa, M),
+                                           tile_partial_bytes(64, pa, M)}),
+                           256);
         }
     }
     L.total = off;
@@ -734,8 +736,7 @@ int autotune(std::vector<StudyPrep>& preps, hipStream_t st) {
         int best = cached_tile(k);
         if (best < 0) {
             float best_ms = 1e30f;
-            for (int T : {0, 16, 32}) {
-                if (T == 32 && k.M > 24) continue;
+            for (int T : {0, 16, 32, 64}) {
                 for (StudyPrep* P : cls) P->T = T;
                 TableBuilder tb;
                 std::vector<const StudyPrep*> ps(cls.begin(), cls.end());

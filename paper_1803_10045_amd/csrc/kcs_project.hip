@@ -10,10 +10,12 @@
 //
 // Tiled variant (large images): the image of one plane does not fit in an XCD's L2, so the
 // ray-driven kernel re-reads it once per angle.  kproj_tile_kernel instead stages one T x T
-// tile (all M frames) in LDS per workgroup and traverses, inside the tile, every subset ray that
-// can meet it, writing one partial line integral per (tile, ray).  kproj_reduce_kernel adds the
-// partials of each ray over the tiles in a fixed order (deterministic, no atomics) and applies
-// the same epilogue.  The image then crosses HBM once per subset.
+// tile (a group of frames) in LDS per workgroup and traverses, inside the tile, every subset ray
+// that can meet it, writing one partial line integral per (tile, ray, frame group).
+// kproj_reduce_kernel adds the partials of each ray over the tiles in a fixed order
+// (deterministic, no atomics) and applies the same epilogue.  The image then crosses HBM once per
+// subset; the partials cost about 2 x image x 16 / T bytes, so larger tiles (with fewer frames
+// staged per workgroup) move less.
 //
 // All kernels take a job source: one study by value, or a device table of studies.
 #include "kcs_device.h"
@@ -81,8 +83,16 @@ __global__ __launch_bounds__(256) void kproj_kernel(Src src) {
     project_ray<M, RATIO>(p, J.x, J.sino, J.out, z, al, ray - al * p.n_bin);
 }
 
+// Frames staged per workgroup and threads per workgroup of the T x T tile variants: the whole
+// record for 16-pixel tiles, half of it for 32 and a quarter for 64, so that the staged tile
+// stays near 100 KB of LDS while larger tiles cut the partial sums (a ray leaves one partial
+// per tile it crosses).  The frame groups of one tile are adjacent work items.
+__host__ __device__ constexpr int tile_frames(int M, int T) { return T == 16 ? M : (T == 32 ? M / 2 : M / 4); }
+__host__ __device__ constexpr int tile_threads(int T) { return T == 16 ? 256 : (T == 32 ? 512 : 1024); }
+
 uint32_t proj_tile_groups(const ProjArgs& p, int T) {
-    return (uint32_t)(((p.nx + T - 1) / T) * ((p.ny + T - 1) / T)) * p.nz;
+    const int groups_per_tile = p.fr.M / tile_frames(p.fr.M, T);
+    return (uint32_t)(((p.nx + T - 1) / T) * ((p.ny + T - 1) / T)) * p.nz * groups_per_tile;
 }
 
 size_t tile_partial_bytes(int T, const ProjArgs& p, int M) {
@@ -90,57 +100,105 @@ size_t tile_partial_bytes(int T, const ProjArgs& p, int M) {
     return (size_t)p.nz * ntx * nty * p.A_q * tile_slots(T, p.h, p.du) * M * sizeof(float);
 }
 
+// FG consecutive floats (FG even; 8-byte aligned, 16-byte aligned when FG % 4 == 0).
+template <int FG>
+__host__ __device__ __forceinline__ void load_frames(const float* __restrict__ p, float (&v)[FG]) {
+    if constexpr (FG % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < FG / 4; ++k) {
+            const float4 q = reinterpret_cast<const float4*>(p)[k];
+            v[4 * k] = q.x;
+            v[4 * k + 1] = q.y;
+            v[4 * k + 2] = q.z;
+            v[4 * k + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < FG / 2; ++k) {
+            const float2 q = reinterpret_cast<const float2*>(p)[k];
+            v[2 * k] = q.x;
+            v[2 * k + 1] = q.y;
+        }
+    }
+}
+
+template <int FG>
+__host__ __device__ __forceinline__ void store_frames(float* __restrict__ p, const float (&v)[FG]) {
+    if constexpr (FG % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < FG / 4; ++k)
+            reinterpret_cast<float4*>(p)[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < FG / 2; ++k) reinterpret_cast<float2*>(p)[k] = make_float2(v[2 * k], v[2 * k + 1]);
+    }
+}
+
+// Partial sums: psum[g][tile][angle][slot][FG] for frame group g, tile (z, ty, tx) in plane-major
+// order; each workgroup writes a dense block.
+__host__ __device__ __forceinline__ size_t partial_offset(int g, size_t n_tiles, size_t tile, int A_q, int al,
+                                                          int slots, int slot, int FG) {
+    return ((((size_t)g * n_tiles + tile) * A_q + al) * slots + slot) * FG;
+}
+
 template <int M, int T, class Src>
-__global__ __launch_bounds__(256) void kproj_tile_kernel(Src src) {
+__global__ __launch_bounds__(tile_threads(T)) void kproj_tile_kernel(Src src) {
+    constexpr int FG = tile_frames(M, T), NG = M / FG, NT = tile_threads(T);
+    static_assert(M % FG == 0 && FG % 2 == 0, "frame groups");
     extern __shared__ float4 lds4[];
     const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
     const ProjJob& J = src.find(w);
     const ProjArgs& p = J.p;
     const int slots = J.slots;
-    AngleRec* sA = reinterpret_cast<AngleRec*>(lds4 + T * T * M / 4);
+    float* tile = reinterpret_cast<float*>(lds4);
+    AngleRec* sA = reinterpret_cast<AngleRec*>(lds4 + T * T * FG / 4);
     const int ntx = (p.nx + T - 1) / T, nty = (p.ny + T - 1) / T;
     const uint32_t lw = w - J.w0;
-    const int z = lw / (ntx * nty);
+    const int g = (int)(lw % NG);
+    const uint32_t tl = lw / NG;
+    const int z = tl / (ntx * nty);
     if (z >= p.nz) return;  // whole workgroup
-    const int tr = lw % (ntx * nty), ty = tr / ntx, tx = tr % ntx;
+    const int tr = tl % (ntx * nty), ty = tr / ntx, tx = tr % ntx;
     const int i0 = tx * T, j0 = ty * T, tw = min(T, p.nx - i0), th = min(T, p.ny - j0);
-    // stage the tile: row r of the tile is tw * M contiguous floats of the image
-    const int row4 = tw * M / 4;
-    const float4* src4 = reinterpret_cast<const float4*>(J.x) + (((size_t)z * p.ny + j0) * p.nx + i0) * (M / 4);
-    for (int e = threadIdx.x; e < th * row4; e += blockDim.x) {
-        const int r = e / row4, c = e - r * row4;
-        lds4[r * (T * M / 4) + c] = src4[(size_t)r * p.nx * (M / 4) + c];
+    // stage frame group g of the tile: pixel (r, c) -> tile[(r * T + c) * FG]
+    const float* src_px = J.x + (((size_t)z * p.ny + j0) * p.nx + i0) * M + g * FG;
+    for (int e = threadIdx.x; e < th * tw; e += NT) {
+        const int r = e / tw, c = e - r * tw;
+        float v[FG];
+        load_frames<FG>(src_px + ((size_t)r * p.nx + c) * M, v);
+        store_frames<FG>(tile + (r * T + c) * FG, v);
     }
-    for (int al = threadIdx.x; al < p.A_q; al += blockDim.x) sA[al] = make_angle(p.q + al * p.Q, p.n_ang, p.ang0, p.h);
+    for (int al = threadIdx.x; al < p.A_q; al += NT) sA[al] = make_angle(p.q + al * p.Q, p.n_ang, p.ang0, p.h);
     __syncthreads();
     const float bc = 0.5f * (float)(p.n_bin - 1);
-    const float* tile = reinterpret_cast<const float*>(lds4);
-    float* out = J.psum + (((size_t)z * nty + ty) * ntx + tx) * (size_t)p.A_q * slots * M;
-    for (int it = threadIdx.x; it < p.A_q * slots; it += blockDim.x) {
+    const size_t n_tiles = (size_t)p.nz * nty * ntx;
+    float* out = J.psum + partial_offset(g, n_tiles, (size_t)z * nty * ntx + tr, p.A_q, 0, slots, 0, FG);
+    for (int it = threadIdx.x; it < p.A_q * slots; it += NT) {
         const int al = it / slots, slot = it - al * slots;
         const AngleRec A = sA[al];
         int b0, b1;
         box_bins(A, i0, j0, tw, th, p.nx, p.ny, p.h, p.inv_du, p.n_bin, b0, b1);
         const int b = b0 + slot;
         if (b > b1) continue;
-        float acc[M];
+        float acc[FG];
 #pragma unroll
-        for (int m = 0; m < M; ++m) acc[m] = 0.0f;
+        for (int m = 0; m < FG; ++m) acc[m] = 0.0f;
         const float u = ((float)b - bc) * p.du;
         const float Xc = u * A.c * p.inv_h + 0.5f * (float)p.nx - (float)i0;
         const float Yc = u * A.s * p.inv_h + 0.5f * (float)p.ny - (float)j0;
         siddon_traverse_box(A, Xc, Yc, tw, th, p.h, [&](int i, int j, float len) {
-            float v[M];
-            load_record<M>(tile + (j * T + i) * M, v);
+            float v[FG];
+            load_frames<FG>(tile + (j * T + i) * FG, v);
 #pragma unroll
-            for (int m = 0; m < M; ++m) acc[m] = fmaf(len, v[m], acc[m]);
+            for (int m = 0; m < FG; ++m) acc[m] = fmaf(len, v[m], acc[m]);
         });
-        store_record<M>(out + (size_t)it * M, acc);
+        store_frames<FG>(out + (size_t)it * FG, acc);
     }
 }
 
 template <int M, int T, bool RATIO, class Src>
 __global__ __launch_bounds__(256) void kproj_reduce_kernel(Src src) {
+    constexpr int FG = tile_frames(M, T), NG = M / FG;
     const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
     const ProjJob& J = src.find(w);
     const ProjArgs& p = J.p;
@@ -155,20 +213,24 @@ __global__ __launch_bounds__(256) void kproj_reduce_kernel(Src src) {
     const int b = ray - al * p.n_bin;
     const AngleRec A = make_angle(p.q + al * p.Q, p.n_ang, p.ang0, p.h);
     const int ntx = (p.nx + T - 1) / T, nty = (p.ny + T - 1) / T;
+    const size_t n_tiles = (size_t)p.nz * nty * ntx;
     float acc[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) acc[m] = 0.0f;
-    const float* pz = J.psum + (size_t)z * nty * ntx * p.A_q * slots * M;
     for (int ty = 0; ty < nty; ++ty) {
         for (int tx = 0; tx < ntx; ++tx) {
             const int i0 = tx * T, j0 = ty * T;
             int b0, b1;
             box_bins(A, i0, j0, min(T, p.nx - i0), min(T, p.ny - j0), p.nx, p.ny, p.h, p.inv_du, p.n_bin, b0, b1);
             if (b < b0 || b > b1 || b - b0 >= slots) continue;
-            float v[M];
-            load_record<M>(pz + (((size_t)(ty * ntx + tx) * p.A_q + al) * slots + (b - b0)) * M, v);
+            const size_t t = ((size_t)z * nty + ty) * ntx + tx;
 #pragma unroll
-            for (int m = 0; m < M; ++m) acc[m] += v[m];
+            for (int g = 0; g < NG; ++g) {
+                float v[FG];
+                load_frames<FG>(J.psum + partial_offset(g, n_tiles, t, p.A_q, al, slots, b - b0, FG), v);
+#pragma unroll
+                for (int m = 0; m < FG; ++m) acc[g * FG + m] += v[m];
+            }
         }
     }
     ray_epilogue<M, RATIO>(p, J.sino, J.out, z, al, b, acc);
@@ -185,8 +247,8 @@ static hipError_t launch_tile(Src src, uint32_t groups, int max_angles, hipStrea
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr_set = true;
     }
-    const size_t lds = (size_t)T * T * M * sizeof(float) + (size_t)max_angles * sizeof(AngleRec);
-    hipLaunchKernelGGL((kproj_tile_kernel<M, T, Src>), dim3(xcd_round_up(groups)), dim3(256), lds, st, src);
+    const size_t lds = (size_t)T * T * tile_frames(M, T) * sizeof(float) + (size_t)max_angles * sizeof(AngleRec);
+    hipLaunchKernelGGL((kproj_tile_kernel<M, T, Src>), dim3(xcd_round_up(groups)), dim3(tile_threads(T)), lds, st, src);
     return hipGetLastError();
 }
 
@@ -213,15 +275,16 @@ static hipError_t launch_direct(Src src, uint32_t groups, bool ratio, hipStream_
 template <int M, class Src>
 static hipError_t project_step(int T, Src src, uint32_t groups, int max_angles, bool ratio, bool reduce_step,
                                hipStream_t st) {
-    if (T == 0) return reduce_step ? hipSuccess : launch_direct<M>(src, groups, ratio, st);
-    if (T == 16)
-        return reduce_step ? launch_reduce<M, 16>(src, groups, ratio, st) : launch_tile<M, 16>(src, groups, max_angles, st);
-    if constexpr (M <= 24) {  // a 32 x 32 tile of 32 frames would exceed the LDS
-        if (T == 32)
-            return reduce_step ? launch_reduce<M, 32>(src, groups, ratio, st)
-                               : launch_tile<M, 32>(src, groups, max_angles, st);
+    switch (T) {
+        case 0: return reduce_step ? hipSuccess : launch_direct<M>(src, groups, ratio, st);
+        case 16:
+            return reduce_step ? launch_reduce<M, 16>(src, groups, ratio, st) : launch_tile<M, 16>(src, groups, max_angles, st);
+        case 32:
+            return reduce_step ? launch_reduce<M, 32>(src, groups, ratio, st) : launch_tile<M, 32>(src, groups, max_angles, st);
+        case 64:
+            return reduce_step ? launch_reduce<M, 64>(src, groups, ratio, st) : launch_tile<M, 64>(src, groups, max_angles, st);
+        default: return hipErrorInvalidValue;
     }
-    return hipErrorInvalidValue;
 }
 
 template <class Src>
@@ -245,7 +308,7 @@ hipError_t launch_project(int M, const float* x, const float* sino, float* out, 
 
 hipError_t launch_project_tiled(int M, int T, const float* x, const float* sino, float* out, float* psum,
                                 const ProjArgs& p, bool ratio, hipStream_t st) {
-    if (T != 16 && T != 32) return hipErrorInvalidValue;
+    if (T != 16 && T != 32 && T != 64) return hipErrorInvalidValue;
     OneJob<ProjJob> src{ProjJob{p, x, sino, out, psum, tile_slots(T, p.h, p.du), 0}};
     hipError_t e = dispatch_project(M, T, src, proj_tile_groups(p, T), p.A_q, ratio, false, st);
     if (e != hipSuccess) return e;

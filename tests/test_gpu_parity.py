@@ -259,10 +259,11 @@ def test_icm_full_size_sampled_planes(cfg_name, n_sweeps):
     compare_icm(gx[:1], gp[:, :1], gl[:1], ox, op, ol, st.frames, f"{cfg_name} full size, plane 0, {n_sweeps} sweeps")
 
 
-@pytest.mark.parametrize("tile", ["0", "16", "32"])
+@pytest.mark.parametrize("tile", ["0", "16", "32", "64"])
 def test_osl_update_projector_variants(tile, monkeypatch):
-    """The OSL update with each forward-projector variant (ray-driven, LDS tiles of 16 or 32
-    pixels with partial sums) on a geometry with ragged edge tiles and uneven subsets."""
+    """The OSL update with each forward-projector variant (ray-driven, LDS tiles of 16, 32 or 64
+    pixels with partial sums; 32 and 64 stage half and a quarter of the frames per workgroup) on a
+    geometry with ragged edge tiles and uneven subsets."""
     monkeypatch.setenv("KCS_PROJ_TILE", tile)
     nx, ny, nz, h, na, nb, du, Q = 150, 130, 2, 2.0, 100, 160, 1.8, 7
     og, kg = geometry_pair(nx, ny, nz, h, na, nb, du, 0.02)
