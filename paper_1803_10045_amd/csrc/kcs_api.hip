@@ -271,7 +271,7 @@ int projector_tile(const kcs_geometry& g, int M) {
         if (t == 0 || t == 16 || t == 32 || t == 64) return t;
     }
     const double plane_bytes = (double)g.nx * g.ny * M * 4.0;
-    return plane_bytes < 2.0 * 1024 * 1024 ? 0 : 16;
+    return plane_bytes < 2.0 * 1024 * 1024 ? 0 : 32;
 }
 
 // Offsets of the workspace regions.  The model TACs of the maps and the ratio buffer (the

@@ -123,7 +123,13 @@ __host__ __device__ __forceinline__ void osl_voxel(const AngleRec* sA, const Osl
 constexpr int kST = 16;               // staged voxel tile: kST x kST voxels, one per thread
 constexpr int kStageBytes = 40 * 1024;  // LDS for the staged bin records of one angle chunk
 
-bool staged_fits(int M, float h, float du) { return tile_slots(kST, h, du) * M * (int)sizeof(float) <= kStageBytes; }
+// LDS stride of a staged bin record in floats: padded by 4 so that the records of nearby bins,
+// which the voxels of a wavefront read at the same time, spread over the banks.
+__host__ __device__ constexpr int stage_record(int M) { return M + 4; }
+
+bool staged_fits(int M, float h, float du) {
+    return tile_slots(kST, h, du) * stage_record(M) * (int)sizeof(float) <= kStageBytes;
+}
 
 uint32_t staged_tile_groups(int nx, int ny, int nz) {
     return (uint32_t)(((nx + kST - 1) / kST) * ((ny + kST - 1) / kST)) * nz;
@@ -131,7 +137,7 @@ uint32_t staged_tile_groups(int nx, int ny, int nz) {
 
 // Angles per staging chunk for this geometry.
 __host__ __device__ inline int stage_chunk(int M, int slots, int A_q) {
-    const int c = kStageBytes / (slots * M * (int)sizeof(float));
+    const int c = kStageBytes / (slots * stage_record(M) * (int)sizeof(float));
     return max(1, min(c, A_q));
 }
 
@@ -158,7 +164,7 @@ __device__ __forceinline__ void staged_gather(const AngleRec* sA, float4* sR, co
             int b0, b1;
             box_bins(sA[al], i0, j0, tw, th, p.nx, p.ny, p.h, p.inv_du, p.n_bin, b0, b1);
             const int b = b0 + slot;
-            if (b <= b1) sR[e] = yz[((size_t)al * p.n_bin + b) * (M / 4) + k];
+            if (b <= b1) sR[rec * (stage_record(M) / 4) + k] = yz[((size_t)al * p.n_bin + b) * (M / 4) + k];
         }
         __syncthreads();
         if (!valid) continue;
@@ -167,11 +173,11 @@ __device__ __forceinline__ void staged_gather(const AngleRec* sA, float4* sR, co
             const AngleRec A = sA[al];
             int b0, b1;
             box_bins(A, i0, j0, tw, th, p.nx, p.ny, p.h, p.inv_du, p.n_bin, b0, b1);
-            const float* ra = reinterpret_cast<const float*>(sR) + (size_t)ac * slots * M;
+            const float* ra = reinterpret_cast<const float*>(sR) + (size_t)ac * slots * stage_record(M);
             pixel_footprint(A, xc, yc, p.n_bin, p.du, p.inv_du, [&](int b, float len) {
                 if (b < b0 || b > b1) return;  // cannot happen: box_bins is a superset
                 float v[M];
-                load_record<M>(ra + (b - b0) * M, v);
+                load_record<M>(ra + (b - b0) * stage_record(M), v);
 #pragma unroll
                 for (int m = 0; m < M; ++m) acc[m] = fmaf(len, v[m], acc[m]);
                 sens += len;

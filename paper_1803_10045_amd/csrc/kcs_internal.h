@@ -57,7 +57,8 @@ struct BoundaryRec {
     float x[kRates];      // l_i t
     float hsw[kRates];    // switch radius kTaylorR0 + kTaylorR1 |l_i t|
     float coef[kRates][kTaylorCoef];
-    float pad[2];
+    float inv_t;          // 1 / t (0 at t = 0)
+    float pad;
 };
 
 struct KinTab {

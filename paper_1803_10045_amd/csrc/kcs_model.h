@@ -77,7 +77,7 @@ __host__ __device__ __forceinline__ void boundary_J(const KinTab& K, const Bound
         return;
     }
     const float y = -R.a * t;
-    const float inv_t = 1.0f / t;
+    const float inv_t = B.inv_t;
     float p2, p2d = 0.0f;
     phi2_pair<DERIV>(y, -R.inv_a * inv_t, p2, p2d);
     const float v = B.t2 * p2;
@@ -210,7 +210,8 @@ __host__ __device__ inline BoundaryRec make_boundary(double t, const double* l) 
             R.coef[i][k - 1] = (float)((m[k] - m[k + 1]) / fact);  // phi2^(k)(x) / k!
         }
     }
-    R.pad[0] = R.pad[1] = 0.0f;
+    R.inv_t = R.t > 0.0f ? 1.0f / R.t : 0.0f;
+    R.pad = 0.0f;
     return R;
 }
 

@@ -84,11 +84,15 @@ __global__ __launch_bounds__(256) void kproj_kernel(Src src) {
 }
 
 // Frames staged per workgroup and threads per workgroup of the T x T tile variants: the whole
-// record for 16-pixel tiles, half of it for 32 and a quarter for 64, so that the staged tile
-// stays near 100 KB of LDS while larger tiles cut the partial sums (a ray leaves one partial
-// per tile it crosses).  The frame groups of one tile are adjacent work items.
-__host__ __device__ constexpr int tile_frames(int M, int T) { return T == 16 ? M : (T == 32 ? M / 2 : M / 4); }
-__host__ __device__ constexpr int tile_threads(int T) { return T == 16 ? 256 : (T == 32 ? 512 : 1024); }
+// record for 16-pixel tiles, half of it for 32 and 4 frames for 64, so that two or more
+// workgroups fit in a CU's LDS (one stages while another traverses) while larger tiles cut the
+// partial sums (a ray leaves one partial per tile it crosses).  The frame groups of one tile
+// are adjacent work items, so they share the tile's cache lines in L2.
+__host__ __device__ constexpr int tile_frames(int M, int T) { return T == 16 ? M : (T == 32 ? M / 2 : 4); }
+__host__ __device__ constexpr int tile_threads(int T) { return T == 16 ? 256 : 512; }
+// LDS row stride of a staged tile in floats: padded by 4 so that vertically adjacent pixels,
+// which parallel rays of a near-horizontal angle read at the same step, fall in other banks.
+__host__ __device__ constexpr int tile_row(int M, int T) { return T * tile_frames(M, T) + 4; }
 
 uint32_t proj_tile_groups(const ProjArgs& p, int T) {
     const int groups_per_tile = p.fr.M / tile_frames(p.fr.M, T);
@@ -143,15 +147,15 @@ __host__ __device__ __forceinline__ size_t partial_offset(int g, size_t n_tiles,
 
 template <int M, int T, class Src>
 __global__ __launch_bounds__(tile_threads(T)) void kproj_tile_kernel(Src src) {
-    constexpr int FG = tile_frames(M, T), NG = M / FG, NT = tile_threads(T);
-    static_assert(M % FG == 0 && FG % 2 == 0, "frame groups");
+    constexpr int FG = tile_frames(M, T), NG = M / FG, NT = tile_threads(T), TS = tile_row(M, T);
+    static_assert(M % FG == 0 && FG % 4 == 0, "frame groups");
     extern __shared__ float4 lds4[];
     const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
     const ProjJob& J = src.find(w);
     const ProjArgs& p = J.p;
     const int slots = J.slots;
     float* tile = reinterpret_cast<float*>(lds4);
-    AngleRec* sA = reinterpret_cast<AngleRec*>(lds4 + T * T * FG / 4);
+    AngleRec* sA = reinterpret_cast<AngleRec*>(lds4 + T * TS / 4);
     const int ntx = (p.nx + T - 1) / T, nty = (p.ny + T - 1) / T;
     const uint32_t lw = w - J.w0;
     const int g = (int)(lw % NG);
@@ -160,13 +164,13 @@ __global__ __launch_bounds__(tile_threads(T)) void kproj_tile_kernel(Src src) {
     if (z >= p.nz) return;  // whole workgroup
     const int tr = tl % (ntx * nty), ty = tr / ntx, tx = tr % ntx;
     const int i0 = tx * T, j0 = ty * T, tw = min(T, p.nx - i0), th = min(T, p.ny - j0);
-    // stage frame group g of the tile: pixel (r, c) -> tile[(r * T + c) * FG]
+    // stage frame group g of the tile: pixel (r, c) -> tile[r * TS + c * FG]
     const float* src_px = J.x + (((size_t)z * p.ny + j0) * p.nx + i0) * M + g * FG;
     for (int e = threadIdx.x; e < th * tw; e += NT) {
         const int r = e / tw, c = e - r * tw;
         float v[FG];
         load_frames<FG>(src_px + ((size_t)r * p.nx + c) * M, v);
-        store_frames<FG>(tile + (r * T + c) * FG, v);
+        store_frames<FG>(tile + r * TS + c * FG, v);
     }
     for (int al = threadIdx.x; al < p.A_q; al += NT) sA[al] = make_angle(p.q + al * p.Q, p.n_ang, p.ang0, p.h);
     __syncthreads();
@@ -188,7 +192,7 @@ __global__ __launch_bounds__(tile_threads(T)) void kproj_tile_kernel(Src src) {
         const float Yc = u * A.s * p.inv_h + 0.5f * (float)p.ny - (float)j0;
         siddon_traverse_box(A, Xc, Yc, tw, th, p.h, [&](int i, int j, float len) {
             float v[FG];
-            load_frames<FG>(tile + (j * T + i) * FG, v);
+            load_frames<FG>(tile + j * TS + i * FG, v);
 #pragma unroll
             for (int m = 0; m < FG; ++m) acc[m] = fmaf(len, v[m], acc[m]);
         });
@@ -247,7 +251,7 @@ static hipError_t launch_tile(Src src, uint32_t groups, int max_angles, hipStrea
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr_set = true;
     }
-    const size_t lds = (size_t)T * T * tile_frames(M, T) * sizeof(float) + (size_t)max_angles * sizeof(AngleRec);
+    const size_t lds = (size_t)T * tile_row(M, T) * sizeof(float) + (size_t)max_angles * sizeof(AngleRec);
     hipLaunchKernelGGL((kproj_tile_kernel<M, T, Src>), dim3(xcd_round_up(groups)), dim3(tile_threads(T)), lds, st, src);
     return hipGetLastError();
 }
