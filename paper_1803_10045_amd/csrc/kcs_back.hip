@@ -4,9 +4,10 @@
 // covers at most ceil(2 w1 / du) + 1 bins; the exact intersection length of each bin's ray with
 // the voxel square (the pixel chord, identical to the Siddon length of that ray in that pixel)
 // weights the bin's M-frame record.  The gather needs no atomics and no transposed system
-// matrix.  A workgroup covers a 16 x 16 voxel tile: for a chunk of the subset's angles it stages
-// in LDS the records of every bin whose ray can meet the tile (at most tile_slots(16) per
-// angle), then each voxel gathers from LDS.
+// matrix.  A workgroup covers a 16 x 32 voxel tile, two vertically adjacent voxels per thread:
+// for a chunk of the subset's angles it stages in LDS the records of every bin whose ray can meet
+// the tile (at most box_slots(16, 32) per angle), then each thread gathers for its voxels from
+// LDS, reading a bin the two share once.
 //
 // OSL update (Eq. 2 with the kinetics-derived potential of Eq. 3, sigma^2 = F / n):
 //   x_new = x * b / D,  b = E_m sum_d p_vd q_dm,  D = n_m (1 + beta (x - F) / max(F, eps_F)),
@@ -120,19 +121,27 @@ __host__ __device__ __forceinline__ void osl_voxel(const AngleRec* sA, const Osl
     osl_finish<M>(a, Fm, x, ((size_t)z * p.ny + j) * p.nx + i, acc, sens);
 }
 
-constexpr int kST = 16;               // staged voxel tile: kST x kST voxels, one per thread
+constexpr int kST = 16;                // staged voxel tile: kST columns, one thread per column ...
+constexpr int kSV = 2;                 // ... and kSV vertically adjacent voxels per thread
+constexpr int kSTY = kST * kSV;        // rows of the staged tile
 constexpr int kStageBytes = 40 * 1024;  // LDS for the staged bin records of one angle chunk
+
+// Bins whose rays can meet a w x hgt pixel box: the box's projection is at most
+// h sqrt(w^2 + hgt^2) wide, and box_bins widens it by a hundredth of a bin on each side.
+__host__ __device__ inline int box_slots(int w, int hgt, float h, float du) {
+    return (int)floorf(sqrtf((float)(w * w + hgt * hgt)) * h / du) + 3;
+}
 
 // LDS stride of a staged bin record in floats: padded by 4 so that the records of nearby bins,
 // which the voxels of a wavefront read at the same time, spread over the banks.
 __host__ __device__ constexpr int stage_record(int M) { return M + 4; }
 
 bool staged_fits(int M, float h, float du) {
-    return tile_slots(kST, h, du) * stage_record(M) * (int)sizeof(float) <= kStageBytes;
+    return box_slots(kST, kSTY, h, du) * stage_record(M) * (int)sizeof(float) <= kStageBytes;
 }
 
 uint32_t staged_tile_groups(int nx, int ny, int nz) {
-    return (uint32_t)(((nx + kST - 1) / kST) * ((ny + kST - 1) / kST)) * nz;
+    return (uint32_t)(((nx + kST - 1) / kST) * ((ny + kSTY - 1) / kSTY)) * nz;
 }
 
 // Angles per staging chunk for this geometry.
@@ -141,20 +150,28 @@ __host__ __device__ inline int stage_chunk(int M, int slots, int A_q) {
     return max(1, min(c, A_q));
 }
 
-// acc_m = sum_{d in S_q} p_vd y_dm and sens for the voxel of this thread in the staged tile
-// (i0, j0) of plane z; all threads of the workgroup must call it (it synchronises).
+// For the kSV voxels (i, j + k) of this thread in the staged tile (i0, j0) of plane z:
+// acc[k]_m = sum_{d in S_q} p_vd y_dm and sens[k] = sum_{d in S_q} p_vd.  All threads of the
+// workgroup must call it (it synchronises).  Per angle the thread walks the union of its voxels'
+// detector footprints once, so a bin shared by the voxels is read from LDS once; each voxel takes
+// exactly the bins, chords and order of its own footprint.
 template <int M>
 __device__ __forceinline__ void staged_gather(const AngleRec* sA, float4* sR, const ProjArgs& p,
-                                              const float* __restrict__ y, int i0, int j0, int z, bool valid, int i,
-                                              int j, float (&acc)[M], float& sens) {
-    const int tw = min(kST, p.nx - i0), th = min(kST, p.ny - j0);
-    const int slots = tile_slots(kST, p.h, p.du);
+                                              const float* __restrict__ y, int i0, int j0, int z, int nvalid, int i,
+                                              int j, float (&acc)[kSV][M], float (&sens)[kSV]) {
+    const int tw = min(kST, p.nx - i0), th = min(kSTY, p.ny - j0);
+    const int slots = box_slots(kST, kSTY, p.h, p.du);
     const int chunk = stage_chunk(M, slots, p.A_q);
+    const float bc = 0.5f * (float)(p.n_bin - 1);
     const float xc = ((float)i - 0.5f * (float)(p.nx - 1)) * p.h;
-    const float yc = ((float)j - 0.5f * (float)(p.ny - 1)) * p.h;
+    float yc[kSV];
 #pragma unroll
-    for (int m = 0; m < M; ++m) acc[m] = 0.0f;
-    sens = 0.0f;
+    for (int k = 0; k < kSV; ++k) {
+        yc[k] = ((float)(j + k) - 0.5f * (float)(p.ny - 1)) * p.h;
+        sens[k] = 0.0f;
+#pragma unroll
+        for (int m = 0; m < M; ++m) acc[k][m] = 0.0f;
+    }
     const float4* yz = reinterpret_cast<const float4*>(y) + (size_t)z * p.A_q * p.n_bin * (M / 4);
     for (int c0 = 0; c0 < p.A_q; c0 += chunk) {
         const int na = min(chunk, p.A_q - c0);
@@ -167,40 +184,68 @@ __device__ __forceinline__ void staged_gather(const AngleRec* sA, float4* sR, co
             if (b <= b1) sR[rec * (stage_record(M) / 4) + k] = yz[((size_t)al * p.n_bin + b) * (M / 4) + k];
         }
         __syncthreads();
-        if (!valid) continue;
+        if (nvalid == 0) continue;
         for (int ac = 0; ac < na; ++ac) {
             const int al = c0 + ac;
             const AngleRec A = sA[al];
             int b0, b1;
             box_bins(A, i0, j0, tw, th, p.nx, p.ny, p.h, p.inv_du, p.n_bin, b0, b1);
             const float* ra = reinterpret_cast<const float*>(sR) + (size_t)ac * slots * stage_record(M);
-            pixel_footprint(A, xc, yc, p.n_bin, p.du, p.inv_du, [&](int b, float len) {
-                if (b < b0 || b > b1) return;  // cannot happen: box_bins is a superset
+            // each voxel's footprint [lo, hi] as in pixel_footprint, and the union of them
+            const float rb = A.w1 * p.inv_du;
+            float tc[kSV];
+            int lo[kSV], hi[kSV], ulo = p.n_bin, uhi = -1;
+#pragma unroll
+            for (int k = 0; k < kSV; ++k) {
+                tc[k] = fmaf(xc, A.c, yc[k] * A.s);
+                const float beta = fmaf(tc[k], p.inv_du, bc);
+                lo[k] = max((int)ceilf(beta - rb), 0);
+                hi[k] = min((int)floorf(beta + rb), p.n_bin - 1);
+                if (k < nvalid) {
+                    ulo = min(ulo, lo[k]);
+                    uhi = max(uhi, hi[k]);
+                }
+            }
+            for (int b = ulo; b <= uhi; ++b) {
+                float len[kSV];
+                bool any = false;
+#pragma unroll
+                for (int k = 0; k < kSV; ++k) {
+                    len[k] = (k < nvalid && b >= lo[k] && b <= hi[k]) ? pixel_chord(A, fmaf((float)b - bc, p.du, -tc[k]))
+                                                                       : 0.0f;
+                    any = any || len[k] > 0.0f;
+                }
+                if (!any || b < b0 || b > b1) continue;  // b outside [b0, b1] cannot happen: box_bins is a superset
                 float v[M];
                 load_record<M>(ra + (b - b0) * stage_record(M), v);
 #pragma unroll
-                for (int m = 0; m < M; ++m) acc[m] = fmaf(len, v[m], acc[m]);
-                sens += len;
-            });
+                for (int k = 0; k < kSV; ++k) {
+                    if (len[k] > 0.0f) {
+#pragma unroll
+                        for (int m = 0; m < M; ++m) acc[k][m] = fmaf(len[k], v[m], acc[k][m]);
+                        sens[k] += len[k];
+                    }
+                }
+            }
         }
     }
 }
 
 struct StagedTile {
     int i0, j0, z, i, j;
-    bool valid;
+    int nvalid;  // voxels (i, j), (i, j + 1), ... of this thread inside the image
 };
 
 __device__ __forceinline__ StagedTile staged_tile(uint32_t w, int nx, int ny, int nz) {
-    const int ntx = (nx + kST - 1) / kST, nty = (ny + kST - 1) / kST;
+    const int ntx = (nx + kST - 1) / kST, nty = (ny + kSTY - 1) / kSTY;
     StagedTile t;
     t.z = w / (ntx * nty);
     const int r = w % (ntx * nty);
-    t.j0 = (r / ntx) * kST;
+    t.j0 = (r / ntx) * kSTY;
     t.i0 = (r % ntx) * kST;
     t.i = t.i0 + (int)(threadIdx.x % kST);
-    t.j = t.j0 + (int)(threadIdx.x / kST);
-    t.valid = t.z < nz && t.i < nx && t.j < ny;
+    t.j = t.j0 + kSV * (int)(threadIdx.x / kST);
+    t.nvalid = (t.z < nz && t.i < nx) ? max(0, min(kSV, ny - t.j)) : 0;
     return t;
 }
 
@@ -215,14 +260,17 @@ __global__ __launch_bounds__(256) void kback_kernel(Src src) {
     AngleRec* sA = reinterpret_cast<AngleRec*>(lds);
     float4* sR = lds + (p.A_q * sizeof(AngleRec) + 15) / 16;
     subset_angles_to_lds(sA, p);
-    float acc[M], sens;
-    staged_gather<M>(sA, sR, p, J.y, t.i0, t.j0, t.z, t.valid, t.i, t.j, acc, sens);
-    if (!t.valid) return;
-    const size_t v = ((size_t)t.z * p.ny + t.j) * p.nx + t.i;
+    float acc[kSV][M], sens[kSV];
+    staged_gather<M>(sA, sR, p, J.y, t.i0, t.j0, t.z, t.nvalid, t.i, t.j, acc, sens);
 #pragma unroll
-    for (int m = 0; m < M; ++m) acc[m] *= p.fr.E[m];
-    store_record<M>(J.b + v * M, acc);
-    if (J.sens) J.sens[v] = sens;
+    for (int k = 0; k < kSV; ++k) {
+        if (k >= t.nvalid) break;
+        const size_t v = ((size_t)t.z * p.ny + t.j + k) * p.nx + t.i;
+#pragma unroll
+        for (int m = 0; m < M; ++m) acc[k][m] *= p.fr.E[m];
+        store_record<M>(J.b + v * M, acc[k]);
+        if (J.sens) J.sens[v] = sens[k];
+    }
 }
 
 template <int M, class Src>
@@ -237,10 +285,13 @@ __global__ __launch_bounds__(256) void kosl_kernel(Src src) {
     AngleRec* sA = reinterpret_cast<AngleRec*>(lds);
     float4* sR = lds + (p.A_q * sizeof(AngleRec) + 15) / 16;
     subset_angles_to_lds(sA, p);
-    float acc[M], sens;
-    staged_gather<M>(sA, sR, p, J.ratio, t.i0, t.j0, t.z, t.valid, t.i, t.j, acc, sens);
-    if (!t.valid) return;
-    osl_finish<M>(a, J.Fm, J.x, ((size_t)t.z * p.ny + t.j) * p.nx + t.i, acc, sens);
+    float acc[kSV][M], sens[kSV];
+    staged_gather<M>(sA, sR, p, J.ratio, t.i0, t.j0, t.z, t.nvalid, t.i, t.j, acc, sens);
+#pragma unroll
+    for (int k = 0; k < kSV; ++k) {
+        if (k >= t.nvalid) break;
+        osl_finish<M>(a, J.Fm, J.x, ((size_t)t.z * p.ny + t.j + k) * p.nx + t.i, acc[k], sens[k]);
+    }
 }
 
 static size_t staged_lds_bytes(int max_angles) {

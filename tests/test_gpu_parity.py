@@ -178,14 +178,17 @@ def test_lm_fit_parity():
     torch.cuda.synchronize()
     op, ol = oracle.lm_fit(st.frames, st.kin, st.prior, st.lm, x, params0, lam0)
     gp = pd.cpu().numpy()
-    mask = st.mask
-    for i in range(3):
-        e = rel_l2(gp[i][mask], op[i][mask])
-        print(f"lm param {i}: relL2 over object {e:.2e}")
-        assert e < 1e-4
-    # same accept/reject history <=> lambda equal up to rounding (it moves by factors of 10)
+    # same accept/reject history <=> lambda equal up to rounding (it moves by factors of 10); an
+    # accept test within rounding of its threshold may go the other way (see the near-tie test)
     same = np.abs(ld.cpu().numpy() / ol - 1.0) < 1e-3
-    assert same.mean() > 0.99
+    mask = st.mask
+    keep = mask & same
+    for i in range(3):
+        e = rel_l2(gp[i][keep], op[i][keep])
+        print(f"lm param {i}: relL2 over object voxels with the oracle's LM path {e:.2e} "
+              f"(all object voxels {rel_l2(gp[i][mask], op[i][mask]):.2e}; other path {int((mask & ~same).sum())})")
+        assert e < 1e-4
+    assert same[mask].mean() > 0.99
 
 
 def compare_icm(gx, gp, glam, ox, op, olam, frames, label, tol_img=1e-3, tol_maps=1e-3):
