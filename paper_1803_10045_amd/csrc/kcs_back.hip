@@ -4,10 +4,11 @@
 // covers at most ceil(2 w1 / du) + 1 bins; the exact intersection length of each bin's ray with
 // the voxel square (the pixel chord, identical to the Siddon length of that ray in that pixel)
 // weights the bin's M-frame record.  The gather needs no atomics and no transposed system
-// matrix.  A workgroup covers a 16 x 32 voxel tile, two vertically adjacent voxels per thread:
-// for a chunk of the subset's angles it stages in LDS the records of every bin whose ray can meet
-// the tile (at most box_slots(16, 32) per angle), then each thread gathers for its voxels from
-// LDS, reading a bin the two share once.
+// matrix.  A workgroup covers a 16 x (16 kSV) voxel tile, kSV vertically adjacent voxels per
+// thread: for a chunk of the subset's angles it stages in LDS the records of every bin whose ray
+// can meet the tile, then each thread gathers for its voxels from LDS, reading a bin its voxels
+// share once.  The kernel is latency-bound, so one voxel per thread and a 20 KB staging buffer
+// (about 7 workgroups per CU) beat two voxels per thread (fewer LDS reads, but 156 VGPRs).
 //
 // OSL update (Eq. 2 with the kinetics-derived potential of Eq. 3, sigma^2 = F / n):
 //   x_new = x * b / D,  b = E_m sum_d p_vd q_dm,  D = n_m (1 + beta (x - F) / max(F, eps_F)),
@@ -122,9 +123,9 @@ __host__ __device__ __forceinline__ void osl_voxel(const AngleRec* sA, const Osl
 }
 
 constexpr int kST = 16;                // staged voxel tile: kST columns, one thread per column ...
-constexpr int kSV = 2;                 // ... and kSV vertically adjacent voxels per thread
+constexpr int kSV = 1;                 // ... and kSV vertically adjacent voxels per thread
 constexpr int kSTY = kST * kSV;        // rows of the staged tile
-constexpr int kStageBytes = 40 * 1024;  // LDS for the staged bin records of one angle chunk
+constexpr int kStageBytes = 20 * 1024;  // LDS for the staged bin records of one angle chunk
 
 // Bins whose rays can meet a w x hgt pixel box: the box's projection is at most
 // h sqrt(w^2 + hgt^2) wide, and box_bins widens it by a hundredth of a bin on each side.
