@@ -49,7 +49,8 @@ extern "C" {
 enum {
     KCS_OK = 0,
     KCS_EINVAL = -1,     /* null pointer, non-positive size, unsorted frames, bad value */
-    KCS_ESHAPE = -2,     /* shape the library does not support (e.g. M not in {8,16,24,32}) */
+    KCS_ESHAPE = -2,     /* shape the library does not support (M not in {8,16,24,32}, more than 1024
+                            angles in a subset, bins more than 6 times narrower than pixels) */
     KCS_EWORKSPACE = -3, /* workspace smaller than kcs_workspace_bytes() */
     KCS_EHIP = -4        /* HIP runtime error (message has hipGetErrorString) */
 };

@@ -102,7 +102,7 @@ int check_subset(const kcs_geometry* g, int32_t q, int32_t Q) {
     if (q < 0 || q >= Q) return fail(KCS_EINVAL, "need 0 <= q < Q");
     if ((g->n_ang + Q - 1) / Q > 1024) return fail(KCS_ESHAPE, "more than 1024 angles in a subset");
     if (!staged_fits(kMaxFrames, (float)g->pixel_mm, (float)g->bin_mm))
-        return fail(KCS_ESHAPE, "bins more than 16 times narrower than pixels are not supported");
+        return fail(KCS_ESHAPE, "bins more than 6 times narrower than pixels are not supported");
     return KCS_OK;
 }
 
