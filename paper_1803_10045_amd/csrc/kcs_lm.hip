@@ -21,6 +21,34 @@ __host__ __device__ __forceinline__ float huber(float t, float d) {
     return at <= d ? 0.5f * t * t : d * at - 0.5f * d * d;
 }
 
+// Weighted Huber energy sum_k w_k sum_p H(q_p - xi_kp) over the in-plane 8-neighbours k of voxel
+// (i, j, z) in the maps xi (neighbours outside the image dropped), and the gradient terms
+// psi_p = sum_k w_k clip(q_p - xi_kp, -delta_p, delta_p).
+__host__ __device__ __forceinline__ float neighbour_energy(const float* __restrict__ xi, const LmArgs& a, int i, int j,
+                                                           int z, size_t N, float q0, float q1, float q2,
+                                                           float (&psi)[3]) {
+    const size_t plane = (size_t)a.nx * a.ny;
+    float e = 0.0f;
+    psi[0] = psi[1] = psi[2] = 0.0f;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            if (dy == 0 && dx == 0) continue;
+            const int jj = j + dy, ii = i + dx;
+            if (jj < 0 || jj >= a.ny || ii < 0 || ii >= a.nx) continue;
+            const size_t u = (size_t)z * plane + (size_t)jj * a.nx + ii;
+            const float w = (dy == 0 || dx == 0) ? 1.0f : 0.70710678118654752f;
+            const float d0 = q0 - xi[u], d1 = q1 - xi[N + u], d2 = q2 - xi[2 * N + u];
+            psi[0] += w * fminf(fmaxf(d0, -a.delta[0]), a.delta[0]);
+            psi[1] += w * fminf(fmaxf(d1, -a.delta[1]), a.delta[1]);
+            psi[2] += w * fminf(fmaxf(d2, -a.delta[2]), a.delta[2]);
+            e += w * (huber(d0, a.delta[0]) + huber(d1, a.delta[1]) + huber(d2, a.delta[2]));
+        }
+    }
+    return e;
+}
+
 // F0 (the model at the current parameters) is kept in a per-thread strip `F0` of M floats with
 // stride `fs` (LDS on the device), so the frame loops can stay rolled.
 template <int M>
@@ -35,34 +63,11 @@ __host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, 
     const float* xv = x + v * M;
     const float p0 = xi_in[v], p1 = xi_in[N + v], p2 = xi_in[2 * N + v];
 
-    // neighbours from the previous maps
-    float nb[8][3], wn[8];
-    int nn = 0;
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy) {
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-            if (dy == 0 && dx == 0) continue;
-            const int jj = j + dy, ii = i + dx;
-            const bool in = jj >= 0 && jj < a.ny && ii >= 0 && ii < a.nx;
-            const size_t u = in ? (size_t)z * plane + (size_t)jj * a.nx + ii : v;
-            nb[nn][0] = xi_in[u];
-            nb[nn][1] = xi_in[N + u];
-            nb[nn][2] = xi_in[2 * N + u];
-            wn[nn] = in ? ((dy == 0 || dx == 0) ? 1.0f : 0.70710678118654752f) : 0.0f;
-            ++nn;
-        }
-    }
-    float psi[3] = {0.0f, 0.0f, 0.0f}, e0 = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const float d0 = p0 - nb[k][0], d1 = p1 - nb[k][1], d2 = p2 - nb[k][2];
-        psi[0] += wn[k] * fminf(fmaxf(d0, -a.delta[0]), a.delta[0]);
-        psi[1] += wn[k] * fminf(fmaxf(d1, -a.delta[1]), a.delta[1]);
-        psi[2] += wn[k] * fminf(fmaxf(d2, -a.delta[2]), a.delta[2]);
-        e0 += wn[k] * (huber(d0, a.delta[0]) + huber(d1, a.delta[1]) + huber(d2, a.delta[2]));
-    }
-
+    // Huber terms over the neighbours of the previous maps: psi (gradient) and e0 (energy) at the
+    // current parameters.  The neighbours are read again for the trial energy below instead of
+    // being held in registers through the model evaluations (they are cache hits).
+    float psi[3] = {0.0f, 0.0f, 0.0f};
+    const float e0 = neighbour_energy(xi_in, a, i, j, z, N, p0, p1, p2, psi);
     // model, Jacobian and normal equations at the current parameters
     float A00 = 0, A01 = 0, A02 = 0, A11 = 0, A12 = 0, A22 = 0, g0 = 0, g1 = 0, g2 = 0, rr = 0;
     model_frames<M, true, false>(a.fr, *K, p0, p1, p2, [&](int m, float F, float j0, float j1, float j2) {
@@ -106,11 +111,8 @@ __host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, 
     const float q1 = fminf(fmaxf(p1 + z1 * s1, a.lo[1]), a.hi[1]);
     const float q2 = fminf(fmaxf(p2 + z2 * s2, a.lo[2]), a.hi[2]);
 
-    float e1 = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-        e1 += wn[k] * (huber(q0 - nb[k][0], a.delta[0]) + huber(q1 - nb[k][1], a.delta[1]) +
-                       huber(q2 - nb[k][2], a.delta[2]));
+    float unused[3];
+    const float e1 = neighbour_energy(xi_in, a, i, j, z, N, q0, q1, q2, unused);
 
     float dphi = 0.0f;
     model_frames<M, false, false>(a.fr, *K, q0, q1, q2, [&](int m, float F, float, float, float) {
