@@ -136,7 +136,7 @@ __host__ __device__ __forceinline__ void model_frames(const FrameTab& FT, const 
     const VoxelRates R = voxel_rates(K, k2, k3);
     const float g = FT.one_minus_vb;
     float Jprev = 0.0f, dJprev = 0.0f;
-#pragma unroll(UNROLL ? M : 1)
+#pragma unroll(UNROLL ? M : 2)
     for (int m = 0; m < M; ++m) {
         if (m == 0 || !FT.contiguous) boundary_J<DERIV>(K, K.b[K.i0[m]], R, Jprev, dJprev);
         float J1, dJ1 = 0.0f;
