@@ -89,14 +89,14 @@ __host__ __device__ __forceinline__ float pixel_chord(const AngleRec& A, float t
 }
 
 // Incremental Siddon traversal of a ray through an nx x ny box of pixels: calls
-// visit(i, j, len) for every pixel the ray crosses, in order, with the exact intersection length
-// (mm).  Coordinates are in pixel units relative to the box corner; (Xc, Yc) is the ray's foot
+// visit(j * row + i * col, len) for every pixel (i, j) the ray crosses, in order, with the exact
+// intersection length (mm).  Coordinates are in pixel units relative to the box corner; (Xc, Yc) is the ray's foot
 // point and the point at parameter lam (pixel units of length) is (Xc - lam s, Yc + lam c).  The
 // crossing parameters are re-derived from the grid-line index at each step, so the rounding
 // error does not accumulate along the ray.  At most nx + ny + 2 steps.
 template <class Visit>
 __host__ __device__ __forceinline__ void siddon_traverse_box(const AngleRec& A, float Xc, float Yc, int nx, int ny,
-                                                             float h, Visit&& visit) {
+                                                             float h, int row, int col, Visit&& visit) {
     float lin = -3.0e38f, lout = 3.0e38f;
     bool hit = true;
     if (A.s != 0.0f) {
@@ -140,21 +140,26 @@ __host__ __device__ __forceinline__ void siddon_traverse_box(const AngleRec& A, 
     const float ly0 = sj ? (by0 - Yc) * A.inv_c : 3.0e38f;
     float lx = lx0, ly = ly0, lcur = lin;
     int kx = 0, ky = 0;
+    // the pixel's element offset j * row + i * col is stepped along with (i, j): no multiplies
+    int idx = j * row + i * col;
+    const int dix = si * col, diy = sj * row;
     const int max_steps = nx + ny + 2;
     for (int step = 0; step < max_steps; ++step) {
         const float lnext = fminf(fminf(lx, ly), lout);
-        visit(i, j, (lnext - lcur) * h);
+        visit(idx, (lnext - lcur) * h);
         if (lnext >= lout) break;
         if (lx <= ly) {
             i += si;
+            idx += dix;
             ++kx;
             lx = fmaf((float)kx, dlx, lx0);
         } else {
             j += sj;
+            idx += diy;
             ++ky;
             ly = fmaf((float)ky, dly, ly0);
         }
-        if (i < 0 || i >= nx || j < 0 || j >= ny) break;
+        if ((unsigned)i >= (unsigned)nx || (unsigned)j >= (unsigned)ny) break;
         lcur = lnext;
     }
 }
@@ -162,10 +167,10 @@ __host__ __device__ __forceinline__ void siddon_traverse_box(const AngleRec& A, 
 // Ray (A, u) through the whole nx x ny grid of h-pixels centred on the origin.
 template <class Visit>
 __host__ __device__ __forceinline__ void siddon_traverse(const AngleRec& A, float u, int nx, int ny, float h,
-                                                         float inv_h, Visit&& visit) {
+                                                         float inv_h, int row, int col, Visit&& visit) {
     const float Xc = u * A.c * inv_h + 0.5f * (float)nx;
     const float Yc = u * A.s * inv_h + 0.5f * (float)ny;
-    siddon_traverse_box(A, Xc, Yc, nx, ny, h, visit);
+    siddon_traverse_box(A, Xc, Yc, nx, ny, h, row, col, visit);
 }
 
 // Slots reserved per (tile, angle) for the bins whose rays can meet a T x T pixel tile:

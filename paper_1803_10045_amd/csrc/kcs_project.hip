@@ -57,9 +57,9 @@ __host__ __device__ __forceinline__ void project_ray(const ProjArgs& p, const fl
     for (int m = 0; m < M; ++m) acc[m] = 0.0f;
     const float u = ((float)b - 0.5f * (float)(p.n_bin - 1)) * p.du;
     const float* plane = x + (size_t)z * p.nx * p.ny * M;
-    siddon_traverse(A, u, p.nx, p.ny, p.h, p.inv_h, [&](int i, int j, float len) {
+    siddon_traverse(A, u, p.nx, p.ny, p.h, p.inv_h, p.nx * M, M, [&](int idx, float len) {
         float v[M];
-        load_record<M>(plane + ((size_t)j * p.nx + i) * M, v);
+        load_record<M>(plane + idx, v);
 #pragma unroll
         for (int m = 0; m < M; ++m) acc[m] = fmaf(len, v[m], acc[m]);
     });
@@ -190,9 +190,9 @@ __global__ __launch_bounds__(tile_threads(T)) void kproj_tile_kernel(Src src) {
         const float u = ((float)b - bc) * p.du;
         const float Xc = u * A.c * p.inv_h + 0.5f * (float)p.nx - (float)i0;
         const float Yc = u * A.s * p.inv_h + 0.5f * (float)p.ny - (float)j0;
-        siddon_traverse_box(A, Xc, Yc, tw, th, p.h, [&](int i, int j, float len) {
+        siddon_traverse_box(A, Xc, Yc, tw, th, p.h, TS, FG, [&](int idx, float len) {
             float v[FG];
-            load_frames<FG>(tile + j * TS + i * FG, v);
+            load_frames<FG>(tile + idx, v);
 #pragma unroll
             for (int m = 0; m < FG; ++m) acc[m] = fmaf(len, v[m], acc[m]);
         });
