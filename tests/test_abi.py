@@ -102,3 +102,31 @@ def test_priors_and_lm_options_validated():
     misaligned = kcs.lib().kcs_lm_fit(ctypes.byref(gc), ctypes.byref(fc), ctypes.byref(k), ctypes.byref(good_p),
                                       ctypes.byref(good_l), vp(256), vp(256), vp(256), vp(260), work, None)
     assert misaligned == kcs.KCS_EINVAL
+
+
+def c_study(g, f, Q=4, s0=0, s1=1, ptr=256, work_bytes=1 << 32):
+    k = kcs.Kinetics(**inputs.FENG, vb=inputs.VB)
+    p = kcs.Prior(0.1, 0.01, 0.1, (1e-3,) * 3)
+    lm = kcs.LMOptions(5, 1e-3, 1e-8, 1e8, inputs.LM_LO, inputs.LM_HI, 1e-3)
+    vp = ctypes.c_void_p
+    return kcs.c_study(g.c(), f.c(), k.c(), p.c(), lm.c(), Q, s0, s1, vp(ptr), vp(ptr), vp(ptr), vp(ptr), vp(ptr),
+                       work_bytes)
+
+
+@pytest.mark.parametrize("bad", ["none", "sweeps", "subsets", "null", "workspace", "second"])
+def test_plan_create_rejects_bad_studies(bad):
+    """Plans validate every study on the host and name the one at fault; nothing is launched."""
+    g, f = geometry(), frames()
+    good = c_study(g, f)
+    studies = {"none": [], "sweeps": [c_study(g, f, s0=3, s1=2)], "subsets": [c_study(g, f, Q=0)],
+               "null": [c_study(g, f, ptr=0)], "workspace": [c_study(g, f, work_bytes=16)],
+               "second": [good, c_study(g, f, Q=61)]}[bad]
+    arr = (kcs.c_study * max(len(studies), 1))(*studies)
+    out = ctypes.c_void_p()
+    rc = kcs.lib().kcs_plan_create(arr, len(studies), 0, None, ctypes.byref(out))
+    assert rc in (kcs.KCS_EINVAL, kcs.KCS_EWORKSPACE)
+    assert out.value is None
+    msg = kcs.kcs_last_error()
+    if bad != "none":
+        assert ("study 1" if bad == "second" else "study 0") in msg
+    kcs.lib().kcs_plan_destroy(None)  # NULL is ignored

@@ -1,0 +1,199 @@
+"""GPU parity on the shapes and inputs the headline studies do not exercise: the other supported
+frame counts (8, 16, 32), frame schedules with gaps, one subset and one angle per subset, tiny
+and ragged grids, a single detector bin, and sinograms with no counts."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1803_10045_amd import inputs
+from kcs_testutil import geometry_pair, make_image, rel_l2
+
+torch = pytest.importorskip("torch")
+from paper_1803_10045_amd import kcs  # noqa: E402
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+DEV = "cuda"
+KIN = oracle.Kinetics(**inputs.FENG, vb=inputs.VB)
+KK = kcs.Kinetics(KIN.A1, KIN.A2, KIN.A3, KIN.l1, KIN.l2, KIN.l3, KIN.vb)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def schedule(M, gaps=False, seed=0):
+    """M frames over 40 min with durations growing geometrically (optionally with gaps between
+    frames), per-frame scale proportional to the duration and a small background."""
+    d = np.geomspace(1.0, 12.0, M)
+    d *= 40.0 / d.sum()
+    t1 = np.cumsum(d)
+    t0 = np.concatenate([[0.0], t1[:-1]])
+    if gaps:
+        t0 = t0 + 0.1 * d  # each frame starts after a pause of a tenth of its length
+    rng = np.random.default_rng(seed)
+    E = (t1 - t0) * rng.uniform(0.5, 2.0)
+    r = rng.uniform(0.01, 0.3, M)
+    return oracle.Frames(t0, t1, E, r), kcs.Frames(t0, t1, E, r)
+
+
+def maps_in_box(shape, seed):
+    rng = np.random.default_rng(seed)
+    lo, hi = np.array([0.02, 0.03, 0.0]), np.array([0.3, 0.4, 0.2])
+    m = lo[:, None] + (hi - lo)[:, None] * rng.random((3, int(np.prod(shape))))
+    return m.reshape((3,) + shape).astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("M,gaps", [(8, False), (16, True), (32, False)])
+def test_other_frame_counts(M, gaps):
+    """Projection, model TAC, OSL update with the prior and one MAP-LM call for M frames."""
+    ofr, kfr = schedule(M, gaps, seed=M)
+    nx, ny, nz, Q = 40, 36, 2, 5
+    og, kg = geometry_pair(nx, ny, nz, 2.0, 45, 38, 2.2, 0.03)
+    x = make_image(nz, ny, nx, M, seed=M)
+    ref = oracle.expected_counts(og, ofr, x, 1, Q)
+    out = torch.empty(ref.shape, device=DEV)
+    kcs.kcs_project(kg, kfr, dev(x), 1, Q, out)
+    maps = maps_in_box((nz, ny, nx), seed=M + 1)
+    F = torch.empty((nz * ny * nx, M), device=DEV)
+    J = torch.empty((nz * ny * nx, M, 3), device=DEV)
+    kcs.kcs_model_tac(kfr, KK, dev(maps.reshape(3, -1)), F, J, kcs.alloc_workspace(None, M, 0, DEV))
+    torch.cuda.synchronize()
+    e_proj = rel_l2(out.cpu().numpy(), ref)
+    Fo, Jo = oracle.model_tac(maps.reshape(3, -1).T, ofr.t0, ofr.t1, KIN, jacobian=True)
+    e_F = rel_l2(F.cpu().numpy(), Fo)
+    e_J = rel_l2(J.cpu().numpy(), Jo)
+    # OSL update with the prior on, against a Poisson sinogram of the image
+    rng = np.random.default_rng(M + 2)
+    sino = rng.poisson(ofr.E * oracle.forward(og, x) + ofr.r).astype(np.float32).astype(np.float64)
+    prior_o = oracle.Prior(beta_kp=0.1, eps_F=0.01, beta_h=0.1, delta=(1e-3,) * 3, kp_on=True)
+    prior_k = kcs.Prior(0.1, 0.01, 0.1, (1e-3,) * 3, True)
+    xd = dev(x)
+    work = kcs.alloc_workspace(kg, M, Q, DEV)
+    ox = x.copy()
+    for q in range(Q):
+        kcs.kcs_osl_update(kg, kfr, KK, prior_k, dev(sino), dev(maps), q, Q, xd, work)
+        ox = oracle.osl_update(og, ofr, KIN, prior_o, sino, maps, ox, q, Q, True)
+    torch.cuda.synchronize()
+    e_osl = rel_l2(xd.cpu().numpy(), ox)
+    # one MAP-LM call from the true maps' TACs with noise; compare the voxels on the oracle's path
+    xt = (Fo.reshape(nz, ny, nx, M) * (1 + 0.05 * rng.standard_normal((nz, ny, nx, M)))).astype(np.float32)
+    xt = xt.astype(np.float64)
+    p0 = np.stack([np.full((nz, ny, nx), v) for v in inputs.XI0])
+    lm_o = oracle.LMOptions(5, inputs.LM_TAU, inputs.LM_LAM_MIN, inputs.LM_LAM_MAX, inputs.LM_LO, inputs.LM_HI,
+                            inputs.LM_ETA)
+    lm_k = kcs.LMOptions(5, inputs.LM_TAU, inputs.LM_LAM_MIN, inputs.LM_LAM_MAX, inputs.LM_LO, inputs.LM_HI,
+                         inputs.LM_ETA)
+    pd, ld = dev(p0), dev(np.zeros((nz, ny, nx)))
+    kcs.kcs_lm_fit(kg, kfr, KK, prior_k, lm_k, dev(xt), pd, ld, kcs.alloc_workspace(kg, M, 0, DEV))
+    torch.cuda.synchronize()
+    op, ol = oracle.lm_fit(ofr, KIN, prior_o, lm_o, xt, p0, np.zeros((nz, ny, nx)))
+    same = np.abs(ld.cpu().numpy() / ol - 1.0) < 1e-3
+    gp = pd.cpu().numpy()
+    e_lm = max(rel_l2(gp[i][same], op[i][same]) for i in range(3))
+    print(f"M={M} gaps={gaps}: project {e_proj:.2e} F {e_F:.2e} J {e_J:.2e} OSL pass {e_osl:.2e} "
+          f"LM {e_lm:.2e} ({(~same).sum()} voxels on another path)")
+    assert e_proj < 1e-5 and e_F < 1e-5 and e_J < 1e-4 and e_osl < 1e-5
+    assert e_lm < 1e-4 and same.mean() > 0.99
+
+
+@pytest.mark.parametrize("Q", [1, 45])
+def test_one_subset_and_one_angle_per_subset(Q):
+    """Q = 1 (plain EM step over all angles) and Q = n_ang (one angle per subset)."""
+    ofr, kfr = schedule(24, seed=5)
+    nx, ny, nz = 33, 29, 1
+    og, kg = geometry_pair(nx, ny, nz, 2.0, 45, 36, 2.0, 0.0)
+    x = make_image(nz, ny, nx, 24, seed=6)
+    rng = np.random.default_rng(7)
+    sino = rng.poisson(ofr.E * oracle.forward(og, x) + ofr.r).astype(np.float32).astype(np.float64)
+    maps = maps_in_box((nz, ny, nx), seed=8)
+    prior_o = oracle.Prior(beta_kp=0.1, eps_F=0.01, beta_h=0.1, delta=(1e-3,) * 3, kp_on=False)
+    prior_k = kcs.Prior(0.1, 0.01, 0.1, (1e-3,) * 3, False)
+    xd = dev(x)
+    work = kcs.alloc_workspace(kg, 24, Q, DEV)
+    ox = x.copy()
+    for q in range(Q):
+        kcs.kcs_osl_update(kg, kfr, KK, prior_k, dev(sino), dev(maps), q, Q, xd, work)
+        ox = oracle.osl_update(og, ofr, KIN, prior_o, sino, maps, ox, q, Q, False)
+    torch.cuda.synchronize()
+    err = rel_l2(xd.cpu().numpy(), ox)
+    print(f"Q={Q}: OSL pass relL2 {err:.2e}")
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("shape", [(3, 2, 1, 3, 4), (5, 7, 3, 6, 1), (1, 1, 2, 4, 3)])
+def test_tiny_grids(shape):
+    """Grids of a few pixels, a single detector bin, and odd plane counts: projection, back
+    projection and one whole ICM sweep."""
+    nx, ny, nz, na, nb = shape
+    ofr, kfr = schedule(24, seed=9)
+    og, kg = geometry_pair(nx, ny, nz, 3.0, na, nb, 4.0, 0.1)
+    x = make_image(nz, ny, nx, 24, seed=10)
+    ref = oracle.expected_counts(og, ofr, x, 0, 1)
+    out = torch.empty(ref.shape, device=DEV)
+    kcs.kcs_project(kg, kfr, dev(x), 0, 1, out)
+    y = np.random.default_rng(11).random(ref.shape).astype(np.float32).astype(np.float64)
+    b = torch.empty((nz, ny, nx, 24), device=DEV)
+    kcs.kcs_backproject(kg, kfr, dev(y), 0, 1, b)
+    torch.cuda.synchronize()
+    e_p = rel_l2(out.cpu().numpy(), ref)
+    e_b = rel_l2(b.cpu().numpy(), ofr.E * oracle.back(og, y, 0, 1))
+    # one ICM sweep from the initial state
+    sino = np.random.default_rng(12).poisson(ofr.E * oracle.forward(og, x) + ofr.r).astype(np.float64)
+    prior_o = oracle.Prior(beta_kp=0.1, eps_F=0.01, beta_h=0.1, delta=(1e-3,) * 3, kp_on=True)
+    prior_k = kcs.Prior(0.1, 0.01, 0.1, (1e-3,) * 3, True)
+    lm_o = oracle.LMOptions(5, inputs.LM_TAU, inputs.LM_LAM_MIN, inputs.LM_LAM_MAX, inputs.LM_LO, inputs.LM_HI,
+                            inputs.LM_ETA)
+    lm_k = kcs.LMOptions(5, inputs.LM_TAU, inputs.LM_LAM_MIN, inputs.LM_LAM_MAX, inputs.LM_LO, inputs.LM_HI,
+                         inputs.LM_ETA)
+    Q = min(2, na)
+    sd = dev(sino)
+    xg = torch.empty((nz, ny, nx, 24), device=DEV)
+    pg = torch.empty((3, nz, ny, nx), device=DEV)
+    lg = torch.empty((nz, ny, nx), device=DEV)
+    work = kcs.alloc_workspace(kg, 24, Q, DEV)
+    kcs.kcs_init_state(kg, kfr, sd, inputs.XI0, xg, pg, lg, work)
+    for s in range(2):
+        kcs.kcs_icm_sweep(kg, kfr, KK, prior_k, lm_k, sd, Q, s, xg, pg, lg, work)
+    torch.cuda.synchronize()
+    ox, op, ol = oracle.icm(og, ofr, KIN, prior_o, lm_o, sino, Q, 2)
+    e_x = rel_l2(xg.cpu().numpy(), ox)
+    same = np.abs(lg.cpu().numpy() / ol - 1.0) < 1e-3
+    e_m = max(rel_l2(pg.cpu().numpy()[i][same], op[i][same]) for i in range(3)) if same.any() else 0.0
+    print(f"{shape}: project {e_p:.2e} back {e_b:.2e} sweep image {e_x:.2e} maps {e_m:.2e} "
+          f"({(~same).sum()} of {same.size} voxels on another LM path)")
+    assert e_p < 1e-5 and e_b < 1e-5 and e_x < 1e-3 and e_m < 1e-3
+
+
+def test_sinogram_without_counts():
+    """No measured counts: the flat initial image is floored at one count per frame, the first
+    update sends every seen voxel to zero, and later sweeps stay finite and equal the oracle's."""
+    ofr, kfr = schedule(24, seed=13)
+    nx, ny, nz, Q = 24, 20, 1, 3
+    og, kg = geometry_pair(nx, ny, nz, 2.0, 30, 26, 2.0, 0.0)
+    sino = np.zeros((nz, 30, 26, 24))
+    prior_o = oracle.Prior(beta_kp=0.1, eps_F=0.01, beta_h=0.1, delta=(1e-3,) * 3, kp_on=True)
+    prior_k = kcs.Prior(0.1, 0.01, 0.1, (1e-3,) * 3, True)
+    lm_o = oracle.LMOptions(5, inputs.LM_TAU, inputs.LM_LAM_MIN, inputs.LM_LAM_MAX, inputs.LM_LO, inputs.LM_HI,
+                            inputs.LM_ETA)
+    lm_k = kcs.LMOptions(5, inputs.LM_TAU, inputs.LM_LAM_MIN, inputs.LM_LAM_MAX, inputs.LM_LO, inputs.LM_HI,
+                         inputs.LM_ETA)
+    sd = dev(sino)
+    xg = torch.empty((nz, ny, nx, 24), device=DEV)
+    pg = torch.empty((3, nz, ny, nx), device=DEV)
+    lg = torch.empty((nz, ny, nx), device=DEV)
+    work = kcs.alloc_workspace(kg, 24, Q, DEV)
+    kcs.kcs_init_state(kg, kfr, sd, inputs.XI0, xg, pg, lg, work)
+    for s in range(2):
+        kcs.kcs_icm_sweep(kg, kfr, KK, prior_k, lm_k, sd, Q, s, xg, pg, lg, work)
+    torch.cuda.synchronize()
+    ox, op, ol = oracle.icm(og, ofr, KIN, prior_o, lm_o, sino, Q, 2)
+    gx, gp = xg.cpu().numpy(), pg.cpu().numpy()
+    assert np.all(np.isfinite(gx)) and np.all(np.isfinite(gp))
+    assert np.array_equal(gx == 0.0, ox == 0.0)
+    assert np.abs(gx - ox).max() <= 1e-6 * max(np.abs(ox).max(), 1.0)
+    em = [rel_l2(gp[i], op[i]) for i in range(3)]
+    print(f"empty sinogram: image max {gx.max():.3e}, maps relL2 {['%.2e' % e for e in em]}")
+    # with no activity K1 goes to its bound and k2, k3 are not determined by the data: only K1 is
+    # held to the schedule tolerance, the others to finite values near the oracle's
+    assert em[0] < 1e-3 and max(em) < 1e-2
