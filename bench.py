@@ -118,6 +118,22 @@ def counter_traffic(cfg_name, kind):
     return blob.get("traffic_bytes_per_launch", {}).get(kind)
 
 
+def counter_valu(cfg_name, kind):
+    """VALU instructions per launch of step `kind` from the committed instruction-counter summary
+    of this workload, or None (missing, or kernel sources changed since)."""
+    path = os.path.join(ROOT, "profiles", f"sweep_{cfg_name.split('_', 1)[1]}_instruction_counters.md")
+    if not os.path.exists(path):
+        return None
+    try:
+        blob = json.loads(open(path).read().split("```json", 1)[1].split("```", 1)[0])
+    except (IndexError, ValueError):
+        return None
+    if blob.get("source") != kernel_source_hash():
+        return None
+    n = blob.get("valu_instructions_per_launch", {}).get(kind)
+    return None if n is None else (n, blob["valu_cycles_per_instruction"], blob["simds"], blob["clock_hz"])
+
+
 def cpu_baseline(cfg):
     """The FP64 oracle on a bounded sample of the same workload, extrapolated to one sweep."""
     import numpy as np
@@ -453,6 +469,11 @@ def main():
             "unit": "GB/s", "frac": kernels[dom]["hbm_frac"],
             "traffic": None if traffic is None else round(traffic / (kernels[dom]["avg_ms"] * 1e-3) / 1e9, 1),
             "traffic_bytes_per_launch": traffic, "alg_bytes_per_launch": kernels[dom]["alg_bytes_per_launch"]}
+    valu = counter_valu(cfg.name, dom)
+    if valu is not None:
+        # the same kernel against the VALU issue rate (wave instructions x cycles / (SIMDs x clock))
+        n, cyc, simds, clk = valu
+        roof["valu_issue_frac"] = round(n * cyc / (simds * clk) / (kernels[dom]["avg_ms"] * 1e-3), 3)
     value = args.steps / (elapsed_ms * 1e-3)
     out = {
         "metric": "ICM sweeps/s",
