@@ -50,6 +50,19 @@ __device__ __forceinline__ void subset_angles_to_lds(AngleRec* sA, const ProjArg
     __syncthreads();
 }
 
+// The same, plus per angle the range of bins whose rays can meet the pixel box (i0, j0, tw, th).
+__device__ __forceinline__ void subset_angles_bins_to_lds(AngleRec* sA, int2* sBB, const ProjArgs& p, int i0, int j0,
+                                                          int tw, int th) {
+    for (int al = threadIdx.x; al < p.A_q; al += blockDim.x) {
+        const AngleRec A = make_angle(p.q + al * p.Q, p.n_ang, p.ang0, p.h);
+        sA[al] = A;
+        int b0, b1;
+        box_bins(A, i0, j0, tw, th, p.nx, p.ny, p.h, p.inv_du, p.n_bin, b0, b1);
+        sBB[al] = make_int2(b0, b1);
+    }
+    __syncthreads();
+}
+
 // acc_m = sum_{d in S_q} p_vd y_dm and sens = sum_{d in S_q} p_vd for voxel (i, j, z).
 template <int M>
 __host__ __device__ __forceinline__ void gather(const AngleRec* sA, const ProjArgs& p, const float* __restrict__ y, int i, int j,
@@ -157,10 +170,9 @@ __host__ __device__ inline int stage_chunk(int M, int slots, int A_q) {
 // detector footprints once, so a bin shared by the voxels is read from LDS once; each voxel takes
 // exactly the bins, chords and order of its own footprint.
 template <int M>
-__device__ __forceinline__ void staged_gather(const AngleRec* sA, float4* sR, const ProjArgs& p,
-                                              const float* __restrict__ y, int i0, int j0, int z, int nvalid, int i,
-                                              int j, float (&acc)[kSV][M], float (&sens)[kSV]) {
-    const int tw = min(kST, p.nx - i0), th = min(kSTY, p.ny - j0);
+__device__ __forceinline__ void staged_gather(const AngleRec* sA, const int2* sBB, float4* sR, const ProjArgs& p,
+                                              const float* __restrict__ y, int z, int nvalid, int i, int j,
+                                              float (&acc)[kSV][M], float (&sens)[kSV]) {
     const int slots = box_slots(kST, kSTY, p.h, p.du);
     const int chunk = stage_chunk(M, slots, p.A_q);
     const float bc = 0.5f * (float)(p.n_bin - 1);
@@ -177,20 +189,23 @@ __device__ __forceinline__ void staged_gather(const AngleRec* sA, float4* sR, co
     for (int c0 = 0; c0 < p.A_q; c0 += chunk) {
         const int na = min(chunk, p.A_q - c0);
         __syncthreads();  // previous chunk consumed
-        for (int e = threadIdx.x; e < na * slots * (M / 4); e += blockDim.x) {
-            const int k = e % (M / 4), rec = e / (M / 4), al = c0 + rec / slots, slot = rec % slots;
-            int b0, b1;
-            box_bins(sA[al], i0, j0, tw, th, p.nx, p.ny, p.h, p.inv_du, p.n_bin, b0, b1);
-            const int b = b0 + slot;
-            if (b <= b1) sR[rec * (stage_record(M) / 4) + k] = yz[((size_t)al * p.n_bin + b) * (M / 4) + k];
+        for (int rec = threadIdx.x; rec < na * slots; rec += blockDim.x) {
+            const int ar = rec / slots, al = c0 + ar, slot = rec - ar * slots;
+            const int2 bb = sBB[al];
+            const int b = bb.x + slot;
+            if (b > bb.y) continue;
+            const float4* src = yz + ((size_t)al * p.n_bin + b) * (M / 4);
+            float4* dst = sR + rec * (stage_record(M) / 4);
+#pragma unroll
+            for (int k = 0; k < M / 4; ++k) dst[k] = src[k];
         }
         __syncthreads();
         if (nvalid == 0) continue;
         for (int ac = 0; ac < na; ++ac) {
             const int al = c0 + ac;
             const AngleRec A = sA[al];
-            int b0, b1;
-            box_bins(A, i0, j0, tw, th, p.nx, p.ny, p.h, p.inv_du, p.n_bin, b0, b1);
+            const int2 bb = sBB[al];
+            const int b0 = bb.x, b1 = bb.y;
             const float* ra = reinterpret_cast<const float*>(sR) + (size_t)ac * slots * stage_record(M);
             // each voxel's footprint [lo, hi] as in pixel_footprint, and the union of them
             const float rb = A.w1 * p.inv_du;
@@ -259,10 +274,11 @@ __global__ __launch_bounds__(256) void kback_kernel(Src src) {
     const StagedTile t = staged_tile(w - J.w0, p.nx, p.ny, p.nz);
     if (t.z >= p.nz) return;  // whole workgroup
     AngleRec* sA = reinterpret_cast<AngleRec*>(lds);
-    float4* sR = lds + (p.A_q * sizeof(AngleRec) + 15) / 16;
-    subset_angles_to_lds(sA, p);
+    int2* sBB = reinterpret_cast<int2*>(lds + (p.A_q * sizeof(AngleRec) + 15) / 16);
+    float4* sR = lds + (p.A_q * sizeof(AngleRec) + 15) / 16 + (p.A_q * sizeof(int2) + 15) / 16;
+    subset_angles_bins_to_lds(sA, sBB, p, t.i0, t.j0, min(kST, p.nx - t.i0), min(kSTY, p.ny - t.j0));
     float acc[kSV][M], sens[kSV];
-    staged_gather<M>(sA, sR, p, J.y, t.i0, t.j0, t.z, t.nvalid, t.i, t.j, acc, sens);
+    staged_gather<M>(sA, sBB, sR, p, J.y, t.z, t.nvalid, t.i, t.j, acc, sens);
 #pragma unroll
     for (int k = 0; k < kSV; ++k) {
         if (k >= t.nvalid) break;
@@ -284,10 +300,11 @@ __global__ __launch_bounds__(256) void kosl_kernel(Src src) {
     const StagedTile t = staged_tile(w - J.w0, p.nx, p.ny, p.nz);
     if (t.z >= p.nz) return;  // whole workgroup
     AngleRec* sA = reinterpret_cast<AngleRec*>(lds);
-    float4* sR = lds + (p.A_q * sizeof(AngleRec) + 15) / 16;
-    subset_angles_to_lds(sA, p);
+    int2* sBB = reinterpret_cast<int2*>(lds + (p.A_q * sizeof(AngleRec) + 15) / 16);
+    float4* sR = lds + (p.A_q * sizeof(AngleRec) + 15) / 16 + (p.A_q * sizeof(int2) + 15) / 16;
+    subset_angles_bins_to_lds(sA, sBB, p, t.i0, t.j0, min(kST, p.nx - t.i0), min(kSTY, p.ny - t.j0));
     float acc[kSV][M], sens[kSV];
-    staged_gather<M>(sA, sR, p, J.ratio, t.i0, t.j0, t.z, t.nvalid, t.i, t.j, acc, sens);
+    staged_gather<M>(sA, sBB, sR, p, J.ratio, t.z, t.nvalid, t.i, t.j, acc, sens);
 #pragma unroll
     for (int k = 0; k < kSV; ++k) {
         if (k >= t.nvalid) break;
@@ -296,7 +313,7 @@ __global__ __launch_bounds__(256) void kosl_kernel(Src src) {
 }
 
 static size_t staged_lds_bytes(int max_angles) {
-    return (max_angles * sizeof(AngleRec) + 15) / 16 * 16 + kStageBytes;
+    return (max_angles * sizeof(AngleRec) + 15) / 16 * 16 + (max_angles * sizeof(int2) + 15) / 16 * 16 + kStageBytes;
 }
 
 template <class K>
