@@ -105,18 +105,22 @@ __host__ __device__ __forceinline__ void osl_finish(const OslArgs& a, const floa
                                                     float* __restrict__ x, size_t v, const float (&acc)[M],
                                                     float sens) {
     if (!(sens > 0.0f)) return;  // no ray of this subset sees the voxel: keep x
+    const float inv_sens = 1.0f / sens;
     float xv[M];
     load_record<M>(x + v * M, xv);
-    const float inv_sens = 1.0f / sens;
     if (a.kp) {
-        // x b / (n (1 + beta (x - F) / Fe)) = x (acc / sens) Fe / (Fe + beta (x - F)),  Fe = max(F, eps_F)
+        // x b / (n (1 + beta (x - F) / Fe)) = x (acc / sens) Fe / (Fe + beta (x - F)),  Fe = max(F, eps_F);
+        // the denominator is at least (1 - beta) Fe > 0, so one hardware reciprocal (1 ulp) serves.
         float F[M];
         load_record<M>(Fm + v * M, F);
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const float fe = fmaxf(F[m], a.eps_F);
             const float den = fmaf(a.beta_kp, xv[m] - F[m], fe);
-            xv[m] = fast_div(xv[m] * acc[m] * inv_sens * fe, den);
+            xv[m] = xv[m] * acc[m] * inv_sens * fe * recip(den);
+            // eight frames at a time: keeps the scheduler from holding every quotient live at
+            // once (all 24 at once need 93 VGPRs and cost two waves per SIMD)
+            if (m % 8 == 7) __builtin_amdgcn_sched_barrier(0);
         }
     } else {
 #pragma unroll

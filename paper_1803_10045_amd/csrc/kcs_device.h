@@ -65,12 +65,12 @@ __host__ __device__ inline AngleRec make_angle(int a, int n_ang, double ang0, fl
     return A;
 }
 
-// a / b with one reciprocal (about 2 ulp): ratios in the update steps.
-__host__ __device__ __forceinline__ float fast_div(float a, float b) {
+// 1 / b from the hardware reciprocal (1 ulp) for normal positive b; exact on the host.
+__host__ __device__ __forceinline__ float recip(float b) {
 #if defined(__HIP_DEVICE_COMPILE__)
-    return __fdividef(a, b);
+    return __builtin_amdgcn_rcpf(b);
 #else
-    return a / b;
+    return 1.0f / b;
 #endif
 }
 
@@ -116,13 +116,11 @@ __host__ __device__ __forceinline__ void siddon_traverse_box(const AngleRec& A, 
     if (!(hit && lout > lin)) return;
     // first pixel: the one the ray enters, judged by its direction of travel
     int i, j, si = 0, sj = 0;
-    float dlx = 0.0f, dly = 0.0f;
     if (A.s != 0.0f) {
         const float Xin = Xc - lin * A.s;
         si = A.s < 0.0f ? 1 : -1;
         i = si > 0 ? (int)floorf(Xin) : (int)ceilf(Xin) - 1;
         i = min(max(i, 0), nx - 1);
-        dlx = fabsf(A.inv_s);
     } else {
         i = (int)floorf(Xc);
     }
@@ -131,35 +129,37 @@ __host__ __device__ __forceinline__ void siddon_traverse_box(const AngleRec& A, 
         sj = A.c > 0.0f ? 1 : -1;
         j = sj > 0 ? (int)floorf(Yin) : (int)ceilf(Yin) - 1;
         j = min(max(j, 0), ny - 1);
-        dly = fabsf(A.inv_c);
     } else {
         j = (int)floorf(Yc);
     }
     const float bx0 = (float)(si > 0 ? i + 1 : i), by0 = (float)(sj > 0 ? j + 1 : j);
-    const float lx0 = si ? (Xc - bx0) * A.inv_s : 3.0e38f;
-    const float ly0 = sj ? (by0 - Yc) * A.inv_c : 3.0e38f;
-    float lx = lx0, ly = ly0, lcur = lin;
-    int kx = 0, ky = 0;
-    // the pixel's element offset j * row + i * col is stepped along with (i, j): no multiplies
+    // crossing parameters in mm of path (pixel units times h), re-derived from the number of
+    // grid lines crossed; a step updates both axes with selects, so the wave does not branch
+    const float lx0 = si ? (Xc - bx0) * (A.inv_s * h) : 3.0e38f;
+    const float ly0 = sj ? (by0 - Yc) * (A.inv_c * h) : 3.0e38f;
+    const float dlx = si ? fabsf(A.inv_s * h) : 0.0f, dly = sj ? fabsf(A.inv_c * h) : 0.0f;
+    float lx = lx0, ly = ly0, lcur = lin * h;
+    // The walk ends at the first grid line of the box's far edges, taken from the same formula
+    // as the steps: fma(k, d, l0) is monotone in k, so no step can pass that line and (i, j)
+    // stays inside the box without a bounds test (in exact arithmetic this is lout).
+    const int nlx = si > 0 ? nx - 1 - i : (si < 0 ? i : 0);
+    const int nly = sj > 0 ? ny - 1 - j : (sj < 0 ? j : 0);
+    const float lend = fminf(lout * h, fminf(fmaf((float)nlx, dlx, lx0), fmaf((float)nly, dly, ly0)));
+    float kx = 0.0f, ky = 0.0f;
+    // the pixel's offset j * row + i * col is stepped along with (i, j): no multiplies
     int idx = j * row + i * col;
     const int dix = si * col, diy = sj * row;
     const int max_steps = nx + ny + 2;
     for (int step = 0; step < max_steps; ++step) {
-        const float lnext = fminf(fminf(lx, ly), lout);
-        visit(idx, (lnext - lcur) * h);
-        if (lnext >= lout) break;
-        if (lx <= ly) {
-            i += si;
-            idx += dix;
-            ++kx;
-            lx = fmaf((float)kx, dlx, lx0);
-        } else {
-            j += sj;
-            idx += diy;
-            ++ky;
-            ly = fmaf((float)ky, dly, ly0);
-        }
-        if ((unsigned)i >= (unsigned)nx || (unsigned)j >= (unsigned)ny) break;
+        const float lnext = fminf(fminf(lx, ly), lend);
+        visit(idx, lnext - lcur);
+        if (lnext >= lend) break;
+        const bool sx = lx <= ly;
+        kx += sx ? 1.0f : 0.0f;
+        ky += sx ? 0.0f : 1.0f;
+        idx += sx ? dix : diy;
+        lx = fmaf(kx, dlx, lx0);
+        ly = fmaf(ky, dly, ly0);
         lcur = lnext;
     }
 }

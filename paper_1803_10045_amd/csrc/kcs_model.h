@@ -51,6 +51,18 @@ __host__ __device__ __forceinline__ void phi2_pair(float y, float inv_y, float& 
     }
 }
 
+// p = sum_{j<N} c[j] d^j and (if DERIV) q = dp/dd by Horner's scheme.
+template <int N, bool DERIV>
+__host__ __device__ __forceinline__ void poly_horner(const float* c, float d, float& p, float& q) {
+    p = c[N - 1];
+    q = 0.0f;
+#pragma unroll
+    for (int j = N - 2; j >= 0; --j) {
+        if (DERIV) q = (j == N - 2) ? p : fmaf(q, d, p);
+        p = fmaf(p, d, c[j]);
+    }
+}
+
 // Voxel constants of the model.
 struct VoxelRates {
     float a, inv_a;
@@ -95,31 +107,20 @@ __host__ __device__ __forceinline__ void boundary_J(const KinTab& K, const Bound
                 if (DERIV) dJp = -(dJi[0] + Jp) * R.inv_b[0];
             }
         } else {
-            // series in d = y - l_i t:  J_i = t^3 sum c_{j+1} d^j,  dJ_i = -t^4 sum (j+1) c_{j+2} d^j,
-            // J'_1 = t^4 sum c_{j+2} d^j,  dJ'_1 = -t^5 sum (j+1) c_{j+3} d^j
+            // series in d = y - l_i t, with c_k the k-th coefficient (1-based):
+            //   J_i = t^3 S(d),  S = sum_{j=0..kTaylor} c_{j+1} d^j,   dJ_i = -t^4 S'(d),
+            //   J'_1 = t^4 T(d), T = sum_{j=0..kTaylor} c_{j+2} d^j,   dJ'_1 = -t^5 T'(d);
+            // Horner's scheme carries each polynomial's derivative along.
             const float d = -h;
             const float* c = B.coef[i];
-            float s1 = c[kTaylor - 1];
-#pragma unroll
-            for (int j = kTaylor - 2; j >= 0; --j) s1 = fmaf(s1, d, c[j]);
-            Ji[i] = B.t3 * s1;
-            if (DERIV) {
-                float s2 = kTaylor * c[kTaylor];
-#pragma unroll
-                for (int j = kTaylor - 2; j >= 0; --j) s2 = fmaf(s2, d, (j + 1) * c[j + 1]);
-                dJi[i] = -B.t4 * s2;
-            }
+            float s, ds;
+            poly_horner<kTaylor + 1, DERIV>(c, d, s, ds);
+            Ji[i] = B.t3 * s;
+            if (DERIV) dJi[i] = -B.t4 * ds;
             if (i == 0) {
-                float s3 = c[kTaylor];
-#pragma unroll
-                for (int j = kTaylor - 2; j >= 0; --j) s3 = fmaf(s3, d, c[j + 1]);
-                Jp = B.t4 * s3;
-                if (DERIV) {
-                    float s4 = kTaylor * c[kTaylor + 1];
-#pragma unroll
-                    for (int j = kTaylor - 2; j >= 0; --j) s4 = fmaf(s4, d, (j + 1) * c[j + 2]);
-                    dJp = -B.t5 * s4;
-                }
+                poly_horner<kTaylor + 1, DERIV>(c + 1, d, s, ds);
+                Jp = B.t4 * s;
+                if (DERIV) dJp = -B.t5 * ds;
             }
         }
     }

@@ -190,9 +190,10 @@ __global__ __launch_bounds__(tile_threads(T)) void kproj_tile_kernel(Src src) {
         const float u = ((float)b - bc) * p.du;
         const float Xc = u * A.c * p.inv_h + 0.5f * (float)p.nx - (float)i0;
         const float Yc = u * A.s * p.inv_h + 0.5f * (float)p.ny - (float)j0;
-        siddon_traverse_box(A, Xc, Yc, tw, th, p.h, TS, FG, [&](int idx, float len) {
+        // pixel offsets in bytes, so that the LDS address needs no scaling per crossing
+        siddon_traverse_box(A, Xc, Yc, tw, th, p.h, TS * 4, FG * 4, [&](int off, float len) {
             float v[FG];
-            load_frames<FG>(tile + idx, v);
+            load_frames<FG>(reinterpret_cast<const float*>(reinterpret_cast<const char*>(tile) + off), v);
 #pragma unroll
             for (int m = 0; m < FG; ++m) acc[m] = fmaf(len, v[m], acc[m]);
         });
