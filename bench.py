@@ -372,10 +372,17 @@ def run_copy(args):
     n = 1 << 28  # FP32 elements: 1 GiB
     a = torch.ones(n, device="cuda:0")
     b = torch.empty_like(a)
+    b.copy_(a)  # warm-up
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
     for _ in range(args.steps):
         b.copy_(a)
+    t1.record()
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_per_launch": 4 * n, "launches": args.steps}), flush=True)
+    ms = t0.elapsed_time(t1) / args.steps
+    print(json.dumps({"copy_bytes_per_launch": 4 * n, "launches": args.steps + 1, "avg_ms": round(ms, 4),
+                      "read_plus_write_GBps": round(2 * 4 * n / ms / 1e6, 1)}), flush=True)
 
 
 def main():

@@ -4,11 +4,11 @@
 // covers at most ceil(2 w1 / du) + 1 bins; the exact intersection length of each bin's ray with
 // the voxel square (the pixel chord, identical to the Siddon length of that ray in that pixel)
 // weights the bin's M-frame record.  The gather needs no atomics and no transposed system
-// matrix.  A workgroup covers a 16 x (16 kSV) voxel tile, kSV vertically adjacent voxels per
-// thread: for a chunk of the subset's angles it stages in LDS the records of every bin whose ray
-// can meet the tile, then each thread gathers for its voxels from LDS, reading a bin its voxels
-// share once.  The kernel is latency-bound, so one voxel per thread and a 20 KB staging buffer
-// (about 7 workgroups per CU) beat two voxels per thread (fewer LDS reads, but 156 VGPRs).
+// matrix.  A workgroup covers a 16 x 16 voxel tile, one voxel per thread: for a chunk of the
+// subset's angles it stages in LDS the records of every bin whose ray can meet the tile, then
+// each thread gathers its voxel's footprint from LDS.  The OSL update streams the image and the
+// model TACs through HBM at about the device's copy rate; their loads are issued before the
+// gather so that the latency hides behind it.
 //
 // OSL update (Eq. 2 with the kinetics-derived potential of Eq. 3, sigma^2 = F / n):
 //   x_new = x * b / D,  b = E_m sum_d p_vd q_dm,  D = n_m (1 + beta (x - F) / max(F, eps_F)),
@@ -98,29 +98,32 @@ __host__ __device__ __forceinline__ void backproject_voxel(const AngleRec* sA, c
     if (sens_out) sens_out[v] = sens;
 }
 
-// OSL-KP update of voxel (i, j, z).  Fm: model TACs of the current maps [N][M] (only read when
-// the prior is on).
+// Loads voxel v's TAC (xv) and, when the prior is on, its model TAC from Fm [N][M] (F).  The
+// update kernels issue these loads before their gather, so that the HBM latency is hidden
+// behind it.
 template <int M>
-__host__ __device__ __forceinline__ void osl_finish(const OslArgs& a, const float* __restrict__ Fm,
-                                                    float* __restrict__ x, size_t v, const float (&acc)[M],
+__host__ __device__ __forceinline__ void osl_load(const OslArgs& a, const float* __restrict__ Fm,
+                                                  const float* __restrict__ x, size_t v, float (&xv)[M],
+                                                  float (&F)[M]) {
+    load_record<M>(x + v * M, xv);
+    if (a.kp) load_record<M>(Fm + v * M, F);
+}
+
+// OSL-KP update of voxel v from its gathered acc, sens and the loaded xv, F; writes x.
+template <int M>
+__host__ __device__ __forceinline__ void osl_finish(const OslArgs& a, float* __restrict__ x, size_t v,
+                                                    float (&xv)[M], const float (&F)[M], const float (&acc)[M],
                                                     float sens) {
     if (!(sens > 0.0f)) return;  // no ray of this subset sees the voxel: keep x
     const float inv_sens = 1.0f / sens;
-    float xv[M];
-    load_record<M>(x + v * M, xv);
     if (a.kp) {
         // x b / (n (1 + beta (x - F) / Fe)) = x (acc / sens) Fe / (Fe + beta (x - F)),  Fe = max(F, eps_F);
-        // the denominator is at least (1 - beta) Fe > 0, so one hardware reciprocal (1 ulp) serves.
-        float F[M];
-        load_record<M>(Fm + v * M, F);
+        // the denominator is at least (1 - beta) Fe > 0, so one hardware reciprocal (1 ulp) serves
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const float fe = fmaxf(F[m], a.eps_F);
             const float den = fmaf(a.beta_kp, xv[m] - F[m], fe);
             xv[m] = xv[m] * acc[m] * inv_sens * fe * recip(den);
-            // eight frames at a time: keeps the scheduler from holding every quotient live at
-            // once (all 24 at once need 93 VGPRs and cost two waves per SIMD)
-            if (m % 8 == 7) __builtin_amdgcn_sched_barrier(0);
         }
     } else {
 #pragma unroll
@@ -134,14 +137,14 @@ __host__ __device__ __forceinline__ void osl_voxel(const AngleRec* sA, const Osl
                                                    const float* __restrict__ Fm, float* __restrict__ x, int i, int j,
                                                    int z) {
     const ProjArgs& p = a.g;
-    float acc[M], sens;
+    const size_t v = ((size_t)z * p.ny + j) * p.nx + i;
+    float acc[M], sens, xv[M], F[M];
+    osl_load<M>(a, Fm, x, v, xv, F);
     gather<M>(sA, p, ratio, i, j, z, acc, sens);
-    osl_finish<M>(a, Fm, x, ((size_t)z * p.ny + j) * p.nx + i, acc, sens);
+    osl_finish<M>(a, x, v, xv, F, acc, sens);
 }
 
-constexpr int kST = 16;                // staged voxel tile: kST columns, one thread per column ...
-constexpr int kSV = 1;                 // ... and kSV vertically adjacent voxels per thread
-constexpr int kSTY = kST * kSV;        // rows of the staged tile
+constexpr int kST = 16;                // staged voxel tile: kST x kST voxels, one per thread
 constexpr int kStageBytes = 20 * 1024;  // LDS for the staged bin records of one angle chunk
 
 // Bins whose rays can meet a w x hgt pixel box: the box's projection is at most
@@ -155,11 +158,11 @@ __host__ __device__ inline int box_slots(int w, int hgt, float h, float du) {
 __host__ __device__ constexpr int stage_record(int M) { return M + 4; }
 
 bool staged_fits(int M, float h, float du) {
-    return box_slots(kST, kSTY, h, du) * stage_record(M) * (int)sizeof(float) <= kStageBytes;
+    return box_slots(kST, kST, h, du) * stage_record(M) * (int)sizeof(float) <= kStageBytes;
 }
 
 uint32_t staged_tile_groups(int nx, int ny, int nz) {
-    return (uint32_t)(((nx + kST - 1) / kST) * ((ny + kSTY - 1) / kSTY)) * nz;
+    return (uint32_t)(((nx + kST - 1) / kST) * ((ny + kST - 1) / kST)) * nz;
 }
 
 // Angles per staging chunk for this geometry.
@@ -168,27 +171,21 @@ __host__ __device__ inline int stage_chunk(int M, int slots, int A_q) {
     return max(1, min(c, A_q));
 }
 
-// For the kSV voxels (i, j + k) of this thread in the staged tile (i0, j0) of plane z:
-// acc[k]_m = sum_{d in S_q} p_vd y_dm and sens[k] = sum_{d in S_q} p_vd.  All threads of the
-// workgroup must call it (it synchronises).  Per angle the thread walks the union of its voxels'
-// detector footprints once, so a bin shared by the voxels is read from LDS once; each voxel takes
-// exactly the bins, chords and order of its own footprint.
+// For the voxel (i, j) of this thread in the staged tile (i0, j0) of plane z (valid: inside the
+// image): acc_m = sum_{d in S_q} p_vd y_dm and sens = sum_{d in S_q} p_vd.  All threads of the
+// workgroup must call it (it synchronises).
 template <int M>
 __device__ __forceinline__ void staged_gather(const AngleRec* sA, const int2* sBB, float4* sR, const ProjArgs& p,
-                                              const float* __restrict__ y, int z, int nvalid, int i, int j,
-                                              float (&acc)[kSV][M], float (&sens)[kSV]) {
-    const int slots = box_slots(kST, kSTY, p.h, p.du);
+                                              const float* __restrict__ y, int z, bool valid, int i, int j,
+                                              float (&acc)[M], float& sens) {
+    const int slots = box_slots(kST, kST, p.h, p.du);
     const int chunk = stage_chunk(M, slots, p.A_q);
     const float bc = 0.5f * (float)(p.n_bin - 1);
     const float xc = ((float)i - 0.5f * (float)(p.nx - 1)) * p.h;
-    float yc[kSV];
+    const float yc = ((float)j - 0.5f * (float)(p.ny - 1)) * p.h;
+    sens = 0.0f;
 #pragma unroll
-    for (int k = 0; k < kSV; ++k) {
-        yc[k] = ((float)(j + k) - 0.5f * (float)(p.ny - 1)) * p.h;
-        sens[k] = 0.0f;
-#pragma unroll
-        for (int m = 0; m < M; ++m) acc[k][m] = 0.0f;
-    }
+    for (int m = 0; m < M; ++m) acc[m] = 0.0f;
     const float4* yz = reinterpret_cast<const float4*>(y) + (size_t)z * p.A_q * p.n_bin * (M / 4);
     for (int c0 = 0; c0 < p.A_q; c0 += chunk) {
         const int na = min(chunk, p.A_q - c0);
@@ -204,48 +201,30 @@ __device__ __forceinline__ void staged_gather(const AngleRec* sA, const int2* sB
             for (int k = 0; k < M / 4; ++k) dst[k] = src[k];
         }
         __syncthreads();
-        if (nvalid == 0) continue;
+        if (!valid) continue;
         for (int ac = 0; ac < na; ++ac) {
             const int al = c0 + ac;
             const AngleRec A = sA[al];
             const int2 bb = sBB[al];
-            const int b0 = bb.x, b1 = bb.y;
-            const float* ra = reinterpret_cast<const float*>(sR) + (size_t)ac * slots * stage_record(M);
-            // each voxel's footprint [lo, hi] as in pixel_footprint, and the union of them
+            // the voxel's footprint as in pixel_footprint, clipped to the staged bins [b0, b1]
+            // (they hold every bin whose ray meets the tile, so the clip removes no chord)
+            const float tc = fmaf(xc, A.c, yc * A.s);
+            const float beta = fmaf(tc, p.inv_du, bc);
             const float rb = A.w1 * p.inv_du;
-            float tc[kSV];
-            int lo[kSV], hi[kSV], ulo = p.n_bin, uhi = -1;
-#pragma unroll
-            for (int k = 0; k < kSV; ++k) {
-                tc[k] = fmaf(xc, A.c, yc[k] * A.s);
-                const float beta = fmaf(tc[k], p.inv_du, bc);
-                lo[k] = max((int)ceilf(beta - rb), 0);
-                hi[k] = min((int)floorf(beta + rb), p.n_bin - 1);
-                if (k < nvalid) {
-                    ulo = min(ulo, lo[k]);
-                    uhi = max(uhi, hi[k]);
-                }
-            }
-            for (int b = ulo; b <= uhi; ++b) {
-                float len[kSV];
-                bool any = false;
-#pragma unroll
-                for (int k = 0; k < kSV; ++k) {
-                    len[k] = (k < nvalid && b >= lo[k] && b <= hi[k]) ? pixel_chord(A, fmaf((float)b - bc, p.du, -tc[k]))
-                                                                       : 0.0f;
-                    any = any || len[k] > 0.0f;
-                }
-                if (!any || b < b0 || b > b1) continue;  // b outside [b0, b1] cannot happen: box_bins is a superset
+            const int lo = max((int)ceilf(beta - rb), bb.x);
+            const int hi = min((int)floorf(beta + rb), bb.y);
+            const float* rec = reinterpret_cast<const float*>(sR) + ((size_t)ac * slots + (lo - bb.x)) * stage_record(M);
+            float fb = (float)lo - bc;  // exact: integers and half-integers
+            // every lane holds the same angle, so the chord form is a uniform branch
+            const bool oblique = __builtin_amdgcn_readfirstlane(A.axis) == 0;
+            for (int b = lo; b <= hi; ++b, fb += 1.0f, rec += stage_record(M)) {
+                const float t = fmaf(fb, p.du, -tc);
+                const float len = oblique ? chord_oblique(A, t) : chord_axis(A, t);
                 float v[M];
-                load_record<M>(ra + (b - b0) * stage_record(M), v);
+                load_record<M>(rec, v);
 #pragma unroll
-                for (int k = 0; k < kSV; ++k) {
-                    if (len[k] > 0.0f) {
-#pragma unroll
-                        for (int m = 0; m < M; ++m) acc[k][m] = fmaf(len[k], v[m], acc[k][m]);
-                        sens[k] += len[k];
-                    }
-                }
+                for (int m = 0; m < M; ++m) acc[m] = fmaf(len, v[m], acc[m]);
+                sens += len;
             }
         }
     }
@@ -253,19 +232,19 @@ __device__ __forceinline__ void staged_gather(const AngleRec* sA, const int2* sB
 
 struct StagedTile {
     int i0, j0, z, i, j;
-    int nvalid;  // voxels (i, j), (i, j + 1), ... of this thread inside the image
+    bool valid;  // the thread's voxel (i, j) lies inside the image
 };
 
 __device__ __forceinline__ StagedTile staged_tile(uint32_t w, int nx, int ny, int nz) {
-    const int ntx = (nx + kST - 1) / kST, nty = (ny + kSTY - 1) / kSTY;
+    const int ntx = (nx + kST - 1) / kST, nty = (ny + kST - 1) / kST;
     StagedTile t;
     t.z = w / (ntx * nty);
     const int r = w % (ntx * nty);
-    t.j0 = (r / ntx) * kSTY;
+    t.j0 = (r / ntx) * kST;
     t.i0 = (r % ntx) * kST;
     t.i = t.i0 + (int)(threadIdx.x % kST);
-    t.j = t.j0 + kSV * (int)(threadIdx.x / kST);
-    t.nvalid = (t.z < nz && t.i < nx) ? max(0, min(kSV, ny - t.j)) : 0;
+    t.j = t.j0 + (int)(threadIdx.x / kST);
+    t.valid = t.z < nz && t.i < nx && t.j < ny;
     return t;
 }
 
@@ -280,18 +259,15 @@ __global__ __launch_bounds__(256) void kback_kernel(Src src) {
     AngleRec* sA = reinterpret_cast<AngleRec*>(lds);
     int2* sBB = reinterpret_cast<int2*>(lds + (p.A_q * sizeof(AngleRec) + 15) / 16);
     float4* sR = lds + (p.A_q * sizeof(AngleRec) + 15) / 16 + (p.A_q * sizeof(int2) + 15) / 16;
-    subset_angles_bins_to_lds(sA, sBB, p, t.i0, t.j0, min(kST, p.nx - t.i0), min(kSTY, p.ny - t.j0));
-    float acc[kSV][M], sens[kSV];
-    staged_gather<M>(sA, sBB, sR, p, J.y, t.z, t.nvalid, t.i, t.j, acc, sens);
+    subset_angles_bins_to_lds(sA, sBB, p, t.i0, t.j0, min(kST, p.nx - t.i0), min(kST, p.ny - t.j0));
+    float acc[M], sens;
+    staged_gather<M>(sA, sBB, sR, p, J.y, t.z, t.valid, t.i, t.j, acc, sens);
+    if (!t.valid) return;
+    const size_t v = ((size_t)t.z * p.ny + t.j) * p.nx + t.i;
 #pragma unroll
-    for (int k = 0; k < kSV; ++k) {
-        if (k >= t.nvalid) break;
-        const size_t v = ((size_t)t.z * p.ny + t.j + k) * p.nx + t.i;
-#pragma unroll
-        for (int m = 0; m < M; ++m) acc[k][m] *= p.fr.E[m];
-        store_record<M>(J.b + v * M, acc[k]);
-        if (J.sens) J.sens[v] = sens[k];
-    }
+    for (int m = 0; m < M; ++m) acc[m] *= p.fr.E[m];
+    store_record<M>(J.b + v * M, acc);
+    if (J.sens) J.sens[v] = sens;
 }
 
 template <int M, class Src>
@@ -306,14 +282,12 @@ __global__ __launch_bounds__(256) void kosl_kernel(Src src) {
     AngleRec* sA = reinterpret_cast<AngleRec*>(lds);
     int2* sBB = reinterpret_cast<int2*>(lds + (p.A_q * sizeof(AngleRec) + 15) / 16);
     float4* sR = lds + (p.A_q * sizeof(AngleRec) + 15) / 16 + (p.A_q * sizeof(int2) + 15) / 16;
-    subset_angles_bins_to_lds(sA, sBB, p, t.i0, t.j0, min(kST, p.nx - t.i0), min(kSTY, p.ny - t.j0));
-    float acc[kSV][M], sens[kSV];
-    staged_gather<M>(sA, sBB, sR, p, J.ratio, t.z, t.nvalid, t.i, t.j, acc, sens);
-#pragma unroll
-    for (int k = 0; k < kSV; ++k) {
-        if (k >= t.nvalid) break;
-        osl_finish<M>(a, J.Fm, J.x, ((size_t)t.z * p.ny + t.j + k) * p.nx + t.i, acc[k], sens[k]);
-    }
+    subset_angles_bins_to_lds(sA, sBB, p, t.i0, t.j0, min(kST, p.nx - t.i0), min(kST, p.ny - t.j0));
+    const size_t v = ((size_t)t.z * p.ny + t.j) * p.nx + t.i;
+    float acc[M], sens, xv[M], F[M];
+    if (t.valid) osl_load<M>(a, J.Fm, J.x, v, xv, F);
+    staged_gather<M>(sA, sBB, sR, p, J.ratio, t.z, t.valid, t.i, t.j, acc, sens);
+    if (t.valid) osl_finish<M>(a, J.x, v, xv, F, acc, sens);
 }
 
 static size_t staged_lds_bytes(int max_angles) {

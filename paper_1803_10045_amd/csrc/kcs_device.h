@@ -75,17 +75,22 @@ __host__ __device__ __forceinline__ float recip(float b) {
 }
 
 // Chord of a ray through a pixel square: the exact intersection length as a function of the
-// signed distance t between the ray and the pixel centre, measured along the detector.
-__host__ __device__ __forceinline__ float pixel_chord(const AngleRec& A, float t) {
-    if (A.axis == 0) {
-        const float f = fminf(fmaxf((A.w1 - fabsf(t)) * A.inv_dw, 0.0f), 1.0f);
-        return A.m * f;
-    }
-    // axis-aligned: the pixel is hit iff the ray lies in its half-open extent
+// signed distance t between the ray and the pixel centre, measured along the detector; for
+// oblique angles a trapezoid in t.
+__host__ __device__ __forceinline__ float chord_oblique(const AngleRec& A, float t) {
+    return A.m * fminf(fmaxf((A.w1 - fabsf(t)) * A.inv_dw, 0.0f), 1.0f);
+}
+
+// Axis-aligned angles: the pixel is hit iff the ray lies in its half-open extent.
+__host__ __device__ __forceinline__ float chord_axis(const AngleRec& A, float t) {
     const float cs = A.axis == 1 ? A.c : A.s;
     const float w0 = A.w1;
     const bool in = cs > 0.0f ? (t >= -w0 && t < w0) : (t > -w0 && t <= w0);
     return in ? A.m : 0.0f;
+}
+
+__host__ __device__ __forceinline__ float pixel_chord(const AngleRec& A, float t) {
+    return A.axis == 0 ? chord_oblique(A, t) : chord_axis(A, t);
 }
 
 // Incremental Siddon traversal of a ray through an nx x ny box of pixels: calls
