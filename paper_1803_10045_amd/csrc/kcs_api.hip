@@ -260,7 +260,7 @@ double total_path_length(const kcs_geometry& g) {
 
 // Workspace layout
 struct Layout {
-    size_t kin, xi, init, F, ratio, psum, total;
+    size_t kin, xi, lms, init, F, ratio, psum, total;
 };
 
 // Forward projector variant for a geometry: 0 = ray-driven, T = LDS tiles of T x T pixels.
@@ -286,6 +286,8 @@ Layout layout(const kcs_geometry* g, int32_t M, int32_t Q) {
         const size_t N = (size_t)g->nx * g->ny * g->nz;
         L.xi = off;
         off = align_up(off + 3 * N * sizeof(float), 256);
+        L.lms = off;  // MAP-LM normal equations carried between iterations: 10 floats per voxel
+        off = align_up(off + 10 * N * sizeof(float), 256);
         L.init = off;
         off = align_up(off + ((size_t)kInitChunks * M + M) * sizeof(double), 256);
         L.F = off;
@@ -437,9 +439,12 @@ int do_lm(const kcs_geometry& g, const Schedule& S, const kcs_prior& p, const kc
         dst = params;
     }
     const KinTab* K = at<KinTab>(d_work, L.kin);
+    float* state = at<float>(d_work, L.lms);
     for (int it = 0; it < o.n_iter; ++it) {
         a.reset_lambda = (fresh_lambda && it == 0) ? 1 : 0;
-        KCS_TRY(launched(timed(KCS_T_LM, st, [&] { return launch_lm(S.fr.M, K, x, src, dst, lam, a, st); }),
+        a.have_state = it > 0 ? 1 : 0;
+        a.need_state = it + 1 < o.n_iter ? 1 : 0;
+        KCS_TRY(launched(timed(KCS_T_LM, st, [&] { return launch_lm(S.fr.M, K, x, src, dst, lam, state, a, st); }),
                          "MAP-LM iteration"));
         std::swap(src, dst);
     }
@@ -650,7 +655,10 @@ void build_schedule(TableBuilder& tb, std::vector<StudyPrep>& preps) {
                     float* dst = (odd == even_it) ? s.d_params : other;
                     LmArgs a = lm_args(*P);
                     a.reset_lambda = it == 0 ? 1 : 0;
-                    jobs.push_back(LmJob{a, at<KinTab>(s.d_work, P->L.kin), s.d_x, src, dst, s.d_lambda, 0});
+                    a.have_state = it > 0 ? 1 : 0;
+                    a.need_state = it + 1 < s.lm.n_iter ? 1 : 0;
+                    jobs.push_back(LmJob{a, at<KinTab>(s.d_work, P->L.kin), s.d_x, src, dst, s.d_lambda,
+                                         at<float>(s.d_work, P->L.lms), 0});
                     g.push_back(lm_groups(s.g.nx, s.g.ny, s.g.nz));
                 }
                 tb.add(PH_LM, M, 0, jobs, g, 0);

@@ -31,6 +31,9 @@ struct LmArgs {
     float tau, lam_min, lam_max;
     float eta;  // sufficient relative decrease of the objective for accepting a step
     int32_t reset_lambda;  // 1: ignore the stored lambda and start from tau * max diag(J^T J)
+    // Normal-equation state carried between the iterations of one fit (see klm_kernel):
+    int32_t have_state;    // 1: J^T J, J^T r and r^T r at the current maps are in `state`
+    int32_t need_state;    // 1: leave them in `state` for the next iteration
     float lo[3], hi[3];
 };
 
@@ -77,6 +80,7 @@ struct LmJob {
     const float* xi_in;
     float* xi_out;
     float* lam;
+    float* state;  // [10][N]: J^T J (6), J^T r (3), r^T r at the current maps
     uint32_t w0;
 };
 struct ModelJob {
@@ -156,7 +160,7 @@ size_t tile_partial_bytes(int T, const ProjArgs& p, int M);
 hipError_t launch_backproject(int M, const float* y, float* b, float* sens, const ProjArgs& p, hipStream_t st);
 hipError_t launch_osl(int M, const float* ratio, const float* Fm, float* x, const OslArgs& a, hipStream_t st);
 hipError_t launch_lm(int M, const KinTab* K, const float* x, const float* xi_in, float* xi_out, float* lam,
-                     const LmArgs& a, hipStream_t st);
+                     float* state, const LmArgs& a, hipStream_t st);
 hipError_t launch_model(int M, const KinTab* K, const FrameTab& fr, const float* params, int64_t n, float* F, float* J,
                         hipStream_t st);
 hipError_t launch_init(int M, const float* sino, int64_t rows, const FrameTab& fr, double denom_scale, int32_t nz_ny_nx,

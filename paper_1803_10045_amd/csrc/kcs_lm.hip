@@ -4,10 +4,15 @@
 // accumulating J^T J and J^T r on the fly, so no Jacobian is stored), the Huber neighbour
 // gradient over the in-plane 8-neighbourhood read from the previous maps (Jacobi update, all
 // voxels see the same old neighbours), the damped 3x3 normal equations solved by a
-// diagonally scaled Cholesky factorisation in registers, box clipping, and the accept test.
-// The test uses the exact change of the voxel's objective,
-//   dPhi = sum_m (F_m - F'_m)(2 x_m - F_m - F'_m) / 2 + beta_h (E(xi') - E(xi)),
-// which equals Phi(xi') - Phi(xi) but avoids cancelling two large sums in FP32.
+// diagonally scaled Cholesky factorisation in registers, box clipping, and the accept test on
+// the change of the voxel objective,
+//   dPhi = (r'^T r' - r^T r) / 2 + beta_h (E(xi') - E(xi)),   r = x - F(xi), r' = x - F(xi').
+// The data terms depend only on the voxel's own maps and image, so the normal equations at the
+// trial maps, evaluated with the Jacobian, are those of the next iteration whenever the step is
+// accepted, and those at the current maps stay valid when it is rejected.  A fit therefore
+// carries J^T J, J^T r and r^T r from one iteration to the next in a per-voxel state buffer: its
+// first iteration evaluates the model twice (with the Jacobian at the current and the trial
+// maps), the middle ones once with the Jacobian, the last one once without.
 #include "kcs_device.h"
 #include "kcs_launch.h"
 #include "kcs_model.h"
@@ -49,13 +54,54 @@ __host__ __device__ __forceinline__ float neighbour_energy(const float* __restri
     return e;
 }
 
-// F0 (the model at the current parameters) is kept in a per-thread strip `F0` of M floats with
-// stride `fs` (LDS on the device), so the frame loops can stay rolled.
+// Normal equations of the data term at maps (k1, k2, k3): J^T J (A), J^T r (g) and r^T r (rr).
+struct Normal {
+    float A00, A01, A02, A11, A12, A22, g0, g1, g2, rr;
+};
+
+template <int M>
+__host__ __device__ __forceinline__ Normal normal_equations(const FrameTab& fr, const KinTab& K, const float* xv,
+                                                            float k1, float k2, float k3) {
+    Normal n{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    model_frames<M, true, false>(fr, K, k1, k2, k3, [&](int m, float F, float j0, float j1, float j2) {
+        const float r = xv[m] - F;
+        n.A00 = fmaf(j0, j0, n.A00);
+        n.A01 = fmaf(j0, j1, n.A01);
+        n.A02 = fmaf(j0, j2, n.A02);
+        n.A11 = fmaf(j1, j1, n.A11);
+        n.A12 = fmaf(j1, j2, n.A12);
+        n.A22 = fmaf(j2, j2, n.A22);
+        n.g0 = fmaf(j0, r, n.g0);
+        n.g1 = fmaf(j1, r, n.g1);
+        n.g2 = fmaf(j2, r, n.g2);
+        n.rr = fmaf(r, r, n.rr);
+    });
+    return n;
+}
+
+__host__ __device__ __forceinline__ Normal load_normal(const float* __restrict__ st, size_t N, size_t v) {
+    return Normal{st[v], st[N + v], st[2 * N + v], st[3 * N + v], st[4 * N + v],
+                  st[5 * N + v], st[6 * N + v], st[7 * N + v], st[8 * N + v], st[9 * N + v]};
+}
+
+__host__ __device__ __forceinline__ void store_normal(float* __restrict__ st, size_t N, size_t v, const Normal& n) {
+    st[v] = n.A00;
+    st[N + v] = n.A01;
+    st[2 * N + v] = n.A02;
+    st[3 * N + v] = n.A11;
+    st[4 * N + v] = n.A12;
+    st[5 * N + v] = n.A22;
+    st[6 * N + v] = n.g0;
+    st[7 * N + v] = n.g1;
+    st[8 * N + v] = n.g2;
+    st[9 * N + v] = n.rr;
+}
+
 template <int M>
 __host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, const float* __restrict__ x,
                                                   const float* __restrict__ xi_in, float* __restrict__ xi_out,
-                                                  float* __restrict__ lam_io, const LmArgs& a, int i, int j, int z,
-                                                  float* F0, int fs) {
+                                                  float* __restrict__ lam_io, float* __restrict__ state,
+                                                  const LmArgs& a, int i, int j, int z) {
     const size_t plane = (size_t)a.nx * a.ny;
     const size_t N = plane * a.nz;
     const size_t v = (size_t)z * plane + (size_t)j * a.nx + i;
@@ -68,25 +114,12 @@ __host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, 
     // being held in registers through the model evaluations (they are cache hits).
     float psi[3] = {0.0f, 0.0f, 0.0f};
     const float e0 = neighbour_energy(xi_in, a, i, j, z, N, p0, p1, p2, psi);
-    // model, Jacobian and normal equations at the current parameters
-    float A00 = 0, A01 = 0, A02 = 0, A11 = 0, A12 = 0, A22 = 0, g0 = 0, g1 = 0, g2 = 0, rr = 0;
-    model_frames<M, true, false>(a.fr, *K, p0, p1, p2, [&](int m, float F, float j0, float j1, float j2) {
-        F0[m * fs] = F;
-        const float r = xv[m] - F;
-        A00 = fmaf(j0, j0, A00);
-        A01 = fmaf(j0, j1, A01);
-        A02 = fmaf(j0, j2, A02);
-        A11 = fmaf(j1, j1, A11);
-        A12 = fmaf(j1, j2, A12);
-        A22 = fmaf(j2, j2, A22);
-        g0 = fmaf(j0, r, g0);
-        g1 = fmaf(j1, r, g1);
-        g2 = fmaf(j2, r, g2);
-        rr = fmaf(r, r, rr);
-    });
-    g0 -= a.beta_h * psi[0];
-    g1 -= a.beta_h * psi[1];
-    g2 -= a.beta_h * psi[2];
+    // data-term normal equations at the current parameters
+    const Normal n0 = a.have_state ? load_normal(state, N, v) : normal_equations<M>(a.fr, *K, xv, p0, p1, p2);
+    const float A00 = n0.A00, A01 = n0.A01, A02 = n0.A02, A11 = n0.A11, A12 = n0.A12, A22 = n0.A22;
+    const float g0 = n0.g0 - a.beta_h * psi[0];
+    const float g1 = n0.g1 - a.beta_h * psi[1];
+    const float g2 = n0.g2 - a.beta_h * psi[2];
 
     float lam = a.reset_lambda ? 0.0f : lam_io[v];
     if (!(lam > 0.0f)) lam = a.tau * fmaxf(A00, fmaxf(A11, A22));
@@ -114,20 +147,28 @@ __host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, 
     float unused[3];
     const float e1 = neighbour_energy(xi_in, a, i, j, z, N, q0, q1, q2, unused);
 
-    float dphi = 0.0f;
-    model_frames<M, false, false>(a.fr, *K, q0, q1, q2, [&](int m, float F, float, float, float) {
-        const float f0 = F0[m * fs];
-        const float df = f0 - F;
-        dphi = fmaf(0.5f * df, 2.0f * xv[m] - f0 - F, dphi);
-    });
-    dphi = fmaf(a.beta_h, e1 - e0, dphi);
-
-    const float phi0 = fmaf(a.beta_h, e0, 0.5f * rr);
+    // data term at the trial parameters (with the normal equations when the next iteration needs them)
+    Normal n1{};
+    if (a.need_state) {
+        n1 = normal_equations<M>(a.fr, *K, xv, q0, q1, q2);
+    } else {
+        model_frames<M, false, false>(a.fr, *K, q0, q1, q2, [&](int m, float F, float, float, float) {
+            const float r = xv[m] - F;
+            n1.rr = fmaf(r, r, n1.rr);
+        });
+    }
+    const float dphi = fmaf(a.beta_h, e1 - e0, 0.5f * (n1.rr - n0.rr));
+    const float phi0 = fmaf(a.beta_h, e0, 0.5f * n0.rr);
     const bool accept = dphi < -a.eta * phi0;
     xi_out[v] = accept ? q0 : p0;
     xi_out[N + v] = accept ? q1 : p1;
     xi_out[2 * N + v] = accept ? q2 : p2;
     lam_io[v] = accept ? fmaxf(lam * 0.1f, a.lam_min) : fminf(lam * 10.0f, a.lam_max);
+    // the state holds the normal equations of the maps this iteration leaves
+    if (a.need_state) {
+        if (accept) store_normal(state, N, v, n1);
+        else if (!a.have_state) store_normal(state, N, v, n0);
+    }
 }
 
 uint32_t lm_groups(int nx, int ny, int nz) {
@@ -146,8 +187,7 @@ __global__ __launch_bounds__(256) void klm_kernel(Src src) {
     const int j = (rr / tx) * kLmTileY + threadIdx.x / kLmTileX;
     const int i = (rr % tx) * kLmTileX + threadIdx.x % kLmTileX;
     if (z >= a.nz || i >= a.nx || j >= a.ny) return;
-    __shared__ float sF0[M * kLmTileX * kLmTileY];
-    lm_voxel<M>(J.K, J.x, J.xi_in, J.xi_out, J.lam, a, i, j, z, sF0 + threadIdx.x, kLmTileX * kLmTileY);
+    lm_voxel<M>(J.K, J.x, J.xi_in, J.xi_out, J.lam, J.state, a, i, j, z);
 }
 
 template <class Src>
@@ -164,8 +204,8 @@ static hipError_t dispatch_lm(int M, Src src, uint32_t groups, hipStream_t st) {
 }
 
 hipError_t launch_lm(int M, const KinTab* K, const float* x, const float* xi_in, float* xi_out, float* lam,
-                     const LmArgs& a, hipStream_t st) {
-    OneJob<LmJob> src{LmJob{a, K, x, xi_in, xi_out, lam, 0}};
+                     float* state, const LmArgs& a, hipStream_t st) {
+    OneJob<LmJob> src{LmJob{a, K, x, xi_in, xi_out, lam, state, 0}};
     return dispatch_lm(M, src, lm_groups(a.nx, a.ny, a.nz), st);
 }
 
