@@ -385,12 +385,42 @@ def run_copy(args):
                       "read_plus_write_GBps": round(2 * 4 * n / ms / 1e6, 1)}), flush=True)
 
 
+def run_ki(args):
+    """K_i map (net uptake rate) over the maps of a study of the chosen configuration: 16 B per
+    voxel (3 maps read, 1 written), timed with HIP events over `steps` launches."""
+    import torch
+
+    from paper_1803_10045_amd import inputs, kcs
+
+    cfg = inputs.CONFIGS[args.config]()
+    shape = (cfg.nz, cfg.ny, cfg.nx)
+    g = torch.Generator(device="cpu").manual_seed(5)
+    lo = torch.tensor(inputs.LM_LO).view(3, 1, 1, 1)
+    hi = torch.tensor(inputs.LM_HI).view(3, 1, 1, 1)
+    params = (lo + (hi - lo) * torch.rand((3,) + shape, generator=g)).to("cuda:0")
+    ki = torch.empty(shape, device="cuda:0")
+    kcs.kcs_ki_map(params, ki)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        kcs.kcs_ki_map(params, ki)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    n = ki.numel()
+    gbps = 16 * n / ms / 1e6
+    print(json.dumps({"metric": "K_i map GB/s", "value": round(gbps, 1), "unit": "GB/s", "voxels": n,
+                      "avg_ms": round(ms, 4), "launches": args.steps, "alg_bytes_per_launch": 16 * n,
+                      "hbm_frac": round(gbps / 8000.0, 4), "config": {"workload": cfg.name}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--mode", default="sweep", choices=["sweep", "batched", "serve", "copy"])
+    ap.add_argument("--mode", default="sweep", choices=["sweep", "batched", "serve", "copy", "ki"])
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--rate", type=float, default=4.0)
     ap.add_argument("--budget-gb", type=float, default=250.0)
@@ -409,6 +439,10 @@ def main():
     if args.mode == "copy":
         args.steps = 4 if args.steps is None else args.steps
         run_copy(args)
+        return
+    if args.mode == "ki":
+        args.steps = 20 if args.steps is None else args.steps
+        run_ki(args)
         return
     if args.mode == "batched":
         args.steps = 2 if args.steps is None else args.steps

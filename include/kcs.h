@@ -115,6 +115,14 @@ int kcs_project(const kcs_geometry* g, const kcs_frames* f, const float* d_x, in
 int kcs_backproject(const kcs_geometry* g, const kcs_frames* f, const float* d_y, int32_t q, int32_t Q,
                     float* d_b, float* d_sens, hipStream_t stream);
 
+/* Net uptake rate map (the macro-parameter of Sec. IV, human data): for each of n voxels
+ *   K_i = K1 k3 / (k2 + k3),   and K_i = K1 where k2 + k3 = 0 (nothing leaves the first
+ *   compartment, so everything that enters is taken up).
+ * d_params: [3][n] device maps (K1, k2, k3), read; d_ki: [n] device, written.  Caller-owned.
+ * Errors: KCS_EINVAL for n < 0, n > (2^31 - 1) * 256 or a NULL pointer with n > 0 (nothing is
+ * launched); n = 0 is a no-op.  Asynchronous on `stream`; needs no workspace. */
+int kcs_ki_map(const float* d_params, int64_t n, float* d_ki, hipStream_t stream);
+
 /* Frame-averaged model TAC (Eq. 3's F(xi)_m, closed-form time integrals) for n voxels:
  *   F_m = (1/dt_m) int_{t0_m}^{t1_m} [(1 - vb) C_T(t; K1, k2, k3) + vb Cp(t)] dt
  * d_params: [3][n] (K1, k2, k3 with k2 + k3 > 0); d_F: [n][M]; d_J: [n][M][3] dF/d(K1,k2,k3) or NULL.

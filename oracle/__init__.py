@@ -7,7 +7,7 @@ passage of the paper it follows.
 """
 from .geometry import (Geometry, build_oracle_library, forward, back, subset_angles, subset_rows,
                        subset_sensitivity, system_matrix, siddon_line)
-from .model import Kinetics, cp, input_integrals, model_tac, cumulative_tissue, moments
+from .model import Kinetics, cp, input_integrals, model_tac, cumulative_tissue, moments, net_influx
 from .recon import (Frames, LMOptions, Prior, expected_counts, huber, huber_grad, icm, icm_sweep,
                     initial_image, initial_state, lm_fit, lm_iteration, neighbour_terms, osl_update)
 from .study import Study, make_study

@@ -161,3 +161,13 @@ def model_tac(params: np.ndarray, t0: np.ndarray, t1: np.ndarray, kin: Kinetics,
         if jacobian:
             J[s:s + chunk] = (1.0 - kin.vb) * (D[:, i1] - D[:, i0]) / dt[None, :, None]
     return (F, J) if jacobian else F
+
+
+def net_influx(params: np.ndarray) -> np.ndarray:
+    """Macro-parameter K_i = K1 k3 / (k2 + k3) of the irreversible model (Sec. IV, human data):
+    the net uptake rate, the late slope of the tissue response to a constant unit input.  Where
+    k2 + k3 = 0 nothing leaves the first compartment and K_i = K1.  params: [3, ...]."""
+    K1, k2, k3 = (np.asarray(params[i], dtype=np.float64) for i in range(3))
+    a = k2 + k3
+    pos = a > 0
+    return np.where(pos, K1 * k3 / np.where(pos, a, 1.0), K1)

@@ -898,6 +898,15 @@ int kcs_model_tac(const kcs_frames* f, const kcs_kinetics* k, const float* d_par
         "model evaluation");
 }
 
+int kcs_ki_map(const float* d_params, int64_t n, float* d_ki, hipStream_t stream) {
+    if (n < 0) return fail(KCS_EINVAL, "n must be >= 0");
+    if (n > (int64_t)INT32_MAX * 256) return fail(KCS_EINVAL, "n is too large (at most 2^31 - 1 workgroups of 256)");
+    if (n > 0 && (!d_params || !d_ki)) return fail(KCS_EINVAL, "device pointers must not be NULL");
+    if (n == 0) return KCS_OK;
+    g_err.clear();
+    return launched(launch_ki(d_params, n, d_ki, stream), "K_i map");
+}
+
 int kcs_osl_update(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics* k, const kcs_prior* p,
                    const float* d_sino, const float* d_params, int32_t q, int32_t Q, float* d_x, void* d_work,
                    size_t work_bytes, hipStream_t stream) {

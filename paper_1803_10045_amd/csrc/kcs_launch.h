@@ -161,6 +161,7 @@ hipError_t launch_backproject(int M, const float* y, float* b, float* sens, cons
 hipError_t launch_osl(int M, const float* ratio, const float* Fm, float* x, const OslArgs& a, hipStream_t st);
 hipError_t launch_lm(int M, const KinTab* K, const float* x, const float* xi_in, float* xi_out, float* lam,
                      float* state, const LmArgs& a, hipStream_t st);
+hipError_t launch_ki(const float* params, int64_t n, float* ki, hipStream_t st);
 hipError_t launch_model(int M, const KinTab* K, const FrameTab& fr, const float* params, int64_t n, float* F, float* J,
                         hipStream_t st);
 hipError_t launch_init(int M, const float* sino, int64_t rows, const FrameTab& fr, double denom_scale, int32_t nz_ny_nx,

@@ -91,6 +91,23 @@ hipError_t launch_model_jobs(int M, JobTable<ModelJob> jobs, uint32_t groups, hi
     return dispatch_model(M, false, jobs, groups, st);
 }
 
+// Net uptake rate K_i = K1 k3 / (k2 + k3) per voxel (the macro-parameter of Sec. IV); where
+// k2 + k3 = 0 nothing leaves the first compartment and K_i = K1.  params [3][n], ki [n].
+__global__ __launch_bounds__(256) void kki_kernel(const float* __restrict__ params, int64_t n,
+                                                  float* __restrict__ ki) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    const float K1 = params[e], k2 = params[n + e], k3 = params[2 * n + e];
+    const float a = k2 + k3;
+    ki[e] = a > 0.0f ? K1 * k3 / a : K1;
+}
+
+hipError_t launch_ki(const float* params, int64_t n, float* ki, hipStream_t st) {
+    const int64_t groups = (n + 255) / 256;
+    hipLaunchKernelGGL(kki_kernel, dim3((uint32_t)groups), dim3(256), 0, st, params, n, ki);
+    return hipGetLastError();
+}
+
 // Batched device-to-device copies (the kinetic maps before an odd number of LM iterations).
 uint32_t copy_groups(int64_t n) { return (uint32_t)((n + 1023) / 1024); }
 

@@ -20,7 +20,7 @@ KCS_OK, KCS_EINVAL, KCS_ESHAPE, KCS_EWORKSPACE, KCS_EHIP = 0, -1, -2, -3, -4
 
 # Entry points declared in include/kcs.h (checked against the header by the tests).
 ENTRY_POINTS = ("kcs_workspace_bytes", "kcs_study_footprint_bytes", "kcs_project", "kcs_backproject",
-                "kcs_model_tac", "kcs_osl_update", "kcs_lm_fit", "kcs_init_state", "kcs_icm_sweep",
+                "kcs_model_tac", "kcs_ki_map", "kcs_osl_update", "kcs_lm_fit", "kcs_init_state", "kcs_icm_sweep",
                 "kcs_plan_create", "kcs_plan_run", "kcs_plan_describe", "kcs_plan_destroy",
                 "kcs_timing_enable", "kcs_timing_collect", "kcs_last_error")
 
@@ -85,6 +85,7 @@ def lib() -> ctypes.CDLL:
     L.kcs_project.argtypes = [P(c_geometry), P(c_frames), vp, i32, i32, vp, vp]
     L.kcs_backproject.argtypes = [P(c_geometry), P(c_frames), vp, i32, i32, vp, vp, vp]
     L.kcs_model_tac.argtypes = [P(c_frames), P(c_kinetics), vp, i64, vp, vp, vp, sz, vp]
+    L.kcs_ki_map.argtypes = [vp, i64, vp, vp]
     L.kcs_osl_update.argtypes = [P(c_geometry), P(c_frames), P(c_kinetics), P(c_prior), vp, vp, i32, i32, vp, vp, sz,
                                  vp]
     L.kcs_lm_fit.argtypes = [P(c_geometry), P(c_frames), P(c_kinetics), P(c_prior), P(c_lm_opts), vp, vp, vp, vp, sz,
@@ -92,7 +93,7 @@ def lib() -> ctypes.CDLL:
     L.kcs_init_state.argtypes = [P(c_geometry), P(c_frames), vp, P(ctypes.c_double), vp, vp, vp, vp, sz, vp]
     L.kcs_icm_sweep.argtypes = [P(c_geometry), P(c_frames), P(c_kinetics), P(c_prior), P(c_lm_opts), vp, i32, i32, vp,
                                 vp, vp, vp, sz, vp]
-    for name in ("kcs_project", "kcs_backproject", "kcs_model_tac", "kcs_osl_update", "kcs_lm_fit",
+    for name in ("kcs_project", "kcs_backproject", "kcs_model_tac", "kcs_ki_map", "kcs_osl_update", "kcs_lm_fit",
                  "kcs_init_state", "kcs_icm_sweep"):
         getattr(L, name).restype = ctypes.c_int
     L.kcs_plan_create.argtypes = [P(c_study), i32, i32, vp, P(vp)]
@@ -283,6 +284,13 @@ def kcs_model_tac(f: Frames, k: Kinetics, params, F, J=None, work=None, stream=N
     wp, wn = _work(work)
     _check(lib().kcs_model_tac(ctypes.byref(fc), ctypes.byref(kc), _ptr(params, (3, n), "params"), n,
                                _ptr(F, (n, f.M), "F"), _ptr(J, (n, f.M, 3), "J"), wp, wn, _stream(stream)))
+
+
+def kcs_ki_map(params, ki, stream=None):
+    """K_i = K1 k3 / (k2 + k3) per voxel of the maps params [3][...] into ki [...]."""
+    n = ki.numel()
+    _check(lib().kcs_ki_map(_ptr(params, (3,) + tuple(ki.shape), "params"), n, _ptr(ki, tuple(ki.shape), "ki"),
+                            _stream(stream)))
 
 
 def kcs_osl_update(g: Geometry, f: Frames, k: Kinetics, p: Prior, sino, params, q: int, Q: int, x, work,

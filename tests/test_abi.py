@@ -130,3 +130,11 @@ def test_plan_create_rejects_bad_studies(bad):
     if bad != "none":
         assert ("study 1" if bad == "second" else "study 0") in msg
     kcs.lib().kcs_plan_destroy(None)  # NULL is ignored
+
+
+def test_ki_map_validates_before_launching():
+    L = kcs.lib()
+    assert L.kcs_ki_map(None, -1, None, None) == kcs.KCS_EINVAL
+    assert L.kcs_ki_map(None, 10, None, None) == kcs.KCS_EINVAL
+    assert L.kcs_ki_map(ctypes.c_void_p(256), 1 << 40, ctypes.c_void_p(256), None) == kcs.KCS_EINVAL
+    assert L.kcs_ki_map(None, 0, None, None) == kcs.KCS_OK  # empty: nothing to do

@@ -121,6 +121,28 @@ def test_model_tac_parity():
     assert np.all(je[inbox].max(axis=0) < 5e-5)
 
 
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 37, 29), (2, 128, 129)])
+def test_ki_map_parity(shape):
+    """K_i map against the oracle's net_influx on random maps in and beyond the box, with k2 = 0,
+    k3 = 0 and k2 = k3 = 0 among them; sizes with a ragged last workgroup."""
+    rng = np.random.default_rng(7)
+    P = np.stack([rng.uniform(0.0, 1.0, shape), rng.uniform(0.0, 2.0, shape), rng.uniform(0.0, 1.0, shape)])
+    flat = P.reshape(3, -1)
+    if flat.shape[1] >= 3:
+        flat[1, 0] = 0.0
+        flat[2, 1] = 0.0
+        flat[1:, 2] = 0.0
+    P = flat.reshape(P.shape).astype(np.float32)
+    ki = torch.empty(shape, device=DEV)
+    kcs.kcs_ki_map(dev(P), ki)
+    torch.cuda.synchronize()
+    ref = oracle.net_influx(P.astype(np.float64))
+    got = ki.cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-30)
+    print(f"K_i map {shape}: max rel err {err.max():.2e}")
+    assert np.all(np.isfinite(got)) and err.max() < 1e-6
+
+
 def cfg1_study():
     return oracle.make_study(inputs.cfg1())
 

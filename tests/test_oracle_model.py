@@ -126,3 +126,31 @@ def test_special_cases_of_the_tissue_model():
     C1, _ = oracle.cumulative_tissue(np.array([[0.1, 0.1, 0.05]]), T, KIN)
     C2, _ = oracle.cumulative_tissue(np.array([[0.3, 0.1, 0.05]]), T, KIN)
     np.testing.assert_allclose(C2, 3 * C1, rtol=1e-13)
+
+
+@pytest.mark.parametrize("p", [(0.10, 0.10, 0.05), (0.30, 0.02, 0.40), (0.05, 0.90, 0.01), (0.20, 0.0, 0.07),
+                               (0.15, 0.12, 0.0), (0.25, 0.0, 0.0)])
+def test_net_influx_is_the_late_slope_for_a_constant_input(p):
+    """K_i pinned to the compartment model itself: under a constant unit plasma input the tissue
+    curve of the irreversible model becomes a straight line of slope K_i (DOP853 solve of the
+    ODEs; with k2 + k3 = 0 the first compartment just fills at rate K1)."""
+    K1, k2, k3 = p
+    a = k2 + k3
+
+    def f(t, c):
+        return [K1 - a * c[0], k3 * c[0]]
+
+    T1, T2 = (40.0 / a, 80.0 / a) if a > 0 else (10.0, 20.0)
+    sol = solve_ivp(f, (0.0, T2), [0.0, 0.0], method="DOP853", rtol=1e-12, atol=1e-14, t_eval=[T1, T2],
+                    dense_output=False)
+    ct = sol.y[0] + sol.y[1]
+    slope = (ct[1] - ct[0]) / (T2 - T1)
+    ki = oracle.net_influx(np.array(p, dtype=np.float64).reshape(3, 1))[0]
+    assert ki == pytest.approx(slope, rel=1e-9, abs=1e-12)
+
+
+def test_net_influx_shapes_and_limits():
+    p = np.array([[[0.2, 0.3]], [[0.1, 1e-12]], [[0.05, 0.2]]])  # [3, 1, 2]
+    ki = oracle.net_influx(p)
+    assert ki.shape == (1, 2)
+    np.testing.assert_allclose(ki[0], [0.2 * 0.05 / 0.15, 0.3 * 0.2 / (0.2 + 1e-12)], rtol=1e-15)
