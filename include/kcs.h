@@ -81,10 +81,15 @@ typedef struct kcs_kinetics {
 
 /* Priors.  OSL denominator (Eq. 2-3): D = n (1 + beta_kp (x - F) / max(F, eps_F)) with
  * 0 <= beta_kp < 1 and eps_F > 0; kp_on = 0 turns the kinetics-derived prior off (plain OS-EM).
- * MAP-LM (Eq. 4-7): weight beta_h >= 0 and Huber threshold delta[p] > 0 per kinetic parameter. */
+ * MAP-LM (Eq. 4-7): weight beta_h >= 0 and Huber threshold delta[p] > 0 per kinetic parameter.
+ * Neighbourhood of the Huber term: plane_ratio = 0 takes the 8 in-plane neighbours (the paper's
+ * prior, weights 1 and 1/sqrt(2)); plane_ratio > 0 takes the 26 neighbours of the 3x3x3 cube,
+ * the planes being plane_ratio pixel sides apart, each weighted by 1 / its distance in pixel
+ * sides.  plane_ratio must be finite and >= 0. */
 typedef struct kcs_prior {
     double beta_kp, eps_F, beta_h, delta[3];
     int32_t kp_on;
+    double plane_ratio;
 } kcs_prior;
 
 /* Levenberg-Marquardt schedule: n_iter synchronous iterations; lambda <= 0 on entry is set to

@@ -38,6 +38,9 @@ class Prior:
     beta_h: float = 0.1
     delta: Tuple[float, float, float] = (1e-3, 1e-3, 1e-3)
     kp_on: bool = True
+    # 0: the in-plane 8-neighbourhood of the Huber term (the paper's prior); > 0: the 26
+    # neighbours of the 3x3x3 cube with planes plane_ratio pixel sides apart (weights 1/distance)
+    plane_ratio: float = 0.0
 
 
 @dataclass(frozen=True)
@@ -103,7 +106,6 @@ def initial_image(g: geo.Geometry, fr: Frames, sino: np.ndarray) -> np.ndarray:
 # MAP-LM with the Huber prior
 # ------------------------------------------------------------------------------------------
 
-_OFFSETS = [(dy, dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1) if (dy, dx) != (0, 0)]
 
 
 def huber(t, delta):
@@ -115,21 +117,40 @@ def huber_grad(t, delta):
     return np.clip(t, -delta, delta)
 
 
-def neighbour_terms(xi_eval: np.ndarray, xi_ref: np.ndarray, delta) -> Tuple[np.ndarray, np.ndarray]:
+def neighbour_offsets(plane_ratio: float = 0.0):
+    """(dz, dy, dx, w) of the Huber neighbourhood: the in-plane 8-neighbours with weights 1 and
+    1/sqrt(2) (Eq. 5-7), and with plane_ratio > 0 also the 18 neighbours of the adjacent planes,
+    each weighted by 1 / its distance in pixel sides (planes plane_ratio pixel sides apart)."""
+    dzs = (-1, 0, 1) if plane_ratio > 0 else (0,)
+    out = []
+    for dz in dzs:
+        for dy, dx in [(dy, dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]:
+            if (dz, dy, dx) == (0, 0, 0):
+                continue
+            out.append((dz, dy, dx, 1.0 / np.sqrt(dy * dy + dx * dx + (dz * plane_ratio) ** 2)))
+    return out
+
+
+def _pair(d, n):
+    """Slices (voxel, neighbour) along an axis of length n for offset d."""
+    return (slice(0, n - d), slice(d, n)) if d >= 0 else (slice(-d, n), slice(0, n + d))
+
+
+def neighbour_terms(xi_eval: np.ndarray, xi_ref: np.ndarray, delta, plane_ratio: float = 0.0
+                    ) -> Tuple[np.ndarray, np.ndarray]:
     """For maps (3, nz, ny, nx): sum_k w_k psi(xi_eval_v - xi_ref_k) per parameter (3, ...) and
-    sum_k w_k sum_p H(xi_eval_vp - xi_ref_kp) (nz, ny, nx), over in-plane 8-neighbours k."""
+    sum_k w_k sum_p H(xi_eval_vp - xi_ref_kp) (nz, ny, nx) over the neighbours k of
+    neighbour_offsets(plane_ratio) that lie inside the image."""
     _, nz, ny, nx = xi_ref.shape
     grad = np.zeros_like(xi_eval)
     energy = np.zeros(xi_eval.shape[1:])
-    for dy, dx in _OFFSETS:
-        w = 1.0 if dy == 0 or dx == 0 else 1.0 / np.sqrt(2.0)
-        ys, yd = (slice(0, ny - dy), slice(dy, ny)) if dy >= 0 else (slice(-dy, ny), slice(0, ny + dy))
-        xs, xd = (slice(0, nx - dx), slice(dx, nx)) if dx >= 0 else (slice(-dx, nx), slice(0, nx + dx))
-        # voxel at (y, x) = destination slice (ys, xs); its neighbour at (y+dy, x+dx) = (yd, xd)
+    for dz, dy, dx, w in neighbour_offsets(plane_ratio):
+        (zs, zd), (ys, yd), (xs, xd) = _pair(dz, nz), _pair(dy, ny), _pair(dx, nx)
+        # voxel at (z, y, x) = source slices; its neighbour at (z+dz, y+dy, x+dx) = destination slices
         for p in range(3):
-            t = xi_eval[p][:, ys, xs] - xi_ref[p][:, yd, xd]
-            grad[p][:, ys, xs] += w * huber_grad(t, delta[p])
-            energy[:, ys, xs] += w * huber(t, delta[p])
+            t = xi_eval[p][zs, ys, xs] - xi_ref[p][zd, yd, xd]
+            grad[p][zs, ys, xs] += w * huber_grad(t, delta[p])
+            energy[zs, ys, xs] += w * huber(t, delta[p])
     return grad, energy
 
 
@@ -145,7 +166,7 @@ def lm_iteration(fr: Frames, kin: Kinetics, prior: Prior, opt: LMOptions, x: np.
     xi = params.reshape(3, N).T.copy()
     F, J = model_tac(xi, fr.t0, fr.t1, kin, jacobian=True)
     r = xv - F
-    pg, pe = neighbour_terms(params, params, prior.delta)
+    pg, pe = neighbour_terms(params, params, prior.delta, prior.plane_ratio)
     g = np.einsum("nmp,nm->np", J, r) - prior.beta_h * pg.reshape(3, N).T
     A = np.einsum("nmp,nmq->npq", J, J)
     lam = lam.reshape(N).copy()
@@ -155,7 +176,7 @@ def lm_iteration(fr: Frames, kin: Kinetics, prior: Prior, opt: LMOptions, x: np.
     trial = np.clip(xi + step, np.array(opt.lo), np.array(opt.hi))
     F1 = model_tac(trial, fr.t0, fr.t1, kin)
     trial_maps = trial.T.reshape(params.shape)
-    _, pe1 = neighbour_terms(trial_maps, params, prior.delta)
+    _, pe1 = neighbour_terms(trial_maps, params, prior.delta, prior.plane_ratio)
     phi0 = 0.5 * np.sum(r * r, axis=1) + prior.beta_h * pe.reshape(N)
     phi1 = 0.5 * np.sum((xv - F1) ** 2, axis=1) + prior.beta_h * pe1.reshape(N)
     accept = phi1 - phi0 < -opt.eta * phi0

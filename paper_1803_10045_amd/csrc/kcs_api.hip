@@ -82,6 +82,7 @@ int check_prior(const kcs_prior* p) {
     if (!(p->beta_h >= 0) || !is_finite(p->beta_h)) return fail(KCS_EINVAL, "beta_h must be >= 0");
     for (int i = 0; i < 3; ++i)
         if (!(p->delta[i] > 0) || !is_finite(p->delta[i])) return fail(KCS_EINVAL, "delta must be > 0");
+    if (!(p->plane_ratio >= 0) || !is_finite(p->plane_ratio)) return fail(KCS_EINVAL, "plane_ratio must be >= 0");
     return KCS_OK;
 }
 
@@ -406,6 +407,14 @@ int do_osl(const kcs_geometry& g, const Schedule& S, const kcs_prior& p, bool kp
     return launched(timed(KCS_T_OSL, st, [&] { return launch_osl(S.fr.M, ratio, Fm, x, a, st); }), "OSL update");
 }
 
+// Neighbourhood of the Huber term: in-plane 3x3, or the 3x3x3 cube with planes plane_ratio
+// pixel sides apart, each neighbour weighted by 1 / its distance.
+void set_neighbourhood(LmArgs& a, const kcs_prior& p) {
+    a.nbr3d = p.plane_ratio > 0 ? 1 : 0;
+    const double r2 = p.plane_ratio * p.plane_ratio;
+    for (int k = 0; k < 3; ++k) a.w_plane[k] = a.nbr3d ? (float)(1.0 / std::sqrt(r2 + k)) : 0.0f;
+}
+
 int do_lm(const kcs_geometry& g, const Schedule& S, const kcs_prior& p, const kcs_lm_opts& o, const float* x,
           float* params, float* lam, void* d_work, int32_t Q, bool fresh_lambda, hipStream_t st) {
     if (o.n_iter == 0) return KCS_OK;
@@ -417,6 +426,7 @@ int do_lm(const kcs_geometry& g, const Schedule& S, const kcs_prior& p, const kc
     a.nz = g.nz;
     a.fr = S.fr;
     a.beta_h = (float)p.beta_h;
+    set_neighbourhood(a, p);
     for (int i = 0; i < 3; ++i) {
         a.delta[i] = (float)p.delta[i];
         a.lo[i] = (float)o.lo[i];
@@ -527,6 +537,7 @@ LmArgs lm_args(const StudyPrep& P) {
     a.nz = s.g.nz;
     a.fr = P.S.fr;
     a.beta_h = (float)s.p.beta_h;
+    set_neighbourhood(a, s.p);
     for (int i = 0; i < 3; ++i) {
         a.delta[i] = (float)s.p.delta[i];
         a.lo[i] = (float)s.lm.lo[i];
@@ -641,12 +652,13 @@ void build_schedule(TableBuilder& tb, std::vector<StudyPrep>& preps) {
         }
         tb.add(PH_COPY, 0, 0, cj, cg, 0);
         for (int it = 0; it < itmax; ++it) {
-            for (int M : frame_counts(act)) {
+            for (int M : frame_counts(act)) for (int nb = 0; nb < 2; ++nb) {
+                // one launch per frame count and neighbourhood (in-plane / 3x3x3)
                 std::vector<LmJob> jobs;
                 std::vector<uint32_t> g;
                 for (const StudyPrep* P : act) {
                     const kcs_study& s = *P->s;
-                    if (P->S.fr.M != M || it >= s.lm.n_iter) continue;
+                    if (P->S.fr.M != M || it >= s.lm.n_iter || (s.p.plane_ratio > 0) != (nb == 1)) continue;
                     float* other = at<float>(s.d_work, P->L.xi);
                     const bool odd = s.lm.n_iter % 2 == 1;
                     const bool even_it = it % 2 == 0;
@@ -661,7 +673,7 @@ void build_schedule(TableBuilder& tb, std::vector<StudyPrep>& preps) {
                                          at<float>(s.d_work, P->L.lms), 0});
                     g.push_back(lm_groups(s.g.nx, s.g.ny, s.g.nz));
                 }
-                tb.add(PH_LM, M, 0, jobs, g, 0);
+                tb.add(PH_LM, M, nb, jobs, g, 0);
             }
         }
     }
@@ -681,7 +693,7 @@ hipError_t run_phase(const PlanPhase& ph, const char* base, hipStream_t st) {
         case PH_REDUCE: return launch_project_reduce_jobs(ph.M, ph.T, table<ProjJob>(ph, base), ph.groups, true, st);
         case PH_OSL: return launch_osl_jobs(ph.M, table<OslJob>(ph, base), ph.groups, ph.max_angles, st);
         case PH_COPY: return launch_copy_jobs(table<CopyJob>(ph, base), ph.groups, st);
-        case PH_LM: return launch_lm_jobs(ph.M, table<LmJob>(ph, base), ph.groups, st);
+        case PH_LM: return launch_lm_jobs(ph.M, ph.T != 0, table<LmJob>(ph, base), ph.groups, st);
         default: return hipErrorInvalidValue;
     }
 }

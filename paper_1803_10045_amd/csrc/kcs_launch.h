@@ -28,6 +28,10 @@ struct LmArgs {
     FrameTab fr;
     float beta_h;
     float delta[3];
+    // 3x3x3 neighbourhood when nbr3d: weights of the through-plane neighbours with 0, 1 or 2
+    // in-plane offsets (1 / distance in pixel sides)
+    int32_t nbr3d;
+    float w_plane[3];
     float tau, lam_min, lam_max;
     float eta;  // sufficient relative decrease of the objective for accepting a step
     int32_t reset_lambda;  // 1: ignore the stored lambda and start from tau * max diag(J^T J)
@@ -147,7 +151,7 @@ hipError_t launch_project_jobs(int M, int T, JobTable<ProjJob> jobs, uint32_t gr
 hipError_t launch_project_reduce_jobs(int M, int T, JobTable<ProjJob> jobs, uint32_t groups, bool ratio,
                                       hipStream_t st);
 hipError_t launch_osl_jobs(int M, JobTable<OslJob> jobs, uint32_t groups, int max_angles, hipStream_t st);
-hipError_t launch_lm_jobs(int M, JobTable<LmJob> jobs, uint32_t groups, hipStream_t st);
+hipError_t launch_lm_jobs(int M, bool nbr3d, JobTable<LmJob> jobs, uint32_t groups, hipStream_t st);
 hipError_t launch_model_jobs(int M, JobTable<ModelJob> jobs, uint32_t groups, hipStream_t st);
 hipError_t launch_copy_jobs(JobTable<CopyJob> jobs, uint32_t groups, hipStream_t st);
 

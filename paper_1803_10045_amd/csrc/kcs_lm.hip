@@ -26,29 +26,49 @@ __host__ __device__ __forceinline__ float huber(float t, float d) {
     return at <= d ? 0.5f * t * t : d * at - 0.5f * d * d;
 }
 
-// Weighted Huber energy sum_k w_k sum_p H(q_p - xi_kp) over the in-plane 8-neighbours k of voxel
-// (i, j, z) in the maps xi (neighbours outside the image dropped), and the gradient terms
-// psi_p = sum_k w_k clip(q_p - xi_kp, -delta_p, delta_p).
-__host__ __device__ __forceinline__ float neighbour_energy(const float* __restrict__ xi, const LmArgs& a, int i, int j,
-                                                           int z, size_t N, float q0, float q1, float q2,
-                                                           float (&psi)[3]) {
+// Weighted Huber energy sum_k w_k sum_p H(q_p - xi_kp) over the neighbours k of voxel (i, j, z)
+// in the maps xi (neighbours outside the image dropped), and the gradient terms
+// psi_p = sum_k w_k clip(q_p - xi_kp, -delta_p, delta_p).  The neighbours are the 8 in-plane ones
+// (weights 1 and 1/sqrt(2)) and, with a.nbr3d, the 18 of the planes z - 1 and z + 1 (weights
+// a.w_plane by the number of in-plane offsets).
+// Adds the terms of the 3x3 neighbours in plane zz of voxel (i, j) (the voxel itself skipped when
+// zz is its own plane); w_edge, w_diag weight neighbours with one and two in-plane offsets.
+__host__ __device__ __forceinline__ void plane_terms(const float* __restrict__ xi, const LmArgs& a, int i, int j,
+                                                     int zz, bool own, float w_centre, float w_edge, float w_diag,
+                                                     size_t N, float q0, float q1, float q2, float& e,
+                                                     float (&psi)[3]) {
     const size_t plane = (size_t)a.nx * a.ny;
-    float e = 0.0f;
-    psi[0] = psi[1] = psi[2] = 0.0f;
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
 #pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
-            if (dy == 0 && dx == 0) continue;
+            if (own && dy == 0 && dx == 0) continue;
             const int jj = j + dy, ii = i + dx;
             if (jj < 0 || jj >= a.ny || ii < 0 || ii >= a.nx) continue;
-            const size_t u = (size_t)z * plane + (size_t)jj * a.nx + ii;
-            const float w = (dy == 0 || dx == 0) ? 1.0f : 0.70710678118654752f;
+            const size_t u = (size_t)zz * plane + (size_t)jj * a.nx + ii;
+            const int off = (dx != 0) + (dy != 0);
+            const float w = off == 0 ? w_centre : (off == 1 ? w_edge : w_diag);
             const float d0 = q0 - xi[u], d1 = q1 - xi[N + u], d2 = q2 - xi[2 * N + u];
             psi[0] += w * fminf(fmaxf(d0, -a.delta[0]), a.delta[0]);
             psi[1] += w * fminf(fmaxf(d1, -a.delta[1]), a.delta[1]);
             psi[2] += w * fminf(fmaxf(d2, -a.delta[2]), a.delta[2]);
             e += w * (huber(d0, a.delta[0]) + huber(d1, a.delta[1]) + huber(d2, a.delta[2]));
+        }
+    }
+}
+
+template <bool NBR3D>
+__host__ __device__ __forceinline__ float neighbour_energy(const float* __restrict__ xi, const LmArgs& a, int i, int j,
+                                                           int z, size_t N, float q0, float q1, float q2,
+                                                           float (&psi)[3]) {
+    float e = 0.0f;
+    psi[0] = psi[1] = psi[2] = 0.0f;
+    plane_terms(xi, a, i, j, z, true, 0.0f, 1.0f, 0.70710678118654752f, N, q0, q1, q2, e, psi);
+    if (NBR3D) {
+#pragma unroll 1
+        for (int dz = -1; dz <= 1; dz += 2) {
+            if (z + dz < 0 || z + dz >= a.nz) continue;
+            plane_terms(xi, a, i, j, z + dz, false, a.w_plane[0], a.w_plane[1], a.w_plane[2], N, q0, q1, q2, e, psi);
         }
     }
     return e;
@@ -97,7 +117,7 @@ __host__ __device__ __forceinline__ void store_normal(float* __restrict__ st, si
     st[9 * N + v] = n.rr;
 }
 
-template <int M>
+template <int M, bool NBR3D>
 __host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, const float* __restrict__ x,
                                                   const float* __restrict__ xi_in, float* __restrict__ xi_out,
                                                   float* __restrict__ lam_io, float* __restrict__ state,
@@ -113,7 +133,7 @@ __host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, 
     // current parameters.  The neighbours are read again for the trial energy below instead of
     // being held in registers through the model evaluations (they are cache hits).
     float psi[3] = {0.0f, 0.0f, 0.0f};
-    const float e0 = neighbour_energy(xi_in, a, i, j, z, N, p0, p1, p2, psi);
+    const float e0 = neighbour_energy<NBR3D>(xi_in, a, i, j, z, N, p0, p1, p2, psi);
     // data-term normal equations at the current parameters
     const Normal n0 = a.have_state ? load_normal(state, N, v) : normal_equations<M>(a.fr, *K, xv, p0, p1, p2);
     const float A00 = n0.A00, A01 = n0.A01, A02 = n0.A02, A11 = n0.A11, A12 = n0.A12, A22 = n0.A22;
@@ -145,7 +165,7 @@ __host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, 
     const float q2 = fminf(fmaxf(p2 + z2 * s2, a.lo[2]), a.hi[2]);
 
     float unused[3];
-    const float e1 = neighbour_energy(xi_in, a, i, j, z, N, q0, q1, q2, unused);
+    const float e1 = neighbour_energy<NBR3D>(xi_in, a, i, j, z, N, q0, q1, q2, unused);
 
     // data term at the trial parameters (with the normal equations when the next iteration needs them)
     Normal n1{};
@@ -175,7 +195,7 @@ uint32_t lm_groups(int nx, int ny, int nz) {
     return (uint32_t)((nx + kLmTileX - 1) / kLmTileX) * ((ny + kLmTileY - 1) / kLmTileY) * nz;
 }
 
-template <int M, class Src>
+template <int M, bool NBR3D, class Src>
 __global__ __launch_bounds__(256) void klm_kernel(Src src) {
     const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
     const LmJob& J = src.find(w);
@@ -187,30 +207,37 @@ __global__ __launch_bounds__(256) void klm_kernel(Src src) {
     const int j = (rr / tx) * kLmTileY + threadIdx.x / kLmTileX;
     const int i = (rr % tx) * kLmTileX + threadIdx.x % kLmTileX;
     if (z >= a.nz || i >= a.nx || j >= a.ny) return;
-    lm_voxel<M>(J.K, J.x, J.xi_in, J.xi_out, J.lam, J.state, a, i, j, z);
+    lm_voxel<M, NBR3D>(J.K, J.x, J.xi_in, J.xi_out, J.lam, J.state, a, i, j, z);
 }
 
-template <class Src>
-static hipError_t dispatch_lm(int M, Src src, uint32_t groups, hipStream_t st) {
+// All jobs of one launch share the neighbourhood (nbr3d), so that the in-plane kernel carries no
+// code or registers for the 3x3x3 case.
+template <bool NBR3D, class Src>
+static hipError_t dispatch_lm_m(int M, Src src, uint32_t groups, hipStream_t st) {
     const dim3 g(xcd_round_up(groups)), b(kLmTileX * kLmTileY);
     switch (M) {
-        case 8: hipLaunchKernelGGL((klm_kernel<8, Src>), g, b, 0, st, src); break;
-        case 16: hipLaunchKernelGGL((klm_kernel<16, Src>), g, b, 0, st, src); break;
-        case 24: hipLaunchKernelGGL((klm_kernel<24, Src>), g, b, 0, st, src); break;
-        case 32: hipLaunchKernelGGL((klm_kernel<32, Src>), g, b, 0, st, src); break;
+        case 8: hipLaunchKernelGGL((klm_kernel<8, NBR3D, Src>), g, b, 0, st, src); break;
+        case 16: hipLaunchKernelGGL((klm_kernel<16, NBR3D, Src>), g, b, 0, st, src); break;
+        case 24: hipLaunchKernelGGL((klm_kernel<24, NBR3D, Src>), g, b, 0, st, src); break;
+        case 32: hipLaunchKernelGGL((klm_kernel<32, NBR3D, Src>), g, b, 0, st, src); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+template <class Src>
+static hipError_t dispatch_lm(int M, bool nbr3d, Src src, uint32_t groups, hipStream_t st) {
+    return nbr3d ? dispatch_lm_m<true>(M, src, groups, st) : dispatch_lm_m<false>(M, src, groups, st);
+}
+
 hipError_t launch_lm(int M, const KinTab* K, const float* x, const float* xi_in, float* xi_out, float* lam,
                      float* state, const LmArgs& a, hipStream_t st) {
     OneJob<LmJob> src{LmJob{a, K, x, xi_in, xi_out, lam, state, 0}};
-    return dispatch_lm(M, src, lm_groups(a.nx, a.ny, a.nz), st);
+    return dispatch_lm(M, a.nbr3d != 0, src, lm_groups(a.nx, a.ny, a.nz), st);
 }
 
-hipError_t launch_lm_jobs(int M, JobTable<LmJob> jobs, uint32_t groups, hipStream_t st) {
-    return dispatch_lm(M, jobs, groups, st);
+hipError_t launch_lm_jobs(int M, bool nbr3d, JobTable<LmJob> jobs, uint32_t groups, hipStream_t st) {
+    return dispatch_lm(M, nbr3d, jobs, groups, st);
 }
 
 }  // namespace kcs

@@ -54,7 +54,7 @@ class c_kinetics(ctypes.Structure):
 
 class c_prior(ctypes.Structure):
     _fields_ = [("beta_kp", ctypes.c_double), ("eps_F", ctypes.c_double), ("beta_h", ctypes.c_double),
-                ("delta", ctypes.c_double * 3), ("kp_on", ctypes.c_int32)]
+                ("delta", ctypes.c_double * 3), ("kp_on", ctypes.c_int32), ("plane_ratio", ctypes.c_double)]
 
 
 class c_lm_opts(ctypes.Structure):
@@ -185,9 +185,11 @@ class Prior:
     beta_h: float
     delta: Sequence[float]
     kp_on: bool = True
+    plane_ratio: float = 0.0  # 0: in-plane 3x3 neighbourhood; > 0: 3x3x3, planes this many pixel sides apart
 
     def c(self) -> c_prior:
-        return c_prior(self.beta_kp, self.eps_F, self.beta_h, (ctypes.c_double * 3)(*self.delta), int(self.kp_on))
+        return c_prior(self.beta_kp, self.eps_F, self.beta_h, (ctypes.c_double * 3)(*self.delta), int(self.kp_on),
+                       float(self.plane_ratio))
 
 
 @dataclass(frozen=True)

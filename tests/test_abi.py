@@ -93,6 +93,8 @@ def test_priors_and_lm_options_validated():
     assert lm(kcs.Prior(1.0, 0.01, 0.1, (1e-3,) * 3).c(), good_l) == kcs.KCS_EINVAL  # beta_kp >= 1
     assert lm(kcs.Prior(0.1, 0.0, 0.1, (1e-3,) * 3).c(), good_l) == kcs.KCS_EINVAL  # eps_F = 0
     assert lm(kcs.Prior(0.1, 0.01, 0.1, (0.0, 1e-3, 1e-3)).c(), good_l) == kcs.KCS_EINVAL  # delta = 0
+    assert lm(kcs.Prior(0.1, 0.01, 0.1, (1e-3,) * 3, True, -1.0).c(), good_l) == kcs.KCS_EINVAL  # plane_ratio < 0
+    assert lm(kcs.Prior(0.1, 0.01, 0.1, (1e-3,) * 3, True, float('nan')).c(), good_l) == kcs.KCS_EINVAL
     assert lm(good_p, kcs.LMOptions(5, 1e-3, 1e-8, 1e8, (0, 0, 0), inputs.LM_HI).c()) == kcs.KCS_EINVAL
     assert lm(good_p, kcs.LMOptions(5, 1e-3, 1.0, 0.1, inputs.LM_LO, inputs.LM_HI).c()) == kcs.KCS_EINVAL
     small = ctypes.c_size_t(1024)

@@ -4,6 +4,8 @@ The studies of a plan are independent, so each study's result must equal what kc
 gives on that study alone (same kernels, same projector variant: identical up to rounding), the
 captured graph must reproduce the eager plan, and the study that has an oracle schedule must match
 the FP64 oracle to the whole-schedule tolerance."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -183,3 +185,29 @@ def test_plan_rejects_bad_study(batch):
     s = as_study(d, studies[0].cfg.Q, (2, 1))
     with pytest.raises(kcs.KcsError, match="study 0"):
         kcs.kcs_plan_create([s])
+
+
+def test_plan_mixes_neighbourhoods():
+    """A plan holding one in-plane and one 3x3x3 study runs their fits as separate launches and
+    equals the per-study calls."""
+    studies, ranges = batch_studies()
+    studies, ranges = [studies[0], studies[3]], [(0, 2), (1, 3)]
+    ref, got = [], []
+    for st, (s0, s1) in zip(studies, ranges):
+        d = device_state(st)
+        if st is studies[1]:
+            d["p"] = dataclasses.replace(d["p"], plane_ratio=1.0)
+        for sw in range(s0, s1):
+            kcs.kcs_icm_sweep(d["g"], d["f"], d["k"], d["p"], d["lm"], d["sino"], st.cfg.Q, sw, d["x"], d["params"],
+                              d["lam"], d["work"])
+        ref.append(d)
+    ds = [device_state(st) for st in studies]
+    ds[1]["p"] = dataclasses.replace(ds[1]["p"], plane_ratio=1.0)
+    plan = kcs.kcs_plan_create([as_study(d, st.cfg.Q, r) for d, st, r in zip(ds, studies, ranges)], kcs.KCS_PLAN_GRAPH)
+    kcs.kcs_plan_run(plan)
+    torch.cuda.synchronize()
+    kcs.kcs_plan_destroy(plan)
+    for st, a, b in zip(studies, ds, ref):
+        err = state_errors(a, b)
+        print(f"{st.cfg.name}: plan vs plain relL2 {err:.2e}")
+        assert err < 1e-6

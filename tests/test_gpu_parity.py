@@ -1,6 +1,8 @@
 """GPU parity: every entry point of the HIP library against the FP64 oracle on the same
 seeded inputs (relative L2 tolerances: 1e-5 for one projection / back projection / update,
 1e-3 for images and kinetic maps after the whole ICM schedule)."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -211,6 +213,36 @@ def test_lm_fit_parity():
               f"(all object voxels {rel_l2(gp[i][mask], op[i][mask]):.2e}; other path {int((mask & ~same).sum())})")
         assert e < 1e-4
     assert same[mask].mean() > 0.99
+
+
+def test_lm_fit_parity_3x3x3_neighbourhood():
+    """The fit with the 3x3x3 Huber neighbourhood (planes 0.97 pixel sides apart) on a 3-plane
+    128x128 stack against the oracle, over the object voxels on the oracle's accept/reject path."""
+    cfg = inputs.scaled(inputs.batch_configs()[3], nz=3, counts=4e5 * 3)
+    st = oracle.make_study(cfg)
+    prior = dataclasses.replace(st.prior, plane_ratio=0.97)
+    g, f, k, p, lm = kcs_objects(st)
+    p = dataclasses.replace(p, plane_ratio=0.97)
+    rng = np.random.default_rng(8)
+    x = st.truth_x * (1 + 0.05 * rng.standard_normal(st.truth_x.shape))
+    x = x.astype(np.float32).astype(np.float64)
+    shp = x.shape[:3]
+    params0 = np.stack([np.full(shp, v) for v in inputs.XI0])
+    lam0 = np.zeros(shp)
+    work = kcs.alloc_workspace(g, M, 0, DEV)
+    pd, ld = dev(params0), dev(lam0)
+    kcs.kcs_lm_fit(g, f, k, p, lm, dev(x), pd, ld, work)
+    torch.cuda.synchronize()
+    op, ol = oracle.lm_fit(st.frames, st.kin, prior, st.lm, x, params0, lam0)
+    gp = pd.cpu().numpy()
+    same = np.abs(ld.cpu().numpy() / ol - 1.0) < 1e-3
+    keep = st.mask & same
+    for i in range(3):
+        e = rel_l2(gp[i][keep], op[i][keep])
+        print(f"3x3x3 lm param {i}: relL2 {e:.2e} over object voxels on the oracle's path "
+              f"({int((st.mask & ~same).sum())} of {int(st.mask.sum())} on another)")
+        assert e < 1e-4
+    assert same[st.mask].mean() > 0.99
 
 
 def compare_icm(gx, gp, glam, ox, op, olam, frames, label, tol_img=1e-3, tol_maps=1e-3):
