@@ -29,7 +29,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def synthesize(cfg, dev, seed_offset=0, phantom=None):
+def synthesize(cfg, dev, seed_offset=0, phantom=None, plane_ratio=0.0):
     """Measured sinogram and study constants for `cfg`, built with the HIP library (`phantom`:
     the (maps, mask) of inputs.phantom_maps(cfg), if already computed)."""
     import numpy as np
@@ -72,7 +72,7 @@ def synthesize(cfg, dev, seed_offset=0, phantom=None):
     cp = lambda t: -((inputs.FENG["A1"] * t - inputs.FENG["A2"] - inputs.FENG["A3"]) * np.exp(inputs.FENG["l1"] * t)
                      + inputs.FENG["A2"] * np.exp(inputs.FENG["l2"] * t) + inputs.FENG["A3"] * np.exp(inputs.FENG["l3"] * t))
     peak = -minimize_scalar(cp, bounds=(0.0, 2.0), method="bounded", options=dict(xatol=1e-10)).fun
-    prior = kcs.Prior(inputs.BETA_KP, 1e-4 * peak, cfg.beta_h, (delta,) * 3, True)
+    prior = kcs.Prior(inputs.BETA_KP, 1e-4 * peak, cfg.beta_h, (delta,) * 3, True, plane_ratio)
     lm = kcs.LMOptions(cfg.n_lm, inputs.LM_TAU, inputs.LM_LAM_MIN, inputs.LM_LAM_MAX, inputs.LM_LO, inputs.LM_HI,
                        inputs.LM_ETA)
     return g, f, kin, prior, lm, sino
@@ -428,6 +428,8 @@ def main():
                     help="comma-separated runs of the serve mode: served|serial @ poisson|saturated")
     ap.add_argument("--config", default="cfg3", choices=["cfg1", "cfg2", "cfg3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plane-ratio", type=float, default=0.0,
+                    help="sweep mode: > 0 fits with the 3x3x3 Huber neighbourhood, planes this many pixel sides apart")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the ICM sweep shards by plane with no "
@@ -460,7 +462,7 @@ def main():
     dev = torch.device("cuda:0")
     cfg = inputs.CONFIGS[args.config]()
     t = time.perf_counter()
-    g, f, kin, prior, lm, sino = synthesize(cfg, dev)
+    g, f, kin, prior, lm, sino = synthesize(cfg, dev, plane_ratio=args.plane_ratio)
     torch.cuda.synchronize()
     log(f"synthesised {cfg.name} in {time.perf_counter() - t:.1f} s; counts {float(sino.sum()):.3e}")
     M, Q = f.M, cfg.Q
@@ -530,7 +532,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded phantom, closed-form FDG TACs, Poisson counts)",
         "config": {"workload": f"{cfg.name}: {cfg.nx}x{cfg.ny}x{cfg.nz} voxels, {cfg.n_ang} angles x {cfg.n_bin} "
-                               f"bins, {M} frames, {Q} subsets, {cfg.n_lm} MAP-LM iterations per sweep",
+                               f"bins, {M} frames, {Q} subsets, {cfg.n_lm} MAP-LM iterations per sweep"
+                               + (f", 3x3x3 Huber neighbourhood (planes {args.plane_ratio} pixel sides apart)"
+                                  if args.plane_ratio > 0 else ""),
                    "counts": cfg.counts, "background": cfg.bg_frac},
         "roofline": roof,
         "kernels": kernels,
