@@ -29,15 +29,20 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def synthesize(cfg, dev, seed_offset=0, phantom=None, plane_ratio=0.0):
+def synthesize(cfg, dev, seed_offset=0, phantom=None, plane_ratio=0.0, correction=False):
     """Measured sinogram and study constants for `cfg`, built with the HIP library (`phantom`:
-    the (maps, mask) of inputs.phantom_maps(cfg), if already computed)."""
+    the (maps, mask) of inputs.phantom_maps(cfg), if already computed; `correction`: a head-sized
+    water cylinder's attenuation times detector efficiencies in the system matrix)."""
     import numpy as np
     import torch
 
     from paper_1803_10045_amd import inputs, kcs
 
     g = kcs.Geometry.from_config(cfg)
+    if correction:
+        import dataclasses
+        mult = inputs.correction_sinogram(cfg.nz, cfg.n_ang, cfg.n_bin, cfg.bin_mm, 100.0, seed=cfg.seed)
+        g = dataclasses.replace(g, mult=torch.from_numpy(mult).to(dev))
     t0, t1 = inputs.frame_times()
     dt = t1 - t0
     M = len(t0)
@@ -428,6 +433,8 @@ def main():
                     help="comma-separated runs of the serve mode: served|serial @ poisson|saturated")
     ap.add_argument("--config", default="cfg3", choices=["cfg1", "cfg2", "cfg3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--correction", action="store_true",
+                    help="sweep mode: attenuation (head-sized water cylinder) x detector efficiencies in the model")
     ap.add_argument("--plane-ratio", type=float, default=0.0,
                     help="sweep mode: > 0 fits with the 3x3x3 Huber neighbourhood, planes this many pixel sides apart")
     args = ap.parse_args()
@@ -462,7 +469,7 @@ def main():
     dev = torch.device("cuda:0")
     cfg = inputs.CONFIGS[args.config]()
     t = time.perf_counter()
-    g, f, kin, prior, lm, sino = synthesize(cfg, dev, plane_ratio=args.plane_ratio)
+    g, f, kin, prior, lm, sino = synthesize(cfg, dev, plane_ratio=args.plane_ratio, correction=args.correction)
     torch.cuda.synchronize()
     log(f"synthesised {cfg.name} in {time.perf_counter() - t:.1f} s; counts {float(sino.sum()):.3e}")
     M, Q = f.M, cfg.Q
@@ -534,7 +541,8 @@ def main():
         "config": {"workload": f"{cfg.name}: {cfg.nx}x{cfg.ny}x{cfg.nz} voxels, {cfg.n_ang} angles x {cfg.n_bin} "
                                f"bins, {M} frames, {Q} subsets, {cfg.n_lm} MAP-LM iterations per sweep"
                                + (f", 3x3x3 Huber neighbourhood (planes {args.plane_ratio} pixel sides apart)"
-                                  if args.plane_ratio > 0 else ""),
+                                  if args.plane_ratio > 0 else "")
+                               + (", attenuation x efficiency correction sinogram" if args.correction else ""),
                    "counts": cfg.counts, "background": cfg.bg_frac},
         "roofline": roof,
         "kernels": kernels,

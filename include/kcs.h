@@ -62,6 +62,12 @@ typedef struct kcs_geometry {
     int32_t n_bin;      /* radial bins per angle, >= 1 */
     double bin_mm;      /* radial bin width > 0 */
     double ang0_rad;    /* angle of projection 0 */
+    /* Multiplicative correction sinogram [nz][n_ang][n_bin] (device, read only, caller-owned):
+     * the product of the attenuation factor and the detector-pair efficiency of each ray, finite
+     * and >= 0 (the acquisition model of Sec. II-A includes attenuation).  The system matrix becomes diag(d_mult) P: every projection, back projection and
+     * sensitivity below is weighted by it.  NULL means all ones (no attenuation, uniform
+     * efficiencies).  The library reads only the rays it projects. */
+    const float* d_mult;
 } kcs_geometry;
 
 typedef struct kcs_frames {
@@ -146,15 +152,17 @@ int kcs_osl_update(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetic
 
 /* lm->n_iter synchronous MAP-LM iterations (Eq. 4-7) on every voxel of the image d_x:
  *   g = J^T (x - F) - beta_h sum_k w_k psi(xi_v - xi_k),  step = (J^T J + lambda I)^{-1} g,
- * trial clipped to [lo, hi] and kept iff the voxel's objective strictly decreases; neighbours k
- * are the in-plane 8-neighbourhood (w = 1 edge, 1/sqrt 2 diagonal) read from the maps of the
- * previous iteration.  d_params [3][nz][ny][nx] and d_lambda [nz][ny][nx] are updated. */
+ * trial clipped to [lo, hi] and kept iff the voxel's objective decreases by more than eta times
+ * its value (kcs_lm_opts); neighbours k are the in-plane 8-neighbourhood (w = 1 edge, 1/sqrt 2
+ * diagonal) or, with p->plane_ratio > 0, the 3x3x3 cube (w = 1 / distance), read from the maps
+ * of the previous iteration.  d_params [3][nz][ny][nx] and d_lambda [nz][ny][nx] are updated. */
 int kcs_lm_fit(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics* k, const kcs_prior* p,
                const kcs_lm_opts* lm, const float* d_x, float* d_params, float* d_lambda, void* d_work,
                size_t work_bytes, hipStream_t stream);
 
 /* Initial ICM state: x_m = max(sum_d (s_dm - r_m), 1) / (E_m sum_v sum_d p_vd) in every voxel,
- * maps = xi0 everywhere, lambda = 0 (initialised by the first LM iteration). */
+ * maps = xi0 everywhere, lambda = 0 (initialised by the first LM iteration).  The flat start
+ * ignores g->d_mult (the first OSL update rescales the image to the data). */
 int kcs_init_state(const kcs_geometry* g, const kcs_frames* f, const float* d_sino, const double xi0[3],
                    float* d_x, float* d_params, float* d_lambda, void* d_work, size_t work_bytes,
                    hipStream_t stream);

@@ -9,5 +9,6 @@ from .geometry import (Geometry, build_oracle_library, forward, back, subset_ang
                        subset_sensitivity, system_matrix, siddon_line)
 from .model import Kinetics, cp, input_integrals, model_tac, cumulative_tissue, moments, net_influx
 from .recon import (Frames, LMOptions, Prior, expected_counts, huber, huber_grad, icm, icm_sweep,
-                    initial_image, initial_state, lm_fit, lm_iteration, neighbour_terms, osl_update)
+                    initial_image, initial_state, lm_fit, lm_iteration, neighbour_terms, osl_update,
+                    subset_mult)
 from .study import Study, make_study

@@ -70,19 +70,36 @@ class Frames:
 # OS-MAP-OSL-KP
 # ------------------------------------------------------------------------------------------
 
-def expected_counts(g: geo.Geometry, fr: Frames, x: np.ndarray, q: int, Q: int) -> np.ndarray:
-    """ybar_dm = E_m sum_v p_vd x_vm + r_m for the rays of subset q: (nz, A_q, n_bin, M)."""
-    return fr.E * geo.forward(g, x, q, Q) + fr.r
+def subset_mult(g: geo.Geometry, mult, q: int, Q: int):
+    """The multiplicative correction (attenuation x efficiency) of the rays of subset q,
+    (nz, A_q, n_bin, 1), or None without one (all ones).  mult: (nz, n_ang, n_bin)."""
+    if mult is None:
+        return None
+    return np.asarray(mult, dtype=np.float64)[:, geo.subset_angles(g.n_ang, q, Q), :, None]
+
+
+def expected_counts(g: geo.Geometry, fr: Frames, x: np.ndarray, q: int, Q: int, mult=None) -> np.ndarray:
+    """ybar_dm = E_m mu_d sum_v p_vd x_vm + r_m for the rays of subset q: (nz, A_q, n_bin, M);
+    mu_d = 1 without a correction sinogram (the system matrix is diag(mu) P)."""
+    proj = geo.forward(g, x, q, Q)
+    mu = subset_mult(g, mult, q, Q)
+    return fr.E * (proj if mu is None else mu * proj) + fr.r
 
 
 def osl_update(g: geo.Geometry, fr: Frames, kin: Kinetics, prior: Prior, sino: np.ndarray, params: np.ndarray,
-               x: np.ndarray, q: int, Q: int, kp: bool) -> np.ndarray:
-    """One OS-MAP-OSL-KP update of the image x (nz, ny, nx, M) with subset q (Eq. 2-3)."""
-    ybar = expected_counts(g, fr, x, q, Q)
+               x: np.ndarray, q: int, Q: int, kp: bool, mult=None) -> np.ndarray:
+    """One OS-MAP-OSL-KP update of the image x (nz, ny, nx, M) with subset q (Eq. 2-3), with the
+    system matrix diag(mult) P when a correction sinogram mult (nz, n_ang, n_bin) is given."""
+    ybar = expected_counts(g, fr, x, q, Q, mult)
     s_q = sino[:, geo.subset_angles(g.n_ang, q, Q)]
     ratio = np.where(ybar > 0.0, s_q / np.where(ybar > 0.0, ybar, 1.0), 0.0)
-    bp = fr.E * geo.back(g, ratio, q, Q)
-    n = fr.E * geo.subset_sensitivity(g, q, Q)[None, :, :, None]
+    mu = subset_mult(g, mult, q, Q)
+    if mu is None:
+        bp = fr.E * geo.back(g, ratio, q, Q)
+        n = fr.E * geo.subset_sensitivity(g, q, Q)[None, :, :, None]
+    else:
+        bp = fr.E * geo.back(g, mu * ratio, q, Q)
+        n = fr.E * geo.back(g, np.ascontiguousarray(mu), q, Q)  # sum_d mu_d p_vd per plane, (nz, ny, nx, 1)
     n = np.broadcast_to(n, x.shape)
     if kp:
         F = model_tac(params.reshape(3, -1).T, fr.t0, fr.t1, kin).reshape(x.shape)
@@ -196,13 +213,13 @@ def lm_fit(fr, kin, prior, opt, x, params, lam):
 # ICM
 # ------------------------------------------------------------------------------------------
 
-def icm_sweep(g, fr, kin, prior, opt, sino, x, params, lam, Q: int, sweep_idx: int):
+def icm_sweep(g, fr, kin, prior, opt, sino, x, params, lam, Q: int, sweep_idx: int, mult=None):
     """One ICM sweep (Sec. II-D): OS-MAP-OSL-KP over all Q subsets given the maps, then MAP-LM
     given the new image.  Each sweep's MAP-LM is a new fit to a new image, so its damping starts
     from tau * max diag(J^T J) (the lambda passed in is ignored; the final one is returned)."""
     kp = prior.kp_on and sweep_idx > 0
     for q in range(Q):
-        x = osl_update(g, fr, kin, prior, sino, params, x, q, Q, kp)
+        x = osl_update(g, fr, kin, prior, sino, params, x, q, Q, kp, mult)
     params, lam = lm_fit(fr, kin, prior, opt, x, params, np.zeros_like(lam))
     return x, params, lam
 
@@ -216,8 +233,10 @@ def initial_state(g: geo.Geometry, fr: Frames, sino: np.ndarray, xi0=(0.08, 0.12
     return x, params, lam
 
 
-def icm(g, fr, kin, prior, opt, sino, Q: int, n_sweeps: int, state=None):
+def icm(g, fr, kin, prior, opt, sino, Q: int, n_sweeps: int, state=None, mult=None):
+    """n_sweeps ICM sweeps from the initial state (the flat start ignores mult: the first OSL
+    update rescales the image to the data)."""
     x, params, lam = state if state is not None else initial_state(g, fr, sino)
     for s in range(n_sweeps):
-        x, params, lam = icm_sweep(g, fr, kin, prior, opt, sino, x, params, lam, Q, s)
+        x, params, lam = icm_sweep(g, fr, kin, prior, opt, sino, x, params, lam, Q, s, mult)
     return x, params, lam

@@ -216,6 +216,7 @@ ProjArgs proj_args(const kcs_geometry& g, const FrameTab& fr, int32_t q, int32_t
     p.du = (float)g.bin_mm;
     p.inv_du = (float)(1.0 / g.bin_mm);
     p.ang0 = g.ang0_rad;
+    p.mult = g.d_mult;
     p.fr = fr;
     return p;
 }

@@ -63,7 +63,8 @@ __device__ __forceinline__ void subset_angles_bins_to_lds(AngleRec* sA, int2* sB
     __syncthreads();
 }
 
-// acc_m = sum_{d in S_q} p_vd y_dm and sens = sum_{d in S_q} p_vd for voxel (i, j, z).
+// acc_m = sum_{d in S_q} mu_d p_vd y_dm and sens = sum_{d in S_q} mu_d p_vd for voxel (i, j, z),
+// mu_d the ray's multiplicative correction (1 without one).
 template <int M>
 __host__ __device__ __forceinline__ void gather(const AngleRec* sA, const ProjArgs& p, const float* __restrict__ y, int i, int j,
                                        int z, float (&acc)[M], float& sens) {
@@ -75,7 +76,9 @@ __host__ __device__ __forceinline__ void gather(const AngleRec* sA, const ProjAr
     const float* yz = y + (size_t)z * p.A_q * p.n_bin * M;
     for (int al = 0; al < p.A_q; ++al) {
         const float* ya = yz + (size_t)al * p.n_bin * M;
+        const float* mua = p.mult ? p.mult + ((size_t)z * p.n_ang + p.q + al * p.Q) * p.n_bin : nullptr;
         pixel_footprint(sA[al], xc, yc, p.n_bin, p.du, p.inv_du, [&](int b, float len) {
+            if (mua) len *= mua[b];
             float v[M];
             load_record<M>(ya + (size_t)b * M, v);
 #pragma unroll
@@ -153,7 +156,8 @@ __host__ __device__ inline int box_slots(int w, int hgt, float h, float du) {
     return (int)floorf(sqrtf((float)(w * w + hgt * hgt)) * h / du) + 3;
 }
 
-// LDS stride of a staged bin record in floats: padded by 4 so that the records of nearby bins,
+// LDS stride of a staged bin record in floats: padded by 4 (the first padding float holds the
+// ray's correction factor) so that the records of nearby bins,
 // which the voxels of a wavefront read at the same time, spread over the banks.
 __host__ __device__ constexpr int stage_record(int M) { return M + 4; }
 
@@ -172,8 +176,9 @@ __host__ __device__ inline int stage_chunk(int M, int slots, int A_q) {
 }
 
 // For the voxel (i, j) of this thread in the staged tile (i0, j0) of plane z (valid: inside the
-// image): acc_m = sum_{d in S_q} p_vd y_dm and sens = sum_{d in S_q} p_vd.  All threads of the
-// workgroup must call it (it synchronises).
+// image): acc_m = sum_{d in S_q} mu_d p_vd y_dm and sens = sum_{d in S_q} mu_d p_vd.  The staged
+// record of bin d holds mu_d y_d and, in its first padding float, mu_d (1 without a correction
+// sinogram).  All threads of the workgroup must call it (it synchronises).
 template <int M>
 __device__ __forceinline__ void staged_gather(const AngleRec* sA, const int2* sBB, float4* sR, const ProjArgs& p,
                                               const float* __restrict__ y, int z, bool valid, int i, int j,
@@ -197,8 +202,19 @@ __device__ __forceinline__ void staged_gather(const AngleRec* sA, const int2* sB
             if (b > bb.y) continue;
             const float4* src = yz + ((size_t)al * p.n_bin + b) * (M / 4);
             float4* dst = sR + rec * (stage_record(M) / 4);
+            if (p.mult) {
+                const float mu = p.mult[((size_t)z * p.n_ang + p.q + al * p.Q) * p.n_bin + b];
 #pragma unroll
-            for (int k = 0; k < M / 4; ++k) dst[k] = src[k];
+                for (int k = 0; k < M / 4; ++k) {
+                    const float4 v = src[k];
+                    dst[k] = make_float4(mu * v.x, mu * v.y, mu * v.z, mu * v.w);
+                }
+                dst[M / 4] = make_float4(mu, 0.0f, 0.0f, 0.0f);
+            } else {
+#pragma unroll
+                for (int k = 0; k < M / 4; ++k) dst[k] = src[k];
+                dst[M / 4] = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
+            }
         }
         __syncthreads();
         if (!valid) continue;
@@ -224,7 +240,7 @@ __device__ __forceinline__ void staged_gather(const AngleRec* sA, const int2* sB
                 load_record<M>(rec, v);
 #pragma unroll
                 for (int m = 0; m < M; ++m) acc[m] = fmaf(len, v[m], acc[m]);
-                sens += len;
+                sens = fmaf(len, rec[M], sens);
             }
         }
     }

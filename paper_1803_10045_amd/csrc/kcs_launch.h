@@ -12,6 +12,7 @@ struct ProjArgs {
     int32_t rays_per_plane;   // A_q * n_bin
     float h, inv_h, du, inv_du;
     double ang0;
+    const float* mult;  // [nz][n_ang][n_bin] multiplicative correction per ray, or NULL (ones)
     FrameTab fr;
 };
 

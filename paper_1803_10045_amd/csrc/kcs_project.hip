@@ -23,25 +23,28 @@
 
 namespace kcs {
 
-// Expected counts or measured/expected ratio of ray (z, al, b) from its line integrals acc.
+// Expected counts or measured/expected ratio of ray (z, al, b) from its line integrals acc:
+// ybar_m = E_m mu acc_m + r_m, mu the ray's multiplicative correction (1 without one).
 template <int M, bool RATIO>
 __host__ __device__ __forceinline__ void ray_epilogue(const ProjArgs& p, const float* __restrict__ sino,
                                                       float* __restrict__ out, int z, int al, int b,
                                                       const float (&acc)[M]) {
     const int a = p.q + al * p.Q;
     const size_t o = (((size_t)z * p.A_q + al) * p.n_bin + b) * M;
+    const size_t ray = ((size_t)z * p.n_ang + a) * p.n_bin + b;
+    const float mu = p.mult ? p.mult[ray] : 1.0f;
     float y[M];
     if (RATIO) {
         float s[M];
-        load_record<M>(sino + (((size_t)z * p.n_ang + a) * p.n_bin + b) * M, s);
+        load_record<M>(sino + ray * M, s);
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            const float yb = fmaf(p.fr.E[m], acc[m], p.fr.r[m]);
+            const float yb = fmaf(p.fr.E[m] * mu, acc[m], p.fr.r[m]);
             y[m] = yb > 0.0f ? s[m] / yb : 0.0f;
         }
     } else {
 #pragma unroll
-        for (int m = 0; m < M; ++m) y[m] = fmaf(p.fr.E[m], acc[m], p.fr.r[m]);
+        for (int m = 0; m < M; ++m) y[m] = fmaf(p.fr.E[m] * mu, acc[m], p.fr.r[m]);
     }
     store_record<M>(out + o, y);
 }

@@ -239,3 +239,23 @@ def poisson_counts(expected: np.ndarray, seed: int) -> np.ndarray:
     """Poisson draws of an expected-count array, returned as FP32 (exact integers)."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 0x5151])))
     return rng.poisson(np.asarray(expected, dtype=np.float64)).astype(np.float32)
+
+
+MU_WATER_PER_MM = 0.0096  # linear attenuation of water at 511 keV
+
+
+def correction_sinogram(nz: int, n_ang: int, n_bin: int, bin_mm: float, radius_mm: float, seed: int = 21,
+                        dead_bins: int = 2) -> np.ndarray:
+    """Multiplicative correction per ray, (nz, n_ang, n_bin) float32: the attenuation of a water
+    cylinder of the given radius centred in the field (exp(-mu L), L the chord of the ray through
+    it) times detector-pair efficiencies drawn uniformly in [0.8, 1.2], with `dead_bins` radial
+    bins of zero efficiency (a detector gap) at one angle of every plane."""
+    rng = np.random.default_rng(seed)
+    u = (np.arange(n_bin) - 0.5 * (n_bin - 1)) * bin_mm
+    chord = 2.0 * np.sqrt(np.maximum(radius_mm ** 2 - u ** 2, 0.0))
+    att = np.exp(-MU_WATER_PER_MM * chord)
+    eff = rng.uniform(0.8, 1.2, (nz, n_ang, n_bin))
+    mult = att[None, None, :] * eff
+    if dead_bins > 0:
+        mult[:, n_ang // 3, n_bin // 2:n_bin // 2 + dead_bins] = 0.0
+    return mult.astype(np.float32)

@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 from functools import lru_cache
 from typing import Optional, Sequence
 
@@ -38,7 +38,7 @@ class KcsError(RuntimeError):
 class c_geometry(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("pixel_mm", ctypes.c_double),
                 ("n_ang", ctypes.c_int32), ("n_bin", ctypes.c_int32), ("bin_mm", ctypes.c_double),
-                ("ang0_rad", ctypes.c_double)]
+                ("ang0_rad", ctypes.c_double), ("d_mult", ctypes.c_void_p)]
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -127,13 +127,17 @@ class Geometry:
     n_bin: int
     bin_mm: float
     ang0_rad: float = 0.0
+    # multiplicative correction sinogram (attenuation x efficiency) [nz][n_ang][n_bin], a float32
+    # device tensor, or None for all ones
+    mult: Optional[object] = field(default=None, compare=False, hash=False, repr=False)
 
     @classmethod
     def from_config(cls, cfg) -> "Geometry":
         return cls(cfg.nx, cfg.ny, cfg.nz, cfg.pixel_mm, cfg.n_ang, cfg.n_bin, cfg.bin_mm, cfg.ang0)
 
     def c(self) -> c_geometry:
-        return c_geometry(self.nx, self.ny, self.nz, self.pixel_mm, self.n_ang, self.n_bin, self.bin_mm, self.ang0_rad)
+        return c_geometry(self.nx, self.ny, self.nz, self.pixel_mm, self.n_ang, self.n_bin, self.bin_mm, self.ang0_rad,
+                          _ptr(self.mult, (self.nz, self.n_ang, self.n_bin), "mult"))
 
     @property
     def n_vox(self) -> int:
