@@ -420,12 +420,54 @@ def run_ki(args):
                       "hbm_frac": round(gbps / 8000.0, 4), "config": {"workload": cfg.name}}), flush=True)
 
 
+def run_compare(args):
+    """The method comparison of the simulation on the ring phantom: INDIRECT, DIRECT and KCS DIRECT
+    (for each spatial weight of `--beta-h`, decades apart) over `--realizations` noise
+    realizations (one plan per sweep over all of them), bias and standard deviation of K1 and K_i
+    per region after 2, 5 and `--sweeps` sweeps."""
+    import torch
+
+    from paper_1803_10045_amd import compare, inputs
+
+    dev = torch.device("cuda:0")
+    cfg = inputs.rings_config(128, nz=4)
+    g, f, kin, prior, lm, ybar, maps, labels = compare.synthesize_truth(cfg, dev)
+    R, S = args.realizations, args.sweeps
+    record = sorted({2, 5, S} & set(range(1, S + 1)))
+    betas = [float(b) for b in args.beta_h.split(",")]
+    runs = [("indirect", 0.0), ("direct", 0.0)] + [("kcs", b) for b in betas]
+    out = {}
+    t_all = 0.0
+    for method, beta in runs:
+        sinos = [compare.realization(ybar, 1000 + r) for r in range(R)]  # the same realizations for every run
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = compare.run_method(g, f, kin, compare.method_prior(prior, method, beta), lm, sinos, cfg.Q, S, record,
+                                 dev)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        t_all += dt
+        key = method if method != "kcs" else f"kcs@beta_h={beta:g}"
+        out[key] = {"seconds": round(dt, 3), "rows": compare.summarize(res, maps, labels)}
+        log(f"{key}: {R} realizations x {S} sweeps in {dt:.2f} s")
+        del sinos, res
+    print(json.dumps({"metric": "comparison realization-sweeps/s", "value": round(len(runs) * R * S / t_all, 2),
+                      "unit": "realization-sweeps/s", "realizations": R, "sweeps": S,
+                      "config": {"workload": f"{cfg.name}: ring phantom (Table I tissue parameters, blood square), "
+                                             f"{cfg.n_ang} angles x {cfg.n_bin} bins, 24 frames (Eq. 8 blocks), "
+                                             f"{cfg.Q} subsets, {cfg.counts:.1e} counts"},
+                      "methods": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--mode", default="sweep", choices=["sweep", "batched", "serve", "copy", "ki"])
+    ap.add_argument("--mode", default="sweep", choices=["sweep", "batched", "serve", "copy", "ki", "compare"])
+    ap.add_argument("--realizations", type=int, default=32, help="compare mode: noise realizations per method")
+    ap.add_argument("--sweeps", type=int, default=10, help="compare mode: ICM sweeps per realization")
+    ap.add_argument("--beta-h", default="1e2,1e3,1e4,1e5", help="compare mode: KCS spatial weights (comma-separated)")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--rate", type=float, default=4.0)
     ap.add_argument("--budget-gb", type=float, default=250.0)
@@ -448,6 +490,9 @@ def main():
     if args.mode == "copy":
         args.steps = 4 if args.steps is None else args.steps
         run_copy(args)
+        return
+    if args.mode == "compare":
+        run_compare(args)
         return
     if args.mode == "ki":
         args.steps = 20 if args.steps is None else args.steps

@@ -49,8 +49,7 @@ def frame_times(blocks=FRAME_BLOCKS) -> Tuple[np.ndarray, np.ndarray]:
     """Frame start and end times in minutes (FP64), contiguous from t=0."""
     durs = np.concatenate([np.full(n, s / 60.0) for n, s in blocks])
     t1 = np.cumsum(durs)
-    t0 = t1 - durs
-    t0[0] = 0.0
+    t0 = np.concatenate([[0.0], t1[:-1]])  # each frame starts exactly where the previous one ends
     return t0, t1
 
 
@@ -161,6 +160,39 @@ def _centres(n: int) -> np.ndarray:
     return np.arange(n, dtype=np.float64) - (n - 1) / 2.0
 
 
+# (K1, k2, k3) of the three tissue regions of the simulation table (Sec. III-A, Table I); its
+# blood region has no tissue (K1 = 0) and carries the plasma input itself.
+TABLE1_INNER = (0.75, 0.35, 0.031)
+TABLE1_MIDDLE = (0.62, 0.30, 0.026)
+TABLE1_OUTER = (0.51, 0.27, 0.018)
+RING_REGIONS = {1: "blood", 2: "inner", 3: "middle", 4: "outer"}
+
+
+def ring_labels(cfg: StudyConfig) -> np.ndarray:
+    """Stand-in for the simulation phantom (its figure is not available): per voxel 0 outside,
+    1 in a central blood square of half-side 0.06 n, and 2 / 3 / 4 in concentric rings (inner,
+    middle, outer) out to radii 0.18 n, 0.30 n and 0.42 n, n the matrix size; every plane alike."""
+    nz, ny, nx = cfg.nz, cfg.ny, cfg.nx
+    n = float(min(nx, ny))
+    y = _centres(ny)[:, None]
+    x = _centres(nx)[None, :]
+    r = np.sqrt(x * x + y * y)
+    lab = np.zeros((ny, nx), dtype=np.int32)
+    lab[r <= 0.42 * n] = 4
+    lab[r <= 0.30 * n] = 3
+    lab[r <= 0.18 * n] = 2
+    lab[(np.abs(x) <= 0.06 * n) & (np.abs(y) <= 0.06 * n)] = 1
+    return np.broadcast_to(lab, (nz, ny, nx)).copy()
+
+
+def rings_config(n: int = 128, nz: int = 4, counts_per_plane: float = 4e6, seed: int = 41) -> StudyConfig:
+    """The comparison study: the ring phantom on an n x n grid (256 mm field), 1.3 n angles,
+    n bins, 6 subsets, 10 sweeps (frames: frame_times(FRAME_BLOCKS_EQ8), the simulation's schedule)."""
+    h = 256.0 / n
+    return StudyConfig(f"rings_{n}x{n}x{nz}", n, n, nz, h, h, int(round(1.3 * n)), n, h, counts_per_plane * nz,
+                       0.1, Q=6, n_sweeps=10, phantom="rings", n_lesions=0, seed=seed)
+
+
 def phantom_maps(cfg: StudyConfig) -> Tuple[np.ndarray, np.ndarray]:
     """True kinetic maps ``(3, nz, ny, nx)`` FP64 (K1, k2, k3) and the object mask ``(nz, ny, nx)``.
 
@@ -194,6 +226,14 @@ def phantom_maps(cfg: StudyConfig) -> Tuple[np.ndarray, np.ndarray]:
             for p in range(3):
                 maps[p][hot] = HOT[p]
         return maps, obj
+    if cfg.phantom == "rings":
+        labels = ring_labels(cfg)
+        # blood square: K1 = 0 (no tissue), its k2, k3 (which then do not change the model TAC)
+        # set to the fit's start so that the model stays defined (k2 + k3 > 0)
+        for reg, par in ((1, (0.0, XI0[1], XI0[2])), (2, TABLE1_INNER), (3, TABLE1_MIDDLE), (4, TABLE1_OUTER)):
+            for p in range(3):
+                maps[p][labels == reg] = par[p]
+        return maps, labels > 0
     if cfg.phantom != "brain":
         raise ValueError(cfg.phantom)
     s = nx / 128.0
