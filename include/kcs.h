@@ -72,7 +72,8 @@ typedef struct kcs_geometry {
 
 typedef struct kcs_frames {
     int32_t n_frames;     /* M */
-    const double* t0_min; /* host [M] frame start, minutes, >= 0 */
+    const double* t0_min; /* host [M] frame start, minutes, >= 0; a start within 1e-12 (relative) of the
+                             previous frame's end is taken as that end (frames then share a boundary) */
     const double* t1_min; /* host [M] frame end, > start, frames sorted and non-overlapping */
     const double* scale;  /* host [M] E_m = c * (t1_m - t0_m): expected counts per activity unit per mm of path */
     const double* bg;     /* host [M] r_m >= 0: flat additive background, counts per bin (randoms + scatter) */

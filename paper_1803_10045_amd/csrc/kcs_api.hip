@@ -50,6 +50,17 @@ int check_geometry(const kcs_geometry* g) {
     return KCS_OK;
 }
 
+// A frame that starts within rounding of the previous frame's end (a schedule built as end -
+// duration) starts exactly there: such frames share a boundary, whose integrals the model
+// evaluates once.
+constexpr double kFrameSnap = 1e-12;
+
+bool starts_at_previous_end(const kcs_frames& f, int m) {
+    return m > 0 && std::fabs(f.t0_min[m] - f.t1_min[m - 1]) <= kFrameSnap * std::max(1.0, f.t1_min[m - 1]);
+}
+
+double frame_start(const kcs_frames& f, int m) { return starts_at_previous_end(f, m) ? f.t1_min[m - 1] : f.t0_min[m]; }
+
 int check_frames(const kcs_frames* f) {
     if (!f) return fail(KCS_EINVAL, "frames is NULL");
     const int M = f->n_frames;
@@ -58,7 +69,8 @@ int check_frames(const kcs_frames* f) {
     for (int m = 0; m < M; ++m) {
         if (!is_finite(f->t0_min[m]) || !is_finite(f->t1_min[m]) || f->t0_min[m] < 0 || !(f->t1_min[m] > f->t0_min[m]))
             return fail(KCS_EINVAL, "frame %d: need 0 <= t0 < t1", m);
-        if (m > 0 && f->t0_min[m] < f->t1_min[m - 1]) return fail(KCS_EINVAL, "frames must be sorted and disjoint");
+        if (m > 0 && f->t0_min[m] < f->t1_min[m - 1] && !starts_at_previous_end(*f, m))
+            return fail(KCS_EINVAL, "frames must be sorted and disjoint");
         if (!(f->scale[m] > 0) || !is_finite(f->scale[m])) return fail(KCS_EINVAL, "frame %d: scale must be > 0", m);
         if (!(f->bg[m] >= 0) || !is_finite(f->bg[m])) return fail(KCS_EINVAL, "frame %d: bg must be >= 0", m);
     }
@@ -159,10 +171,10 @@ Schedule make_schedule(const kcs_frames& f, const kcs_kinetics* k) {
     S.fr.M = M;
     S.fr.contiguous = 1;
     for (int m = 1; m < M; ++m)
-        if (f.t0_min[m] != f.t1_min[m - 1]) S.fr.contiguous = 0;
+        if (frame_start(f, m) != f.t1_min[m - 1]) S.fr.contiguous = 0;
     std::vector<double> tb;
     for (int m = 0; m < M; ++m) {
-        tb.push_back(f.t0_min[m]);
+        tb.push_back(frame_start(f, m));
         tb.push_back(f.t1_min[m]);
     }
     std::sort(tb.begin(), tb.end());
@@ -171,9 +183,9 @@ Schedule make_schedule(const kcs_frames& f, const kcs_kinetics* k) {
     for (size_t b = 0; b < tb.size(); ++b) S.setup.t[b] = tb[b];
     S.setup.M = M;
     for (int m = 0; m < M; ++m) {
-        S.setup.i0[m] = (int32_t)(std::lower_bound(tb.begin(), tb.end(), f.t0_min[m]) - tb.begin());
+        S.setup.i0[m] = (int32_t)(std::lower_bound(tb.begin(), tb.end(), frame_start(f, m)) - tb.begin());
         S.setup.i1[m] = (int32_t)(std::lower_bound(tb.begin(), tb.end(), f.t1_min[m]) - tb.begin());
-        const double dt = f.t1_min[m] - f.t0_min[m];
+        const double dt = f.t1_min[m] - frame_start(f, m);
         S.fr.E[m] = (float)f.scale[m];
         S.fr.r[m] = (float)f.bg[m];
         S.fr.inv_dt[m] = (float)(1.0 / dt);
@@ -189,7 +201,7 @@ Schedule make_schedule(const kcs_frames& f, const kcs_kinetics* k) {
         S.fr.one_minus_vb = (float)(1.0 - k->vb);
         for (int m = 0; m < M; ++m) {
             double a1, a2, b1, b2;
-            input_integrals(*k, f.t0_min[m], a1, a2);
+            input_integrals(*k, frame_start(f, m), a1, a2);
             input_integrals(*k, f.t1_min[m], b1, b2);
             S.fr.blood[m] = (float)(k->vb * (b1 - a1));
             S.fr.dP2[m] = (float)(b2 - a2);

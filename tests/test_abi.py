@@ -140,3 +140,19 @@ def test_ki_map_validates_before_launching():
     assert L.kcs_ki_map(None, 10, None, None) == kcs.KCS_EINVAL
     assert L.kcs_ki_map(ctypes.c_void_p(256), 1 << 40, ctypes.c_void_p(256), None) == kcs.KCS_EINVAL
     assert L.kcs_ki_map(None, 0, None, None) == kcs.KCS_OK  # empty: nothing to do
+
+
+def test_frame_starts_within_rounding_of_the_previous_end_are_accepted():
+    """A schedule built as end - duration may start a frame an ulp before the previous end: it
+    counts as starting there.  A real overlap is still rejected (validation runs before the
+    pointer checks, so the messages tell the two apart)."""
+    t0, t1 = inputs.frame_times()
+    t0u = t0.copy()
+    t0u[1:] = np.nextafter(t1[:-1], -np.inf)  # an ulp before the previous end
+    g = geometry()
+    assert call_project(g, kcs.Frames(t0u, t1, np.ones(24), np.zeros(24)), x=0, y=0) == kcs.KCS_EINVAL
+    assert "frames" not in kcs.lib().kcs_last_error().decode()
+    t0o = t0.copy()
+    t0o[5] = t1[4] - 1e-6
+    assert call_project(g, kcs.Frames(t0o, t1, np.ones(24), np.zeros(24)), x=0, y=0) == kcs.KCS_EINVAL
+    assert "sorted and disjoint" in kcs.lib().kcs_last_error().decode()
