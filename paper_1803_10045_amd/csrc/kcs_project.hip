@@ -225,8 +225,27 @@ __global__ __launch_bounds__(256) void kproj_reduce_kernel(Src src) {
     float acc[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) acc[m] = 0.0f;
+    // Along a row of tiles the projection of a full-width tile moves by `slope` bins per column,
+    // so the columns whose bin range can hold b form an interval; it is found from the row's
+    // first tile and widened by one column on each side, and box_bins, the producer's own test,
+    // then decides for each column in it (a last, narrower tile projects inside the full-width
+    // one, so the interval still covers it).
+    const float slope = (float)T * p.h * A.c * p.inv_du;
+    const float bc = 0.5f * (float)(p.n_bin - 1);
     for (int ty = 0; ty < nty; ++ty) {
-        for (int tx = 0; tx < ntx; ++tx) {
+        int lo = 0, hi = ntx - 1;
+        if (fabsf(slope) > 1e-3f) {
+            const float xl = -0.5f * (float)p.nx * p.h, xr = xl + (float)T * p.h;
+            const float yl = ((float)(ty * T) - 0.5f * (float)p.ny) * p.h, yr = yl + (float)min(T, p.ny - ty * T) * p.h;
+            const float umin = fminf(xl * A.c, xr * A.c) + fminf(yl * A.s, yr * A.s);
+            const float umax = fmaxf(xl * A.c, xr * A.c) + fmaxf(yl * A.s, yr * A.s);
+            const float ta = ((float)b - fmaf(umax, p.inv_du, bc) - 0.01f) / slope;
+            const float tb = ((float)b - fmaf(umin, p.inv_du, bc) + 0.01f) / slope;
+            const float lim = (float)ntx + 2.0f;
+            lo = max(lo, (int)floorf(fminf(fmaxf(fminf(ta, tb), -lim), lim)) - 1);
+            hi = min(hi, (int)ceilf(fminf(fmaxf(fmaxf(ta, tb), -lim), lim)) + 1);
+        }
+        for (int tx = lo; tx <= hi; ++tx) {
             const int i0 = tx * T, j0 = ty * T;
             int b0, b1;
             box_bins(A, i0, j0, min(T, p.nx - i0), min(T, p.ny - j0), p.nx, p.ny, p.h, p.inv_du, p.n_bin, b0, b1);
