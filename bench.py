@@ -558,6 +558,13 @@ def main():
         kernels[kind] = {"launches": n, "avg_ms": round(avg, 4), "ms_per_sweep": round(ms / args.steps, 3),
                          "alg_bytes_per_launch": int(nbytes[kind]), "alg_GBps": round(gbps, 1),
                          "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4)}
+        # counter-measured HBM traffic and VALU issue of the same kernel (committed rocprofv3
+        # summaries, averaged over a sweep's launches; None once the kernel sources changed)
+        tb = counter_traffic(cfg.name, kind)
+        kernels[kind]["traffic_GBps"] = None if tb is None else round(tb / (avg * 1e-3) / 1e9, 1)
+        vc = counter_valu(cfg.name, kind)
+        kernels[kind]["valu_issue_frac"] = (None if vc is None else
+                                            round(vc[0] * vc[1] / (vc[2] * vc[3]) / (avg * 1e-3), 3))
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_sweep"])
     traffic = counter_traffic(cfg.name, dom)
     roof = {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["alg_GBps"], "peak": HBM_PEAK_GBPS,
