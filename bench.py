@@ -473,7 +473,7 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=250.0)
     ap.add_argument("--serve-runs", default="served@poisson,serial@poisson,served@saturated,serial@saturated",
                     help="comma-separated runs of the serve mode: served|serial @ poisson|saturated")
-    ap.add_argument("--config", default="cfg3", choices=["cfg1", "cfg2", "cfg3"])
+    ap.add_argument("--config", default="brain344", choices=["disk64", "brain128", "brain344"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--correction", action="store_true",
                     help="sweep mode: attenuation (head-sized water cylinder) x detector efficiencies in the model")

@@ -84,25 +84,25 @@ class StudyConfig:
         return self.nx * self.ny * self.nz
 
 
-def cfg1() -> StudyConfig:
+def disk64() -> StudyConfig:
     """64x64 single slice, 4 mm pixels, 60 angles x 64 bins, 2e6 counts + 10 % background."""
-    return StudyConfig("cfg1_64x64x1", 64, 64, 1, 4.0, 4.0, 60, 64, 4.0, 2e6, 0.10, Q=4, n_sweeps=10,
+    return StudyConfig("disk_64x64x1", 64, 64, 1, 4.0, 4.0, 60, 64, 4.0, 2e6, 0.10, Q=4, n_sweeps=10,
                        phantom="disk", n_lesions=3, seed=1)
 
 
-def cfg2() -> StudyConfig:
+def brain128() -> StudyConfig:
     """128x128x47 direct planes at 2.5 mm, 168 angles x 128 bins, 5e7 counts + 10 %."""
-    return StudyConfig("cfg2_128x128x47", 128, 128, 47, 2.5, 2.5, 168, 128, 2.5, 5e7, 0.10, Q=6, n_sweeps=20,
+    return StudyConfig("brain_128x128x47", 128, 128, 47, 2.5, 2.5, 168, 128, 2.5, 5e7, 0.10, Q=6, n_sweeps=20,
                        phantom="brain", n_lesions=6, seed=1)
 
 
-def cfg3() -> StudyConfig:
+def brain344() -> StudyConfig:
     """Clinical-scale 344x344x127 (2.09 x 2.09 x 2.03 mm), 252 angles x 344 bins, 3e8 counts + 15 %."""
-    return StudyConfig("cfg3_344x344x127", 344, 344, 127, 2.09, 2.03, 252, 344, 2.09, 3e8, 0.15, Q=21, n_sweeps=10,
+    return StudyConfig("brain_344x344x127", 344, 344, 127, 2.09, 2.03, 252, 344, 2.09, 3e8, 0.15, Q=21, n_sweeps=10,
                        phantom="brain", n_lesions=12, seed=1)
 
 
-CONFIGS = {"cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3}
+CONFIGS = {"disk64": disk64, "brain128": brain128, "brain344": brain344}
 
 
 def batch_configs(n_studies: int = 32, seed: int = 4) -> List[StudyConfig]:

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_entry_point():
 
 
 def geometry():
-    return kcs.Geometry.from_config(inputs.cfg1())
+    return kcs.Geometry.from_config(inputs.disk64())
 
 
 def frames(M=24):

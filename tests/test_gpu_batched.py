@@ -26,7 +26,7 @@ def batch_studies():
     (6 subsets; the 172 plane takes the tiled projector), and a ragged 37x29x3 grid with 7 subsets
     and an even LM count, starting at sweep 1."""
     bc = inputs.batch_configs()
-    cfgs = [inputs.cfg1(),
+    cfgs = [inputs.disk64(),
             inputs.scaled(bc[3], nz=3, counts=4e5 * 3),
             inputs.scaled(bc[1], nz=2, counts=4e5 * 2),
             inputs.StudyConfig("ragged_37x29x3", 37, 29, 3, 2.3, 2.3, 50, 45, 1.9, 3e5, 0.1, Q=7, n_sweeps=3,

@@ -18,10 +18,10 @@ DEV = "cuda"
 M = 24
 
 GEOMS = {
-    "cfg1": (64, 64, 1, 4.0, 60, 64, 4.0, 0.0, 4),
+    "disk64": (64, 64, 1, 4.0, 60, 64, 4.0, 0.0, 4),
     "ragged": (37, 29, 3, 2.3, 50, 45, 1.9, 0.05, 7),
     "wide_bins": (40, 44, 2, 2.0, 33, 23, 3.7, 0.0, 3),
-    "cfg3_1plane": (344, 344, 1, 2.09, 252, 344, 2.09, 0.0, 21),
+    "brain344_1plane": (344, 344, 1, 2.09, 252, 344, 2.09, 0.0, 21),
 }
 
 
@@ -91,7 +91,7 @@ def test_backproject_with_correction(name):
 
 def corrected_study(seed=31):
     """The 64x64 study with its sinogram regenerated through diag(mu) P (seeded Poisson counts)."""
-    st = oracle.make_study(inputs.cfg1())
+    st = oracle.make_study(inputs.disk64())
     g = st.geom
     mult = inputs.correction_sinogram(g.nz, g.n_ang, g.n_bin, g.du, radius(g.nx, g.h)).astype(np.float64)
     ybar = oracle.expected_counts(g, st.frames, st.truth_x, 0, 1, mult)

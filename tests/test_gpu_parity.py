@@ -22,11 +22,11 @@ T0, T1 = inputs.frame_times()
 M = len(T0)
 
 GEOMS = {
-    "cfg1": (64, 64, 1, 4.0, 60, 64, 4.0, 0.0, 4),
+    "disk64": (64, 64, 1, 4.0, 60, 64, 4.0, 0.0, 4),
     "ragged": (37, 29, 3, 2.3, 50, 45, 1.9, 0.05, 7),  # uneven subsets, bins narrower than pixels
     "wide_bins": (40, 44, 2, 2.0, 33, 23, 3.7, 0.0, 3),  # bins wider than pixels: > 2 bins per voxel
-    "cfg2_2planes": (128, 128, 2, 2.5, 168, 128, 2.5, 0.0, 6),
-    "cfg3_1plane": (344, 344, 1, 2.09, 252, 344, 2.09, 0.0, 21),
+    "brain128_2planes": (128, 128, 2, 2.5, 168, 128, 2.5, 0.0, 6),
+    "brain344_1plane": (344, 344, 1, 2.09, 252, 344, 2.09, 0.0, 21),
 }
 
 
@@ -145,12 +145,12 @@ def test_ki_map_parity(shape):
     assert np.all(np.isfinite(got)) and err.max() < 1e-6
 
 
-def cfg1_study():
-    return oracle.make_study(inputs.cfg1())
+def disk64_study():
+    return oracle.make_study(inputs.disk64())
 
 
 def test_init_state_parity():
-    st = cfg1_study()
+    st = disk64_study()
     g, f, *_ = kcs_objects(st)
     x = torch.empty((g.nz, g.ny, g.nx, M), device=DEV)
     params = torch.empty((3, g.nz, g.ny, g.nx), device=DEV)
@@ -166,7 +166,7 @@ def test_init_state_parity():
 
 @pytest.mark.parametrize("kp", [False, True])
 def test_osl_update_parity(kp):
-    st = cfg1_study()
+    st = disk64_study()
     g, f, k, p, _ = kcs_objects(st)
     rng = np.random.default_rng(5)
     x0 = (st.truth_x * (1 + 0.2 * rng.standard_normal(st.truth_x.shape)) + 0.05).clip(0.01)
@@ -189,7 +189,7 @@ def test_osl_update_parity(kp):
 
 
 def test_lm_fit_parity():
-    st = cfg1_study()
+    st = disk64_study()
     g, f, k, p, lm = kcs_objects(st)
     rng = np.random.default_rng(6)
     x = st.truth_x * (1 + 0.05 * rng.standard_normal(st.truth_x.shape))
@@ -260,11 +260,11 @@ def compare_icm(gx, gp, glam, ox, op, olam, frames, label, tol_img=1e-3, tol_map
     assert max(maps) < tol_maps
 
 
-def test_icm_full_schedule_cfg1():
+def test_icm_full_schedule_disk64():
     """The whole 64x64 schedule (10 sweeps x (4 subsets + 5 LM)) from the same initial state: the
     image over all voxels, the maps over the active voxels whose accept/reject path matched the
     oracle's in every sweep (at most 2 % of them on another path)."""
-    st = cfg1_study()
+    st = disk64_study()
     gx, gp, ox, op, diverged = run_schedule_tracking_decisions(st, st.cfg.n_sweeps)
     act = (ox * (st.frames.t1 - st.frames.t0)).sum(axis=-1)
     mask = act >= 0.1 * act.max()
@@ -304,7 +304,7 @@ def run_tiled_plane(cfg_full, n_sweeps, n_distinct=1):
     return x.cpu().numpy(), params.cpu().numpy(), lam.cpu().numpy(), planes, which
 
 
-@pytest.mark.parametrize("cfg_name,n_sweeps", [("cfg2", 3), ("cfg3", 1)])
+@pytest.mark.parametrize("cfg_name,n_sweeps", [("brain128", 3), ("brain344", 1)])
 def test_icm_full_size_sampled_planes(cfg_name, n_sweeps):
     """Full-size study in the benchmark's launch configuration; planes are independent, so each
     sampled plane is checked against the oracle run on that plane alone, and planes with the

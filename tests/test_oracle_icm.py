@@ -7,7 +7,7 @@ from paper_1803_10045_amd import inputs
 
 
 def test_noise_free_icm_moves_toward_truth():
-    cfg = inputs.cfg1()
+    cfg = inputs.disk64()
     st = oracle.make_study(cfg)
     clean = st.frames.E * oracle.forward(st.geom, st.truth_x) + st.frames.r
     state = oracle.initial_state(st.geom, st.frames, clean)
