@@ -156,3 +156,12 @@ def test_frame_starts_within_rounding_of_the_previous_end_are_accepted():
     t0o[5] = t1[4] - 1e-6
     assert call_project(g, kcs.Frames(t0o, t1, np.ones(24), np.zeros(24)), x=0, y=0) == kcs.KCS_EINVAL
     assert "sorted and disjoint" in kcs.lib().kcs_last_error().decode()
+
+
+def test_limits_rejected_before_launching():
+    """Beyond the supported shapes: more than 1024 angles in a subset, bins more than 6 times
+    narrower than pixels."""
+    g = kcs.Geometry(16, 16, 1, 3.0, 2050, 32, 3.0)
+    assert call_project(g, frames(), q=0, Q=2, x=0, y=0) == kcs.KCS_ESHAPE  # 1025 angles in subset 0
+    g = kcs.Geometry(12, 12, 1, 3.0, 30, 120, 0.45)
+    assert call_project(g, frames(), q=0, Q=3, x=0, y=0) == kcs.KCS_ESHAPE  # 6.7 times narrower

@@ -197,3 +197,51 @@ def test_sinogram_without_counts():
     # with no activity K1 goes to its bound and k2, k3 are not determined by the data: only K1 is
     # held to the schedule tolerance, the others to finite values near the oracle's
     assert em[0] < 1e-3 and max(em) < 1e-2
+
+
+@pytest.mark.parametrize("case", ["max_angles", "narrowest_bins"])
+def test_largest_supported_shapes(case):
+    """The limits of the library: 1024 angles in one subset on a plane large enough for the tiled
+    projector (150 x 150 x 24 frames > 2 MB), and bins 6 times narrower than the pixels (the
+    narrowest accepted).  Projection of every subset and one OSL pass against the oracle."""
+    if case == "max_angles":
+        nx, ny, h, n_ang, n_bin, du, Q = 150, 150, 2.0, 1024, 72, 6.4, 1  # bins cover the grid's diagonal
+    else:
+        nx, ny, h, n_ang, n_bin, du, Q = 12, 12, 3.0, 30, 104, 0.5, 3
+    ofr, kfr = schedule(24, seed=9)
+    og, kg = geometry_pair(nx, ny, 1, h, n_ang, n_bin, du, 0.0)
+    x = make_image(1, ny, nx, 24, seed=10)
+    for q in range(Q):
+        ref = oracle.expected_counts(og, ofr, x, q, Q)
+        out = torch.empty((1, kg.subset_size(q, Q), n_bin, 24), device=DEV)
+        kcs.kcs_project(kg, kfr, dev(x), q, Q, out)
+        torch.cuda.synchronize()
+        e = rel_l2(out.cpu().numpy(), ref)
+        print(f"{case} q={q}: project relL2 {e:.2e}")
+        assert e < 1e-5
+    rng = np.random.default_rng(11)
+    sino = rng.poisson(ofr.E * oracle.forward(og, x) + ofr.r).astype(np.float32).astype(np.float64)
+    maps = maps_in_box((1, ny, nx), seed=12)
+    # prior off: with an image unrelated to the maps the prior term amplifies the FP32 model's
+    # relative error in the earliest frames (tested with consistent images elsewhere); here the
+    # geometry at its limits is under test
+    prior_o = oracle.Prior(beta_kp=0.1, eps_F=0.01, beta_h=0.1, delta=(1e-3,) * 3, kp_on=False)
+    prior_k = kcs.Prior(0.1, 0.01, 0.1, (1e-3,) * 3, False)
+    xd = dev(x)
+    work = kcs.alloc_workspace(kg, 24, Q, DEV)
+    ox = x.copy()
+    for q in range(Q):
+        kcs.kcs_osl_update(kg, kfr, KK, prior_k, dev(sino), dev(maps), q, Q, xd, work)
+        ox = oracle.osl_update(og, ofr, KIN, prior_o, sino, maps, ox, q, Q, False)
+    torch.cuda.synchronize()
+    gx = xd.cpu().numpy()
+    err = rel_l2(gx, ox)
+    rel = np.abs(gx - ox) / np.maximum(np.abs(ox), 1e-30)
+    worst = np.unravel_index(np.argmax(rel), rel.shape)
+    print(f"{case}: OSL pass relL2 {err:.2e}; largest voxel error {rel.max():.2e} at {worst}")
+    # 1024 angles put oblique angles within 0.18 degrees of the axes, where the pixel chord rises
+    # to its plateau within h sin(0.18 deg) = 6 um of the ray offset; the FP32 chord of the gather
+    # then errs by ~1e-7 mm on that ramp, which bounds this case at a few 1e-5 (measured 2.9e-5;
+    # at the 252 angles of the headline study the nearest oblique angle is 0.71 degrees and the
+    # same pass is within 5e-6)
+    assert err < (5e-5 if case == "max_angles" else 1e-5)
