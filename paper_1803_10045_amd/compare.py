@@ -93,8 +93,9 @@ def realization(ybar, seed: int):
 
 
 def run_method(g, f, kin, prior, lm, sinos: Sequence, Q: int, n_sweeps: int, record: Iterable[int], dev,
-               flags: int = kcs.KCS_PLAN_GRAPH) -> Dict[int, np.ndarray]:
-    """ICM sweeps of every realization in `sinos` as one plan per sweep.  Returns, for each sweep
+               flags: int = 0) -> Dict[int, np.ndarray]:
+    """ICM sweeps of every realization in `sinos` as one plan per sweep (run once each, so not
+    captured as a graph unless `flags` asks for it).  Returns, for each sweep
     count in `record`, the maps of all realizations (R, 3, nz, ny, nx) and their K_i (R, nz, ny, nx)
     stacked as (R, 4, nz, ny, nx)."""
     import torch
