@@ -112,7 +112,8 @@ typedef struct kcs_lm_opts {
 /* Bytes of device workspace the calls below need for this geometry, frame count and subset count. */
 size_t kcs_workspace_bytes(const kcs_geometry* g, int32_t n_frames, int32_t Q);
 
-/* Device bytes one study occupies: sinogram, image, three maps, lambda, workspace. */
+/* Device bytes one study occupies: sinogram, image, three maps, lambda, workspace (not the
+ * optional correction sinogram g->d_mult, nz * n_ang * n_bin floats more when given). */
 size_t kcs_study_footprint_bytes(const kcs_geometry* g, int32_t n_frames, int32_t Q);
 
 /* Expected counts of subset q (denominator of Eq. 2 plus background):
