@@ -23,11 +23,11 @@ _SO = os.path.join(_HERE, "liboracle.so")
 
 
 def build_oracle_library(force: bool = False) -> str:
-    """Compile ``siddon.c`` with gcc into ``liboracle.so`` (seconds)."""
+    """Compile ``siddon.c`` and ``kinetics.c`` with gcc into ``liboracle.so`` (seconds)."""
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11",
-                               "-o", tmp, os.path.join(_HERE, "siddon.c"), "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11", "-o", tmp,
+                               os.path.join(_HERE, "siddon.c"), os.path.join(_HERE, "kinetics.c"), "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -52,6 +52,9 @@ def _lib():
     lib.orc_siddon_line.argtypes = [ctypes.POINTER(_Geom2D), ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, f64p]
     lib.orc_siddon_line.restype = ctypes.c_int32
+    lib.orc_tissue_integrals.argtypes = [ctypes.c_int64, f64p, ctypes.c_int32, f64p, f64p, f64p, ctypes.c_int32,
+                                         f64p, f64p, ctypes.c_void_p]
+    lib.orc_tissue_integrals.restype = None
     return lib
 
 
@@ -133,8 +136,17 @@ def subset_rows(geom: Geometry, q: int, Q: int) -> np.ndarray:
     return (ang[:, None] * geom.n_bin + np.arange(geom.n_bin)[None, :]).ravel()
 
 
+_SUBSET_CACHE: dict = {}
+
+
 def _subset_matrix(geom: Geometry, q: int, Q: int) -> sp.csr_matrix:
-    return system_matrix(geom)[subset_rows(geom, q, Q)]
+    """Rows of the system matrix that belong to subset q (kept for the geometry's later calls)."""
+    key = (geom.nx, geom.ny, geom.h, geom.n_ang, geom.n_bin, geom.du, geom.ang0, q, Q)
+    if key not in _SUBSET_CACHE:
+        if len(_SUBSET_CACHE) > 256:
+            _SUBSET_CACHE.clear()
+        _SUBSET_CACHE[key] = system_matrix(geom)[subset_rows(geom, q, Q)]
+    return _SUBSET_CACHE[key]
 
 
 def forward(geom: Geometry, x: np.ndarray, q: int = 0, Q: int = 1) -> np.ndarray:

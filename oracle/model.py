@@ -89,57 +89,31 @@ def input_integrals(T, kin: Kinetics):
     return P1, P2
 
 
-def _conv_integrals(a, T, kin: Kinetics):
-    """For the kernel e^{-a t} (a > 0, broadcast against T):
-    G(T) = int_0^T Cp(s) e^{-a (T - s)} ds and A4(T) = int_0^T Cp(s) (T - s) e^{-a (T - s)} ds."""
-    G = 0.0
-    A4 = 0.0
-    for c, lam, n in kin.components():
-        b = lam + a
-        neg = b <= 0.0
-        # b <= 0: substitute nothing, exponent b s <= 0
-        mb = moments(np.where(neg, b * T, 0.0), n + 1)
-        g_neg = np.exp(-a * T) * T ** (n + 1) * mb[n]
-        a4_neg = np.exp(-a * T) * T ** (n + 2) * (mb[n] - mb[n + 1])
-        # b > 0: substitute u = T - s, exponent -b u <= 0
-        mp = moments(np.where(neg, 0.0, -b * T), 2)
-        if n == 0:
-            g_pos = np.exp(lam * T) * T * mp[0]
-            a4_pos = np.exp(lam * T) * T ** 2 * mp[1]
-        else:
-            g_pos = np.exp(lam * T) * T ** 2 * (mp[0] - mp[1])
-            a4_pos = np.exp(lam * T) * T ** 3 * (mp[1] - mp[2])
-        G = G + c * np.where(neg, g_neg, g_pos)
-        A4 = A4 + c * np.where(neg, a4_neg, a4_pos)
-    return G, A4
-
-
 def cumulative_tissue(params: np.ndarray, T: np.ndarray, kin: Kinetics, jacobian: bool = False):
     """int_0^T C_T for each voxel (rows of params = (K1, k2, k3)) and each time T.
 
-    Returns C (n, nT) and, if requested, dC/d(K1, k2, k3) as (n, nT, 3)."""
-    params = np.atleast_2d(np.asarray(params, dtype=np.float64))
-    T = np.asarray(T, dtype=np.float64)[None, :]
-    K1, k2, k3 = (params[:, p:p + 1] for p in range(3))
-    a = k2 + k3
-    if np.any(a <= 0.0):
+    Returns C (n, nT) and, if requested, dC/d(K1, k2, k3) as (n, nT, 3).  The convolutions of
+    the input with e^{-a t} and t e^{-a t} (a = k2 + k3) and the combination above are evaluated
+    per voxel and time in ``kinetics.c`` (same closed form, FP64, OpenMP over voxels); P1 and P2
+    come from :func:`input_integrals`."""
+    from .geometry import _lib
+
+    params = np.ascontiguousarray(np.atleast_2d(np.asarray(params, dtype=np.float64)))
+    T = np.ascontiguousarray(np.asarray(T, dtype=np.float64).ravel())
+    if np.any(params[:, 1] + params[:, 2] <= 0.0):
         raise ValueError("k2 + k3 must be positive")
-    alpha = k3 / a
     P1, P2 = input_integrals(T, kin)
-    G, A4 = _conv_integrals(a, T, kin)
-    I = (P1 - G) / a
-    dK1 = alpha * P2 + (1.0 - alpha) * I
-    C = K1 * dK1
-    if not jacobian:
-        return C, None
-    a2 = a * a
-    dk2 = K1 * (-(k3 / a2) * (P2 - I) + (k2 / a2) * (A4 - I))
-    dk3 = K1 * ((k2 / a2) * (P2 - I) + (k2 / a2) * (A4 - I))
-    return C, np.stack([dK1, dk2, dk3], axis=-1)
+    comp = np.array(kin.components(), dtype=np.float64).ravel()
+    n, nT = params.shape[0], T.shape[0]
+    C = np.empty((n, nT))
+    D = np.empty((n, nT, 3)) if jacobian else None
+    _lib().orc_tissue_integrals(n, params, nT, T, np.ascontiguousarray(P1), np.ascontiguousarray(P2),
+                                len(kin.components()), comp, C, None if D is None else D.ctypes.data)
+    return C, D
 
 
 def model_tac(params: np.ndarray, t0: np.ndarray, t1: np.ndarray, kin: Kinetics, jacobian: bool = False,
-              chunk: int = 1 << 15):
+              chunk: int = 1 << 18):
     """Frame-averaged model TAC F_m(xi) (n, M) and optionally its Jacobian (n, M, 3)."""
     params = np.atleast_2d(np.asarray(params, dtype=np.float64))
     t0 = np.asarray(t0, dtype=np.float64)
@@ -157,9 +131,9 @@ def model_tac(params: np.ndarray, t0: np.ndarray, t1: np.ndarray, kin: Kinetics,
     for s in range(0, n, chunk):
         p = params[s:s + chunk]
         C, D = cumulative_tissue(p, tb, kin, jacobian)
-        F[s:s + chunk] = ((1.0 - kin.vb) * (C[:, i1] - C[:, i0]) + blood[None, :]) / dt[None, :]
+        F[s:s + chunk] = ((1.0 - kin.vb) * (np.take(C, i1, axis=1) - np.take(C, i0, axis=1)) + blood[None, :]) / dt[None, :]
         if jacobian:
-            J[s:s + chunk] = (1.0 - kin.vb) * (D[:, i1] - D[:, i0]) / dt[None, :, None]
+            J[s:s + chunk] = (1.0 - kin.vb) * (np.take(D, i1, axis=1) - np.take(D, i0, axis=1)) / dt[None, :, None]
     return (F, J) if jacobian else F
 
 

@@ -52,6 +52,10 @@ class LMOptions:
     lo: Tuple[float, float, float] = (0.0, 1e-4, 0.0)
     hi: Tuple[float, float, float] = (2.0, 2.0, 1.0)
     eta: float = 0.0
+    # True: every ICM sweep's fit starts its damping afresh from tau * max diag(J^T J) (the fit is
+    # a new problem whenever the image has changed); False: the damping left by the previous
+    # sweep's fit carries over (lambda <= 0 still means "initialise")
+    restart: bool = True
 
 
 @dataclass
@@ -87,9 +91,11 @@ def expected_counts(g: geo.Geometry, fr: Frames, x: np.ndarray, q: int, Q: int, 
 
 
 def osl_update(g: geo.Geometry, fr: Frames, kin: Kinetics, prior: Prior, sino: np.ndarray, params: np.ndarray,
-               x: np.ndarray, q: int, Q: int, kp: bool, mult=None) -> np.ndarray:
+               x: np.ndarray, q: int, Q: int, kp: bool, mult=None, F=None) -> np.ndarray:
     """One OS-MAP-OSL-KP update of the image x (nz, ny, nx, M) with subset q (Eq. 2-3), with the
-    system matrix diag(mult) P when a correction sinogram mult (nz, n_ang, n_bin) is given."""
+    system matrix diag(mult) P when a correction sinogram mult (nz, n_ang, n_bin) is given.
+    F: the model TAC of `params` (shape of x), if the caller has it already (the maps do not
+    change during an OSL pass, so a pass evaluates it once)."""
     ybar = expected_counts(g, fr, x, q, Q, mult)
     s_q = sino[:, geo.subset_angles(g.n_ang, q, Q)]
     ratio = np.where(ybar > 0.0, s_q / np.where(ybar > 0.0, ybar, 1.0), 0.0)
@@ -102,7 +108,8 @@ def osl_update(g: geo.Geometry, fr: Frames, kin: Kinetics, prior: Prior, sino: n
         n = fr.E * geo.back(g, np.ascontiguousarray(mu), q, Q)  # sum_d mu_d p_vd per plane, (nz, ny, nx, 1)
     n = np.broadcast_to(n, x.shape)
     if kp:
-        F = model_tac(params.reshape(3, -1).T, fr.t0, fr.t1, kin).reshape(x.shape)
+        if F is None:
+            F = model_tac(params.reshape(3, -1).T, fr.t0, fr.t1, kin).reshape(x.shape)
         D = n * (1.0 + prior.beta_kp * (x - F) / np.maximum(F, prior.eps_F))
     else:
         D = n
@@ -215,12 +222,14 @@ def lm_fit(fr, kin, prior, opt, x, params, lam):
 
 def icm_sweep(g, fr, kin, prior, opt, sino, x, params, lam, Q: int, sweep_idx: int, mult=None):
     """One ICM sweep (Sec. II-D): OS-MAP-OSL-KP over all Q subsets given the maps, then MAP-LM
-    given the new image.  Each sweep's MAP-LM is a new fit to a new image, so its damping starts
-    from tau * max diag(J^T J) (the lambda passed in is ignored; the final one is returned)."""
+    given the new image.  With opt.restart (the default) each sweep's MAP-LM is a new fit to a
+    new image and its damping starts from tau * max diag(J^T J) (the lambda passed in is
+    ignored); otherwise it continues from the lambda passed in.  The final lambda is returned."""
     kp = prior.kp_on and sweep_idx > 0
+    F = model_tac(params.reshape(3, -1).T, fr.t0, fr.t1, kin).reshape(x.shape) if kp else None
     for q in range(Q):
-        x = osl_update(g, fr, kin, prior, sino, params, x, q, Q, kp, mult)
-    params, lam = lm_fit(fr, kin, prior, opt, x, params, np.zeros_like(lam))
+        x = osl_update(g, fr, kin, prior, sino, params, x, q, Q, kp, mult, F)
+    params, lam = lm_fit(fr, kin, prior, opt, x, params, np.zeros_like(lam) if opt.restart else lam)
     return x, params, lam
 
 
