@@ -50,13 +50,14 @@ enum {
     KCS_OK = 0,
     KCS_EINVAL = -1,     /* null pointer, non-positive size, unsorted frames, bad value */
     KCS_ESHAPE = -2,     /* shape the library does not support (M not in {8,16,24,32}, more than 1024
-                            angles in a subset, bins more than 6 times narrower than pixels) */
+                            angles in a subset, bins more than 6 times narrower than pixels, a plane of
+                            nx*ny*M >= 2^31 values) */
     KCS_EWORKSPACE = -3, /* workspace smaller than kcs_workspace_bytes() */
     KCS_EHIP = -4        /* HIP runtime error (message has hipGetErrorString) */
 };
 
 typedef struct kcs_geometry {
-    int32_t nx, ny, nz; /* image grid, >= 1 each, nx*ny*nz < 2^31 */
+    int32_t nx, ny, nz; /* image grid, >= 1 each, nx*ny*nz < 2^31 and nx*ny*M < 2^31 (M frames) */
     double pixel_mm;    /* in-plane square pixel side h > 0 */
     int32_t n_ang;      /* projection angles over 180 degrees, >= 1 */
     int32_t n_bin;      /* radial bins per angle, >= 1 */
@@ -103,17 +104,22 @@ typedef struct kcs_prior {
  * tau * max diag(J^T J); parameters clipped to [lo, hi] (lo[1] + lo[2] > 0); a step is accepted
  * iff the voxel objective decreases by more than eta times its value,
  * Phi(xi') - Phi(xi) < -eta Phi(xi) (0 <= eta < 1; eta = 0 is the plain strict decrease), then
- * lambda = max(lambda/10, lam_min), otherwise lambda = min(10 lambda, lam_max). */
+ * lambda = max(lambda/10, lam_min), otherwise lambda = min(10 lambda, lam_max).
+ * restart (ICM sweeps and plans only): non-zero starts every sweep's fit from
+ * tau * max diag(J^T J) whatever d_lambda holds (each sweep fits a new image); zero continues
+ * from d_lambda, the damping the previous sweep's fit left (lambda <= 0 still initialises).
+ * kcs_lm_fit always starts from d_lambda. */
 typedef struct kcs_lm_opts {
     int32_t n_iter;
     double tau, lam_min, lam_max, lo[3], hi[3], eta;
+    int32_t restart;
 } kcs_lm_opts;
 
 /* Bytes of device workspace the calls below need for this geometry, frame count and subset count. */
 size_t kcs_workspace_bytes(const kcs_geometry* g, int32_t n_frames, int32_t Q);
 
-/* Device bytes one study occupies: sinogram, image, three maps, lambda, workspace (not the
- * optional correction sinogram g->d_mult, nz * n_ang * n_bin floats more when given). */
+/* Device bytes one study occupies: sinogram, image, three maps, lambda, workspace and, when
+ * g->d_mult is given, the correction sinogram (nz * n_ang * n_bin floats). */
 size_t kcs_study_footprint_bytes(const kcs_geometry* g, int32_t n_frames, int32_t Q);
 
 /* Expected counts of subset q (denominator of Eq. 2 plus background):
@@ -170,8 +176,9 @@ int kcs_init_state(const kcs_geometry* g, const kcs_frames* f, const float* d_si
                    hipStream_t stream);
 
 /* One ICM sweep (Sec. II-D): kcs_osl_update for q = 0..Q-1 (prior on iff p->kp_on and
- * sweep_idx > 0), then kcs_lm_fit as a fresh fit: lambda is initialised from tau * max diag(J^T J)
- * whatever d_lambda holds on entry; d_lambda returns the damping after the last iteration. */
+ * sweep_idx > 0), then the lm->n_iter iterations of kcs_lm_fit.  With lm->restart the fit starts
+ * from tau * max diag(J^T J) whatever d_lambda holds on entry; without it from d_lambda (lambda <= 0
+ * initialises).  d_lambda returns the damping after the last iteration. */
 int kcs_icm_sweep(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics* k, const kcs_prior* p,
                   const kcs_lm_opts* lm, const float* d_sino, int32_t Q, int32_t sweep_idx, float* d_x,
                   float* d_params, float* d_lambda, void* d_work, size_t work_bytes, hipStream_t stream);

@@ -42,7 +42,7 @@ def peak_input(kin: Kinetics) -> float:
 def make_study(cfg, with_truth: bool = True) -> Study:
     g = geo.Geometry.from_config(cfg)
     kin = Kinetics(**inputs.FENG, vb=inputs.VB)
-    t0, t1 = inputs.frame_times()
+    t0, t1 = inputs.frame_times(cfg.frame_blocks)
     dt = t1 - t0
     M = len(t0)
     maps, mask = inputs.phantom_maps(cfg)
@@ -51,6 +51,8 @@ def make_study(cfg, with_truth: bool = True) -> Study:
     if len(idx):
         F = model_tac(maps.reshape(3, -1).T[idx], t0, t1, kin)
         x_true.reshape(-1, M)[idx] = F
+    if cfg.phantom == "rings":  # the blood square holds plasma: frame average of Cp (its K1 = 0)
+        x_true[inputs.ring_labels(cfg) == 1] /= kin.vb
     proj = geo.forward(g, x_true)  # unit-calibration line integrals, (nz, n_ang, n_bin, M)
     total = float(np.sum(proj.reshape(-1, M).sum(axis=0) * dt))
     c = cfg.counts / total if total > 0 else 1.0

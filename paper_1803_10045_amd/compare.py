@@ -51,7 +51,7 @@ def synthesize_truth(cfg: inputs.StudyConfig, dev):
     import torch
 
     g = kcs.Geometry.from_config(cfg)
-    t0, t1 = inputs.frame_times(inputs.FRAME_BLOCKS_EQ8)
+    t0, t1 = inputs.frame_times(cfg.frame_blocks)
     dt = t1 - t0
     M = len(t0)
     kin = kcs.Kinetics(**inputs.FENG, vb=inputs.VB)
@@ -74,13 +74,25 @@ def synthesize_truth(cfg: inputs.StudyConfig, dev):
     r = cfg.bg_frac * cfg.counts * (dt / dt.sum()) / (cfg.n_ang * cfg.n_bin * cfg.nz)
     y.mul_(torch.from_numpy(E.astype(np.float32)).to(dev)).add_(torch.from_numpy(r.astype(np.float32)).to(dev))
     f = kcs.Frames(t0, t1, E, r)
-    tissue = labels >= 2
-    delta = inputs.huber_delta(maps, tissue)
-    peak = float(np.max(x.view(-1, M).max(dim=0).values.cpu().numpy()))
-    prior = kcs.Prior(inputs.BETA_KP, 1e-4 * peak, cfg.beta_h, (delta,) * 3, True)
+    delta = inputs.huber_delta(maps, labels > 0)
+    prior = kcs.Prior(inputs.BETA_KP, 1e-4 * peak_input(), cfg.beta_h, (delta,) * 3, True)
     lm = kcs.LMOptions(cfg.n_lm, inputs.LM_TAU, inputs.LM_LAM_MIN, inputs.LM_LAM_MAX, inputs.LM_LO, inputs.LM_HI,
                        inputs.LM_ETA)
     return g, f, kin, prior, lm, y, maps, labels
+
+
+def peak_input() -> float:
+    """max_t Cp(t) of the Feng input (the floor eps_F of the OSL-KP denominator is 1e-4 of it),
+    by bounded minimisation of -Cp over the first two minutes, where its peak lies."""
+    from scipy.optimize import minimize_scalar
+
+    k = inputs.FENG
+
+    def neg_cp(t):
+        return -((k["A1"] * t - k["A2"] - k["A3"]) * np.exp(k["l1"] * t) + k["A2"] * np.exp(k["l2"] * t)
+                 + k["A3"] * np.exp(k["l3"] * t))
+
+    return -minimize_scalar(neg_cp, bounds=(0.0, 2.0), method="bounded", options=dict(xatol=1e-10)).fun
 
 
 def realization(ybar, seed: int):

@@ -110,6 +110,12 @@ int check_lm(const kcs_lm_opts* o) {
     return KCS_OK;
 }
 
+// Offsets within one plane's image (j * nx * M + i * M) are 32-bit in the kernels.
+int check_plane(const kcs_geometry* g, int32_t M) {
+    if ((double)g->nx * g->ny * M >= 2147483647.0) return fail(KCS_ESHAPE, "a plane of nx*ny*M >= 2^31 values");
+    return KCS_OK;
+}
+
 int check_subset(const kcs_geometry* g, int32_t q, int32_t Q) {
     if (Q < 1 || Q > g->n_ang) return fail(KCS_EINVAL, "need 1 <= Q <= n_ang");
     if (q < 0 || q >= Q) return fail(KCS_EINVAL, "need 0 <= q < Q");
@@ -521,6 +527,7 @@ struct TableBuilder {
 int check_study(const kcs_study& st) {
     KCS_TRY(check_geometry(&st.g));
     KCS_TRY(check_frames(&st.f));
+    KCS_TRY(check_plane(&st.g, st.f.n_frames));
     KCS_TRY(check_kinetics(&st.k));
     KCS_TRY(check_prior(&st.p));
     KCS_TRY(check_lm(&st.lm));
@@ -679,7 +686,7 @@ void build_schedule(TableBuilder& tb, std::vector<StudyPrep>& preps) {
                     const float* src = (odd == even_it) ? other : s.d_params;
                     float* dst = (odd == even_it) ? s.d_params : other;
                     LmArgs a = lm_args(*P);
-                    a.reset_lambda = it == 0 ? 1 : 0;
+                    a.reset_lambda = (it == 0 && s.lm.restart) ? 1 : 0;
                     a.have_state = it > 0 ? 1 : 0;
                     a.need_state = it + 1 < s.lm.n_iter ? 1 : 0;
                     jobs.push_back(LmJob{a, at<KinTab>(s.d_work, P->L.kin), s.d_x, src, dst, s.d_lambda,
@@ -875,13 +882,15 @@ size_t kcs_study_footprint_bytes(const kcs_geometry* g, int32_t n_frames, int32_
     if (!g || check_geometry(g) != KCS_OK) return 0;
     const size_t N = (size_t)g->nx * g->ny * g->nz;
     const size_t S = (size_t)g->nz * g->n_ang * g->n_bin * n_frames;
-    return (S + N * n_frames + 3 * N + N) * sizeof(float) + kcs_workspace_bytes(g, n_frames, Q);
+    const size_t mult = g->d_mult ? (size_t)g->nz * g->n_ang * g->n_bin : 0;
+    return (S + N * n_frames + 3 * N + N + mult) * sizeof(float) + kcs_workspace_bytes(g, n_frames, Q);
 }
 
 int kcs_project(const kcs_geometry* g, const kcs_frames* f, const float* d_x, int32_t q, int32_t Q, float* d_ybar,
                 hipStream_t stream) {
     KCS_TRY(check_geometry(g));
     KCS_TRY(check_frames(f));
+    KCS_TRY(check_plane(g, f->n_frames));
     KCS_TRY(check_subset(g, q, Q));
     if (!d_x || !d_ybar) return fail(KCS_EINVAL, "device pointers must not be NULL");
     const Schedule S = make_schedule(*f, nullptr);
@@ -896,6 +905,7 @@ int kcs_backproject(const kcs_geometry* g, const kcs_frames* f, const float* d_y
                     float* d_sens, hipStream_t stream) {
     KCS_TRY(check_geometry(g));
     KCS_TRY(check_frames(f));
+    KCS_TRY(check_plane(g, f->n_frames));
     KCS_TRY(check_subset(g, q, Q));
     if (!d_y || !d_b) return fail(KCS_EINVAL, "device pointers must not be NULL");
     const Schedule S = make_schedule(*f, nullptr);
@@ -937,6 +947,7 @@ int kcs_osl_update(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetic
                    size_t work_bytes, hipStream_t stream) {
     KCS_TRY(check_geometry(g));
     KCS_TRY(check_frames(f));
+    KCS_TRY(check_plane(g, f->n_frames));
     KCS_TRY(check_kinetics(k));
     KCS_TRY(check_prior(p));
     KCS_TRY(check_subset(g, q, Q));
@@ -956,6 +967,7 @@ int kcs_lm_fit(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics* k
                size_t work_bytes, hipStream_t stream) {
     KCS_TRY(check_geometry(g));
     KCS_TRY(check_frames(f));
+    KCS_TRY(check_plane(g, f->n_frames));
     KCS_TRY(check_kinetics(k));
     KCS_TRY(check_prior(p));
     KCS_TRY(check_lm(lm));
@@ -971,6 +983,7 @@ int kcs_init_state(const kcs_geometry* g, const kcs_frames* f, const float* d_si
                    float* d_params, float* d_lambda, void* d_work, size_t work_bytes, hipStream_t stream) {
     KCS_TRY(check_geometry(g));
     KCS_TRY(check_frames(f));
+    KCS_TRY(check_plane(g, f->n_frames));
     if (!d_sino || !d_x || !d_params || !d_lambda || !xi0) return fail(KCS_EINVAL, "pointers must not be NULL");
     for (int i = 0; i < 3; ++i)
         if (!is_finite(xi0[i])) return fail(KCS_EINVAL, "xi0 must be finite");
@@ -996,6 +1009,7 @@ int kcs_icm_sweep(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics
                   float* d_lambda, void* d_work, size_t work_bytes, hipStream_t stream) {
     KCS_TRY(check_geometry(g));
     KCS_TRY(check_frames(f));
+    KCS_TRY(check_plane(g, f->n_frames));
     KCS_TRY(check_kinetics(k));
     KCS_TRY(check_prior(p));
     KCS_TRY(check_lm(lm));
@@ -1009,7 +1023,7 @@ int kcs_icm_sweep(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics
     const bool kp = p->kp_on != 0 && sweep_idx > 0;
     if (kp) KCS_TRY(do_model_pass(*g, S, d_params, d_work, Q, stream));
     for (int32_t q = 0; q < Q; ++q) KCS_TRY(do_osl(*g, S, *p, kp, d_sino, q, Q, d_x, d_work, stream));
-    return do_lm(*g, S, *p, *lm, d_x, d_params, d_lambda, d_work, Q, true, stream);
+    return do_lm(*g, S, *p, *lm, d_x, d_params, d_lambda, d_work, Q, lm->restart != 0, stream);
 }
 
 int kcs_plan_create(const kcs_study* studies, int32_t n, int32_t flags, hipStream_t stream, kcs_plan** out) {

@@ -39,8 +39,9 @@ LM_TAU = 1e-3
 LM_LAM_MIN, LM_LAM_MAX = 1e-8, 1e8
 LM_LO = (0.0, 1e-4, 0.0)
 LM_HI = (2.0, 2.0, 1.0)
-# A step is kept only if it lowers the voxel objective by more than this fraction of its value
-# (a sufficient-decrease test; improvements below it are at the resolution of FP32 arithmetic).
+# A step is kept only if it lowers the voxel objective by more than this fraction of its value:
+# the fit of a voxel counts as converged to this relative tolerance of its objective, and a
+# step that gains less is treated as no progress (rejected, damping raised).
 LM_ETA = 1e-3
 BETA_KP = 0.1
 
@@ -74,10 +75,11 @@ class StudyConfig:
     n_lesions: int = 6
     seed: int = 1
     ang0: float = 0.0
+    frame_blocks: Tuple[Tuple[int, float], ...] = FRAME_BLOCKS  # (count, seconds) per block
 
     @property
     def n_frames(self) -> int:
-        return sum(n for n, _ in FRAME_BLOCKS)
+        return sum(n for n, _ in self.frame_blocks)
 
     @property
     def n_vox(self) -> int:
@@ -187,10 +189,11 @@ def ring_labels(cfg: StudyConfig) -> np.ndarray:
 
 def rings_config(n: int = 128, nz: int = 4, counts_per_plane: float = 4e6, seed: int = 41) -> StudyConfig:
     """The comparison study: the ring phantom on an n x n grid (256 mm field), 1.3 n angles,
-    n bins, 6 subsets, 10 sweeps (frames: frame_times(FRAME_BLOCKS_EQ8), the simulation's schedule)."""
+    n bins, 6 subsets, 10 sweeps, the simulation's frame blocks (FRAME_BLOCKS_EQ8).  Its blood
+    square carries the plasma input itself: its activity is the frame average of Cp."""
     h = 256.0 / n
     return StudyConfig(f"rings_{n}x{n}x{nz}", n, n, nz, h, h, int(round(1.3 * n)), n, h, counts_per_plane * nz,
-                       0.1, Q=6, n_sweeps=10, phantom="rings", n_lesions=0, seed=seed)
+                       0.1, Q=6, n_sweeps=10, phantom="rings", n_lesions=0, seed=seed, frame_blocks=FRAME_BLOCKS_EQ8)
 
 
 def phantom_maps(cfg: StudyConfig) -> Tuple[np.ndarray, np.ndarray]:

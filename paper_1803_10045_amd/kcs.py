@@ -60,7 +60,7 @@ class c_prior(ctypes.Structure):
 class c_lm_opts(ctypes.Structure):
     _fields_ = [("n_iter", ctypes.c_int32), ("tau", ctypes.c_double), ("lam_min", ctypes.c_double),
                 ("lam_max", ctypes.c_double), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
-                ("eta", ctypes.c_double)]
+                ("eta", ctypes.c_double), ("restart", ctypes.c_int32)]
 
 
 class c_study(ctypes.Structure):
@@ -205,10 +205,11 @@ class LMOptions:
     lo: Sequence[float]
     hi: Sequence[float]
     eta: float = 0.0
+    restart: bool = True  # ICM sweeps: every sweep's fit starts lambda afresh (False: carries it over)
 
     def c(self) -> c_lm_opts:
         return c_lm_opts(self.n_iter, self.tau, self.lam_min, self.lam_max, (ctypes.c_double * 3)(*self.lo),
-                         (ctypes.c_double * 3)(*self.hi), self.eta)
+                         (ctypes.c_double * 3)(*self.hi), self.eta, int(self.restart))
 
 
 # ----------------------------------------------------------------------------------------------

@@ -20,7 +20,8 @@ def kcs_objects(st):
     k = kcs.Kinetics(st.kin.A1, st.kin.A2, st.kin.A3, st.kin.l1, st.kin.l2, st.kin.l3, st.kin.vb)
     p = kcs.Prior(st.prior.beta_kp, st.prior.eps_F, st.prior.beta_h, st.prior.delta, st.prior.kp_on,
                   st.prior.plane_ratio)
-    lm = kcs.LMOptions(st.lm.n_iter, st.lm.tau, st.lm.lam_min, st.lm.lam_max, st.lm.lo, st.lm.hi, st.lm.eta)
+    lm = kcs.LMOptions(st.lm.n_iter, st.lm.tau, st.lm.lam_min, st.lm.lam_max, st.lm.lo, st.lm.hi, st.lm.eta,
+                       st.lm.restart)
     return g, f, k, p, lm
 
 

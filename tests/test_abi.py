@@ -165,3 +165,28 @@ def test_limits_rejected_before_launching():
     assert call_project(g, frames(), q=0, Q=2, x=0, y=0) == kcs.KCS_ESHAPE  # 1025 angles in subset 0
     g = kcs.Geometry(12, 12, 1, 3.0, 30, 120, 0.45)
     assert call_project(g, frames(), q=0, Q=3, x=0, y=0) == kcs.KCS_ESHAPE  # 6.7 times narrower
+
+
+def test_plane_of_more_than_2_31_values_rejected():
+    """Offsets within one plane's image are 32-bit in the kernels: a plane of nx * ny * M >= 2^31
+    values is refused on the host (16384 x 16384 pixels with 8 frames) while one below passes the
+    shape checks (it fails later, on the NULL pointers)."""
+    big = kcs.Geometry(16384, 16384, 1, 1.0, 60, 64, 1.0)
+    assert call_project(big, frames(M=8), x=0, y=0) == kcs.KCS_ESHAPE
+    assert "2^31" in kcs.kcs_last_error()
+    ok = kcs.Geometry(16384, 8192, 1, 1.0, 60, 64, 1.0)
+    assert call_project(ok, frames(M=8), x=0, y=0) == kcs.KCS_EINVAL
+
+
+def test_footprint_counts_the_correction_sinogram():
+    g = geometry()
+    gc = g.c()
+    plain = kcs.lib().kcs_study_footprint_bytes(ctypes.byref(gc), 24, 4)
+    gc.d_mult = ctypes.c_void_p(256)
+    with_mult = kcs.lib().kcs_study_footprint_bytes(ctypes.byref(gc), 24, 4)
+    assert with_mult - plain == g.nz * g.n_ang * g.n_bin * 4
+
+
+def test_lm_options_carry_the_restart_flag():
+    assert kcs.LMOptions(5, 1e-3, 1e-8, 1e8, inputs.LM_LO, inputs.LM_HI).c().restart == 1
+    assert kcs.LMOptions(5, 1e-3, 1e-8, 1e8, inputs.LM_LO, inputs.LM_HI, 1e-3, False).c().restart == 0
