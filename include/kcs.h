@@ -183,6 +183,19 @@ int kcs_icm_sweep(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics
                   const kcs_lm_opts* lm, const float* d_sino, int32_t Q, int32_t sweep_idx, float* d_x,
                   float* d_params, float* d_lambda, void* d_work, size_t work_bytes, hipStream_t stream);
 
+/* kcs_icm_sweep without a caller workspace, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid hipMalloc).  The workspace
+ * is a static array of the library, 256 MiB per GPU, held from the library's load until the
+ * process ends; the call itself allocates nothing.  Arguments, results and errors are those of
+ * kcs_icm_sweep, plus KCS_EWORKSPACE (nothing launched) when kcs_workspace_bytes(g, M, Q)
+ * exceeds 256 MiB (for example 128 x 128 images with M = 24, Q = 6 and more than about 35
+ * planes).  All calls on one GPU share that GPU's array: calls that overlap on one GPU (other
+ * streams, other host threads) race and must be ordered by the caller.  Nothing in the array
+ * carries over from one call to the next. */
+int kcs_icm_sweep_noalloc(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics* k, const kcs_prior* p,
+                          const kcs_lm_opts* lm, const float* d_sino, int32_t Q, int32_t sweep_idx, float* d_x,
+                          float* d_params, float* d_lambda, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------------------------
  * Batched execution.  A plan runs ICM sweeps of many independent studies (uneven sizes, subset
  * counts and schedules) together: every phase of a sweep (model pass, forward projection,

@@ -816,6 +816,67 @@ int autotune(std::vector<StudyPrep>& preps, hipStream_t st) {
     return rc;
 }
 
+// ----- one ICM sweep, shared by the caller-workspace and the static-scratch entry points -----
+int check_sweep_args(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics* k, const kcs_prior* p,
+                     const kcs_lm_opts* lm, const float* d_sino, int32_t Q, int32_t sweep_idx, const float* d_x,
+                     const float* d_params, const float* d_lambda) {
+    KCS_TRY(check_geometry(g));
+    KCS_TRY(check_frames(f));
+    KCS_TRY(check_plane(g, f->n_frames));
+    KCS_TRY(check_kinetics(k));
+    KCS_TRY(check_prior(p));
+    KCS_TRY(check_lm(lm));
+    KCS_TRY(check_subset(g, 0, Q));
+    if (sweep_idx < 0) return fail(KCS_EINVAL, "sweep_idx must be >= 0");
+    if (!d_sino || !d_x || !d_params || !d_lambda) return fail(KCS_EINVAL, "device pointers must not be NULL");
+    return KCS_OK;
+}
+
+// Every region of the workspace that the sweep reads is written earlier in the same sweep (the
+// kinetic table, the model TACs, the ratio and partial sums of each subset, the ping-pong maps
+// and the carried normal equations), so a workspace needs no clearing between calls.
+int icm_sweep_body(const kcs_geometry& g, const kcs_frames& f, const kcs_kinetics& k, const kcs_prior& p,
+                   const kcs_lm_opts& lm, const float* d_sino, int32_t Q, int32_t sweep_idx, float* d_x,
+                   float* d_params, float* d_lambda, void* d_work, hipStream_t stream) {
+    const Schedule S = make_schedule(f, &k);
+    g_err.clear();
+    KCS_TRY(do_setup(S, d_work, stream));
+    const bool kp = p.kp_on != 0 && sweep_idx > 0;
+    if (kp) KCS_TRY(do_model_pass(g, S, d_params, d_work, Q, stream));
+    for (int32_t q = 0; q < Q; ++q) KCS_TRY(do_osl(g, S, p, kp, d_sino, q, Q, d_x, d_work, stream));
+    return do_lm(g, S, p, lm, d_x, d_params, d_lambda, d_work, Q, lm.restart != 0, stream);
+}
+
+// ----- static scratch of kcs_icm_sweep_noalloc -----
+// A workspace in the library's own device memory for callers that cannot allocate.  Each GPU
+// holds its own copy from the load of the library to the end of the process.  In host code the
+// array's name is not a device address: the address comes from hipGetSymbolAddress, taken once
+// per device with that device current, and only that address is passed to kernels.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(KCS_EINVAL, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255) != 0)
+            return fail(KCS_EHIP, "static scratch has no 256-byte aligned device address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return KCS_OK;
+}
+
 }  // namespace
 }  // namespace kcs
 
@@ -1007,23 +1068,22 @@ int kcs_init_state(const kcs_geometry* g, const kcs_frames* f, const float* d_si
 int kcs_icm_sweep(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics* k, const kcs_prior* p,
                   const kcs_lm_opts* lm, const float* d_sino, int32_t Q, int32_t sweep_idx, float* d_x, float* d_params,
                   float* d_lambda, void* d_work, size_t work_bytes, hipStream_t stream) {
-    KCS_TRY(check_geometry(g));
-    KCS_TRY(check_frames(f));
-    KCS_TRY(check_plane(g, f->n_frames));
-    KCS_TRY(check_kinetics(k));
-    KCS_TRY(check_prior(p));
-    KCS_TRY(check_lm(lm));
-    KCS_TRY(check_subset(g, 0, Q));
-    if (sweep_idx < 0) return fail(KCS_EINVAL, "sweep_idx must be >= 0");
-    if (!d_sino || !d_x || !d_params || !d_lambda) return fail(KCS_EINVAL, "device pointers must not be NULL");
+    KCS_TRY(check_sweep_args(g, f, k, p, lm, d_sino, Q, sweep_idx, d_x, d_params, d_lambda));
     KCS_TRY(check_work(g, f->n_frames, Q, d_work, work_bytes));
-    const Schedule S = make_schedule(*f, k);
-    g_err.clear();
-    KCS_TRY(do_setup(S, d_work, stream));
-    const bool kp = p->kp_on != 0 && sweep_idx > 0;
-    if (kp) KCS_TRY(do_model_pass(*g, S, d_params, d_work, Q, stream));
-    for (int32_t q = 0; q < Q; ++q) KCS_TRY(do_osl(*g, S, *p, kp, d_sino, q, Q, d_x, d_work, stream));
-    return do_lm(*g, S, *p, *lm, d_x, d_params, d_lambda, d_work, Q, lm->restart != 0, stream);
+    return icm_sweep_body(*g, *f, *k, *p, *lm, d_sino, Q, sweep_idx, d_x, d_params, d_lambda, d_work, stream);
+}
+
+int kcs_icm_sweep_noalloc(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics* k, const kcs_prior* p,
+                          const kcs_lm_opts* lm, const float* d_sino, int32_t Q, int32_t sweep_idx, float* d_x,
+                          float* d_params, float* d_lambda, hipStream_t stream) {
+    KCS_TRY(check_sweep_args(g, f, k, p, lm, d_sino, Q, sweep_idx, d_x, d_params, d_lambda));
+    const size_t need = layout(g, f->n_frames, Q).total;
+    if (need > kScratchBytes)
+        return fail(KCS_EWORKSPACE, "study needs %zu bytes of workspace; the library's static scratch holds %zu", need,
+                    kScratchBytes);
+    void* work = nullptr;
+    KCS_TRY(scratch_address(&work));
+    return icm_sweep_body(*g, *f, *k, *p, *lm, d_sino, Q, sweep_idx, d_x, d_params, d_lambda, work, stream);
 }
 
 int kcs_plan_create(const kcs_study* studies, int32_t n, int32_t flags, hipStream_t stream, kcs_plan** out) {

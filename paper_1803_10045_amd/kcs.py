@@ -21,6 +21,7 @@ KCS_OK, KCS_EINVAL, KCS_ESHAPE, KCS_EWORKSPACE, KCS_EHIP = 0, -1, -2, -3, -4
 # Entry points declared in include/kcs.h (checked against the header by the tests).
 ENTRY_POINTS = ("kcs_workspace_bytes", "kcs_study_footprint_bytes", "kcs_project", "kcs_backproject",
                 "kcs_model_tac", "kcs_ki_map", "kcs_osl_update", "kcs_lm_fit", "kcs_init_state", "kcs_icm_sweep",
+                "kcs_icm_sweep_noalloc",
                 "kcs_plan_create", "kcs_plan_run", "kcs_plan_describe", "kcs_plan_destroy",
                 "kcs_timing_enable", "kcs_timing_collect", "kcs_last_error")
 
@@ -93,8 +94,10 @@ def lib() -> ctypes.CDLL:
     L.kcs_init_state.argtypes = [P(c_geometry), P(c_frames), vp, P(ctypes.c_double), vp, vp, vp, vp, sz, vp]
     L.kcs_icm_sweep.argtypes = [P(c_geometry), P(c_frames), P(c_kinetics), P(c_prior), P(c_lm_opts), vp, i32, i32, vp,
                                 vp, vp, vp, sz, vp]
+    L.kcs_icm_sweep_noalloc.argtypes = [P(c_geometry), P(c_frames), P(c_kinetics), P(c_prior), P(c_lm_opts), vp, i32,
+                                        i32, vp, vp, vp, vp]
     for name in ("kcs_project", "kcs_backproject", "kcs_model_tac", "kcs_ki_map", "kcs_osl_update", "kcs_lm_fit",
-                 "kcs_init_state", "kcs_icm_sweep"):
+                 "kcs_init_state", "kcs_icm_sweep", "kcs_icm_sweep_noalloc"):
         getattr(L, name).restype = ctypes.c_int
     L.kcs_plan_create.argtypes = [P(c_study), i32, i32, vp, P(vp)]
     L.kcs_plan_create.restype = ctypes.c_int
@@ -335,6 +338,17 @@ def kcs_icm_sweep(g: Geometry, f: Frames, k: Kinetics, p: Prior, lm: LMOptions, 
                                ctypes.byref(lc), _ptr(sino, (g.nz, g.n_ang, g.n_bin, f.M), "sino"), Q, sweep_idx,
                                _ptr(x, (g.nz, g.ny, g.nx, f.M), "x"), _ptr(params, (3, g.nz, g.ny, g.nx), "params"),
                                _ptr(lam, (g.nz, g.ny, g.nx), "lambda"), wp, wn, _stream(stream)))
+
+
+def kcs_icm_sweep_noalloc(g: Geometry, f: Frames, k: Kinetics, p: Prior, lm: LMOptions, sino, Q: int,
+                          sweep_idx: int, x, params, lam, stream=None):
+    """kcs_icm_sweep with the library's static per-GPU scratch as workspace (allocates nothing)."""
+    gc, fc, kc, pc, lc = g.c(), f.c(), k.c(), p.c(), lm.c()
+    _check(lib().kcs_icm_sweep_noalloc(ctypes.byref(gc), ctypes.byref(fc), ctypes.byref(kc), ctypes.byref(pc),
+                                       ctypes.byref(lc), _ptr(sino, (g.nz, g.n_ang, g.n_bin, f.M), "sino"), Q,
+                                       sweep_idx, _ptr(x, (g.nz, g.ny, g.nx, f.M), "x"),
+                                       _ptr(params, (3, g.nz, g.ny, g.nx), "params"),
+                                       _ptr(lam, (g.nz, g.ny, g.nx), "lambda"), _stream(stream)))
 
 
 @dataclass

@@ -190,3 +190,24 @@ def test_footprint_counts_the_correction_sinogram():
 def test_lm_options_carry_the_restart_flag():
     assert kcs.LMOptions(5, 1e-3, 1e-8, 1e8, inputs.LM_LO, inputs.LM_HI).c().restart == 1
     assert kcs.LMOptions(5, 1e-3, 1e-8, 1e8, inputs.LM_LO, inputs.LM_HI, 1e-3, False).c().restart == 0
+
+
+def test_noalloc_sweep_rejects_studies_beyond_its_static_scratch():
+    """kcs_icm_sweep_noalloc refuses, on the host and before touching the device, a study whose
+    workspace exceeds the library's 256 MiB static scratch (128 x 128 x 60, 6 subsets)."""
+    cfg = inputs.scaled(inputs.brain128(), nz=60)
+    g = kcs.Geometry.from_config(cfg)
+    assert kcs.kcs_workspace_bytes(g, 24, cfg.Q) > 256 << 20
+    f = frames()
+    k = kcs.Kinetics(**inputs.FENG, vb=inputs.VB).c()
+    p = kcs.Prior(0.1, 0.01, 0.1, (1e-3,) * 3).c()
+    lm = kcs.LMOptions(5, 1e-3, 1e-8, 1e8, inputs.LM_LO, inputs.LM_HI).c()
+    gc, fc = g.c(), f.c()
+    vp = ctypes.c_void_p
+    rc = kcs.lib().kcs_icm_sweep_noalloc(ctypes.byref(gc), ctypes.byref(fc), ctypes.byref(k), ctypes.byref(p),
+                                         ctypes.byref(lm), vp(256), cfg.Q, 0, vp(256), vp(256), vp(256), None)
+    assert rc == kcs.KCS_EWORKSPACE
+    assert "static scratch" in kcs.kcs_last_error()
+    rc = kcs.lib().kcs_icm_sweep_noalloc(ctypes.byref(gc), ctypes.byref(fc), ctypes.byref(k), ctypes.byref(p),
+                                         ctypes.byref(lm), vp(0), cfg.Q, 0, vp(256), vp(256), vp(256), None)
+    assert rc == kcs.KCS_EINVAL  # argument checks come first
