@@ -227,9 +227,13 @@ typedef struct kcs_plan kcs_plan;
 
 enum {
     KCS_PLAN_GRAPH = 1,   /* capture the whole schedule in one HIP graph; kcs_plan_run launches it */
-    KCS_PLAN_AUTOTUNE = 2 /* time the projector variants (ray-driven, 16, 32 or 64 pixel tiles) per shape
-                             class on these studies and keep the fastest; results are cached in the
-                             file named by KCS_TUNE_CACHE when that variable is set */
+    KCS_PLAN_AUTOTUNE = 2 /* time the projector variants (ray-driven, 16, 32 or 64 pixel tiles) on these
+                             studies for every study shape (grid, bins, subset size, frames, pixel/bin
+                             ratio) not tuned yet, and keep the fastest for that shape for the rest of
+                             the process: every later call on a study of that shape, plain or planned,
+                             uses it, so a study's result depends on its shape and not on the call.
+                             With KCS_TUNE_CACHE set, tuned shapes are appended to that file and read
+                             back by later processes (which then start from them) */
 };
 
 /* Validates every study (on failure: KCS_EINVAL / KCS_EWORKSPACE naming the study, nothing is
@@ -270,6 +274,13 @@ enum {
 };
 int kcs_timing_enable(int32_t on);
 int kcs_timing_collect(double* total_ms, int64_t* count);
+
+/* Device bandwidth probe for measurement harnesses (no part of the method): kind 0 reads `bytes`
+ * from d_src (16-byte aligned, bytes a positive multiple of 16) with a grid-stride loop of
+ * `groups` workgroups of 256 threads and writes one partial sum per thread into d_dst
+ * (groups * 256 floats); kind 1 copies `bytes` from d_src to d_dst (16-byte aligned, not
+ * overlapping).  1 <= groups <= 2^20.  Asynchronous on `stream`; KCS_EINVAL otherwise. */
+int kcs_stream_probe(int32_t kind, const void* d_src, void* d_dst, size_t bytes, int32_t groups, hipStream_t stream);
 
 /* Message describing the last error on the calling thread ("" if none). */
 const char* kcs_last_error(void);

@@ -67,3 +67,49 @@ def make_study(cfg, with_truth: bool = True) -> Study:
                    lo=inputs.LM_LO, hi=inputs.LM_HI, eta=inputs.LM_ETA)
     fr = Frames(t0=t0, t1=t1, E=E, r=r)
     return Study(cfg, g, fr, kin, prior, lm, sino, maps, x_true if with_truth else None, mask)
+
+
+def make_plane_study(cfg, planes, seed=None) -> Study:
+    """Planes `planes` of the 3D study `cfg` as a study of their own, with the whole study's
+    calibration: the same scale E_m = c dt_m (c from the expected trues of all nz planes), the
+    same background per bin r_m (bg_frac x counts spread over every bin of the nz planes) and the
+    same Huber threshold (from the whole phantom), so that each plane carries the counts it has in
+    the full study.  Direct planes do not interact in the projector or in the in-plane prior, so
+    running these planes alone follows the full study's schedule on them.  The counts are drawn
+    for these planes only, from `seed` (default: derived from the study's seed and the planes)."""
+    planes = [int(z) for z in planes]
+    maps, mask = inputs.phantom_maps(cfg)
+    g_full = geo.Geometry.from_config(cfg)
+    kin = Kinetics(**inputs.FENG, vb=inputs.VB)
+    t0, t1 = inputs.frame_times(cfg.frame_blocks)
+    dt = t1 - t0
+    M = len(t0)
+    # sum_d p_vd over all angles (one plane), then the expected trues of the whole study per unit c:
+    # sum_m dt_m sum_z sum_v sens_v x_zvm, with x the model TAC of each voxel's true maps
+    sens = np.asarray(geo.system_matrix(g_full).sum(axis=0)).reshape(cfg.ny, cfg.nx)
+    obj = np.nonzero(mask.reshape(-1))[0]
+    triples, which = np.unique(maps.reshape(3, -1)[:, obj].T, axis=0, return_inverse=True)
+    F = model_tac(triples, t0, t1, kin)  # (n_unique, M)
+    weight = np.broadcast_to(sens, mask.shape).reshape(-1)[obj]
+    total = float(np.sum(np.bincount(which.ravel(), weights=weight, minlength=len(triples)) * (F @ dt)))
+    c = cfg.counts / total
+    E = c * dt
+    r = cfg.bg_frac * cfg.counts * (dt / dt.sum()) / (cfg.n_ang * cfg.n_bin * cfg.nz)
+    delta = inputs.huber_delta(maps, mask)
+    sub = inputs.scaled(cfg, name=f"{cfg.name}_planes_{'_'.join(map(str, planes))}", nz=len(planes))
+    g = geo.Geometry.from_config(sub)
+    pm = maps[:, planes]
+    pmask = mask[planes]
+    x_true = np.zeros((len(planes), cfg.ny, cfg.nx, M))
+    idx = np.nonzero(pmask.ravel())[0]
+    if len(idx):
+        x_true.reshape(-1, M)[idx] = model_tac(pm.reshape(3, -1).T[idx], t0, t1, kin)
+    expected = E * geo.forward(g, x_true) + r
+    if seed is None:
+        seed = int(cfg.seed) * 100003 + sum((z + 1) * 7919 ** k for k, z in enumerate(planes))
+    sino = inputs.poisson_counts(expected, seed)
+    prior = Prior(beta_kp=inputs.BETA_KP, eps_F=1e-4 * peak_input(kin), beta_h=cfg.beta_h,
+                  delta=(delta, delta, delta), kp_on=True)
+    lm = LMOptions(n_iter=cfg.n_lm, tau=inputs.LM_TAU, lam_min=inputs.LM_LAM_MIN, lam_max=inputs.LM_LAM_MAX,
+                   lo=inputs.LM_LO, hi=inputs.LM_HI, eta=inputs.LM_ETA)
+    return Study(sub, g, Frames(t0=t0, t1=t1, E=E, r=r), kin, prior, lm, sino, pm, x_true, pmask)

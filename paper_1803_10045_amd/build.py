@@ -2,7 +2,10 @@
 
 Every translation unit compiles in parallel to an object under ``_build/`` and the objects
 link into ``paper_1803_10045_amd/libkcs.so``.  Packed FP32 instructions are switched off for
-all device code.
+all device code.  Multiply-adds are fused only within one source expression
+(``-ffp-contract=on``), so a kernel rounds the same way in every template instantiation (one
+study, or a device table of studies) and batched runs reproduce the single-study calls bit for
+bit.
 """
 from __future__ import annotations
 
@@ -21,7 +24,7 @@ ARCH = os.environ.get("KCS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
-          "-packed-fp32-ops", "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-parameter"]
+          "-packed-fp32-ops", "-ffp-contract=on", "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-parameter"]
 
 
 def sources():

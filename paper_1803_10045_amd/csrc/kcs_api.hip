@@ -234,6 +234,8 @@ ProjArgs proj_args(const kcs_geometry& g, const FrameTab& fr, int32_t q, int32_t
     p.du = (float)g.bin_mm;
     p.inv_du = (float)(1.0 / g.bin_mm);
     p.ang0 = g.ang0_rad;
+    p.hd = g.pixel_mm;
+    p.dud = g.bin_mm;
     p.mult = g.d_mult;
     p.fr = fr;
     return p;
@@ -283,12 +285,68 @@ struct Layout {
     size_t kin, xi, lms, init, F, ratio, psum, total;
 };
 
-// Forward projector variant for a geometry: 0 = ray-driven, T = LDS tiles of T x T pixels.
-// Images whose plane exceeds an XCD's L2 use tiles.  KCS_PROJ_TILE overrides (0, 16, 32, 64).
-int projector_tile(const kcs_geometry& g, int M) {
+// ----- forward projector variant per shape -----
+// The variants (ray-driven, LDS tiles of 16, 32 or 64 pixels) add a ray's line integral in
+// different orders, so they round differently.  A study's variant is a function of its shape
+// only, the same for plain calls and plans: the default rule below, or the variant the plan
+// autotuner measured for that shape, which it records here for the rest of the process (and in
+// the file named by KCS_TUNE_CACHE, from which later processes start).
+struct TuneKey {
+    int nx, ny, n_bin, A_q, M;
+    float hdu;
+    bool operator==(const TuneKey& o) const {
+        return nx == o.nx && ny == o.ny && n_bin == o.n_bin && A_q == o.A_q && M == o.M && hdu == o.hdu;
+    }
+};
+
+TuneKey tune_key(const kcs_geometry& g, int M, int32_t Q) {
+    return TuneKey{g.nx, g.ny, g.n_bin, (g.n_ang + Q - 1) / Q, M, (float)(g.pixel_mm / g.bin_mm)};
+}
+
+std::mutex g_tune_mu;
+std::vector<std::pair<TuneKey, int>> g_tuned;  // guarded by g_tune_mu
+bool g_tune_file_read = false;
+
+// Tuned variant of a shape, or -1; on first use loads the KCS_TUNE_CACHE file.  Caller holds
+// g_tune_mu.
+int tuned_tile_locked(const TuneKey& k) {
+    if (!g_tune_file_read) {
+        g_tune_file_read = true;
+        const char* path = getenv("KCS_TUNE_CACHE");
+        if (FILE* f = path ? fopen(path, "r") : nullptr) {
+            int nx, ny, nb, aq, M, T;
+            float hdu, ms;
+            while (fscanf(f, "%d %d %d %d %d %f %d %f", &nx, &ny, &nb, &aq, &M, &hdu, &T, &ms) == 8) {
+                if (T != 0 && T != 16 && T != 32 && T != 64) continue;
+                const TuneKey key{nx, ny, nb, aq, M, hdu};
+                bool seen = false;
+                for (auto& e : g_tuned)
+                    if (e.first == key) {
+                        e.second = T;  // the file's last entry for a shape wins
+                        seen = true;
+                    }
+                if (!seen) g_tuned.push_back({key, T});
+            }
+            fclose(f);
+        }
+    }
+    for (const auto& e : g_tuned)
+        if (e.first == k) return e.second;
+    return -1;
+}
+
+// Variant for a study shape: KCS_PROJ_TILE (0, 16, 32, 64) overrides; then a tuned variant of
+// this shape; otherwise LDS tiles of 32 pixels for planes beyond an XCD's L2 share (2 MB),
+// ray-driven below.
+int projector_tile(const kcs_geometry& g, int M, int32_t Q) {
     if (const char* e = getenv("KCS_PROJ_TILE")) {
         const int t = atoi(e);
         if (t == 0 || t == 16 || t == 32 || t == 64) return t;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        const int t = tuned_tile_locked(tune_key(g, M, Q));
+        if (t >= 0) return t;
     }
     const double plane_bytes = (double)g.nx * g.ny * M * 4.0;
     return plane_bytes < 2.0 * 1024 * 1024 ? 0 : 32;
@@ -414,7 +472,7 @@ int do_osl(const kcs_geometry& g, const Schedule& S, const kcs_prior& p, bool kp
     a.eps_F = (float)p.eps_F;
     a.kp = kp ? 1 : 0;
     float* ratio = at<float>(d_work, L.ratio);
-    const int T = projector_tile(g, S.fr.M);
+    const int T = projector_tile(g, S.fr.M, Q);
     float* psum = at<float>(d_work, L.psum);
     KCS_TRY(launched(timed(KCS_T_PROJECT, st,
                            [&] {
@@ -718,31 +776,6 @@ hipError_t run_phase(const PlanPhase& ph, const char* base, hipStream_t st) {
     }
 }
 
-// ----- projector autotuning: time each variant on the studies of one shape class -----
-struct TuneKey {
-    int nx, ny, n_bin, A_q, M;
-    float hdu;
-    bool operator==(const TuneKey& o) const {
-        return nx == o.nx && ny == o.ny && n_bin == o.n_bin && A_q == o.A_q && M == o.M && hdu == o.hdu;
-    }
-};
-
-std::mutex g_tune_mu;
-
-int cached_tile(const TuneKey& k) {
-    const char* path = getenv("KCS_TUNE_CACHE");
-    if (!path) return -1;
-    FILE* f = fopen(path, "r");
-    if (!f) return -1;
-    int nx, ny, nb, aq, M, T;
-    float hdu, ms;
-    int found = -1;
-    while (fscanf(f, "%d %d %d %d %d %f %d %f", &nx, &ny, &nb, &aq, &M, &hdu, &T, &ms) == 8)
-        if (TuneKey{nx, ny, nb, aq, M, hdu} == k) found = T;
-    fclose(f);
-    return found;
-}
-
 void store_tile(const TuneKey& k, int T, float ms) {
     const char* path = getenv("KCS_TUNE_CACHE");
     if (!path) return;
@@ -752,13 +785,14 @@ void store_tile(const TuneKey& k, int T, float ms) {
     }
 }
 
+// Times the projector variants on the studies of each shape not tuned yet in this process (or in
+// the KCS_TUNE_CACHE file), keeps the fastest for the shape (plain calls of that shape use it from
+// now on) and appends it to the file.
 int autotune(std::vector<StudyPrep>& preps, hipStream_t st) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     std::vector<TuneKey> keys;
     for (const StudyPrep& P : preps) {
-        const kcs_study& s = *P.s;
-        TuneKey k{s.g.nx, s.g.ny, s.g.n_bin, subset_size(s.g, 0, s.Q), s.f.n_frames,
-                  (float)(s.g.pixel_mm / s.g.bin_mm)};
+        const TuneKey k = tune_key(P.s->g, P.s->f.n_frames, P.s->Q);
         if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
     }
     void* dtab = nullptr;
@@ -767,13 +801,9 @@ int autotune(std::vector<StudyPrep>& preps, hipStream_t st) {
     int rc = KCS_OK;
     for (const TuneKey& k : keys) {
         std::vector<StudyPrep*> cls;
-        for (StudyPrep& P : preps) {
-            const kcs_study& s = *P.s;
-            if (TuneKey{s.g.nx, s.g.ny, s.g.n_bin, subset_size(s.g, 0, s.Q), s.f.n_frames,
-                        (float)(s.g.pixel_mm / s.g.bin_mm)} == k)
-                cls.push_back(&P);
-        }
-        int best = cached_tile(k);
+        for (StudyPrep& P : preps)
+            if (tune_key(P.s->g, P.s->f.n_frames, P.s->Q) == k) cls.push_back(&P);
+        int best = tuned_tile_locked(k);
         if (best < 0) {
             float best_ms = 1e30f;
             for (int T : {0, 16, 32, 64}) {
@@ -807,6 +837,7 @@ int autotune(std::vector<StudyPrep>& preps, hipStream_t st) {
                 }
             }
             if (rc != KCS_OK) break;
+            g_tuned.push_back({k, best});
             store_tile(k, best, best_ms / 3.0f);
         }
         for (StudyPrep* P : cls) P->T = best;
@@ -931,6 +962,21 @@ int kcs_timing_collect(double* total_ms, int64_t* count) {
         g_event_pool.push_back(t.b);
     }
     return rc;
+}
+
+int kcs_stream_probe(int32_t kind, const void* d_src, void* d_dst, size_t bytes, int32_t groups, hipStream_t stream) {
+    if (kind != 0 && kind != 1) return fail(KCS_EINVAL, "kind must be 0 (read) or 1 (copy)");
+    if (!d_src || !d_dst) return fail(KCS_EINVAL, "device pointers must not be NULL");
+    if (bytes == 0 || bytes % 16 != 0) return fail(KCS_EINVAL, "bytes must be a positive multiple of 16");
+    if ((reinterpret_cast<uintptr_t>(d_src) | reinterpret_cast<uintptr_t>(d_dst)) & 15)
+        return fail(KCS_EINVAL, "pointers must be 16-byte aligned");
+    if (groups < 1 || groups > (1 << 20)) return fail(KCS_EINVAL, "need 1 <= groups <= 2^20");
+    if (kind == 1) {
+        const uintptr_t a = reinterpret_cast<uintptr_t>(d_src), b = reinterpret_cast<uintptr_t>(d_dst);
+        if (a < b + bytes && b < a + bytes) return fail(KCS_EINVAL, "copy ranges overlap");
+    }
+    g_err.clear();
+    return launched(launch_stream(kind, d_src, d_dst, bytes, groups, stream), "stream probe");
 }
 
 size_t kcs_workspace_bytes(const kcs_geometry* g, int32_t n_frames, int32_t Q) {
@@ -1097,7 +1143,7 @@ int kcs_plan_create(const kcs_study* studies, int32_t n, int32_t flags, hipStrea
         preps[i].s = &studies[i];
         preps[i].S = make_schedule(studies[i].f, &studies[i].k);
         preps[i].L = layout(&studies[i].g, studies[i].f.n_frames, studies[i].Q);
-        preps[i].T = projector_tile(studies[i].g, studies[i].f.n_frames);
+        preps[i].T = projector_tile(studies[i].g, studies[i].f.n_frames, studies[i].Q);
     }
     g_err.clear();
     for (const StudyPrep& P : preps) KCS_TRY(do_setup(P.S, P.s->d_work, stream));

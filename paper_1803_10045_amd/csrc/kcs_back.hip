@@ -20,85 +20,35 @@
 
 namespace kcs {
 
-constexpr int kTileX = 64, kTileY = 4;
 constexpr int kMaxSubsetAngles = 1024;
 
-struct TileIdx {
-    int i, j, z;
-    bool valid;
+// Per angle, the bins [b0, b1] whose rays can meet a pixel box and the signed distance tb from
+// the centre of the box's corner pixel to ray b0, along the detector (mm).
+struct BinRange {
+    int32_t b0, b1;
+    float tb, pad;
 };
 
-__device__ __forceinline__ TileIdx tile_voxel(uint32_t w, int nx, int ny, int nz) {
-    const uint32_t tx = (nx + kTileX - 1) / kTileX, ty = (ny + kTileY - 1) / kTileY;
-    TileIdx t;
-    t.z = w / (tx * ty);
-    const uint32_t r = w % (tx * ty);
-    t.j = (r / tx) * kTileY + threadIdx.x / kTileX;
-    t.i = (r % tx) * kTileX + threadIdx.x % kTileX;
-    t.valid = t.z < nz && t.i < nx && t.j < ny;
-    return t;
-}
-
-uint32_t voxel_tile_groups(int nx, int ny, int nz) {
-    const uint32_t tx = (nx + kTileX - 1) / kTileX, ty = (ny + kTileY - 1) / kTileY;
-    return tx * ty * (uint32_t)nz;
-}
-
-// Builds the subset's angle constants in LDS; all threads of the block take part.
-__device__ __forceinline__ void subset_angles_to_lds(AngleRec* sA, const ProjArgs& p) {
-    for (int al = threadIdx.x; al < p.A_q; al += blockDim.x) sA[al] = make_angle(p.q + al * p.Q, p.n_ang, p.ang0, p.h);
-    __syncthreads();
-}
-
-// The same, plus per angle the range of bins whose rays can meet the pixel box (i0, j0, tw, th).
-__device__ __forceinline__ void subset_angles_bins_to_lds(AngleRec* sA, int2* sBB, const ProjArgs& p, int i0, int j0,
-                                                          int tw, int th) {
+// The same, plus the bin range of every angle for the pixel box (i0, j0, tw, th).  tb is formed
+// in FP64, so that a voxel's distance to a ray, tb + (b - b0) du - (its offset from the corner
+// pixel projected on the detector), is a sum of terms no larger than the box: its FP32 error is
+// that of the box's size, not of the distance to the image centre.
+__device__ __forceinline__ void subset_angles_bins_to_lds(AngleRec* sA, BinRange* sBB, const ProjArgs& p, int i0,
+                                                          int j0, int tw, int th) {
     for (int al = threadIdx.x; al < p.A_q; al += blockDim.x) {
-        const AngleRec A = make_angle(p.q + al * p.Q, p.n_ang, p.ang0, p.h);
+        double c, s;
+        angle_cos_sin(p.q + al * p.Q, p.n_ang, p.ang0, c, s);
+        const AngleRec A = make_angle_cs(c, s, p.h);
         sA[al] = A;
-        int b0, b1;
-        box_bins(A, i0, j0, tw, th, p.nx, p.ny, p.h, p.inv_du, p.n_bin, b0, b1);
-        sBB[al] = make_int2(b0, b1);
+        BinRange r;
+        box_bins(A, i0, j0, tw, th, p.nx, p.ny, p.h, p.inv_du, p.n_bin, r.b0, r.b1);
+        const double xc0 = ((double)i0 - 0.5 * (double)(p.nx - 1)) * p.hd;
+        const double yc0 = ((double)j0 - 0.5 * (double)(p.ny - 1)) * p.hd;
+        r.tb = (float)(((double)r.b0 - 0.5 * (double)(p.n_bin - 1)) * p.dud - (xc0 * c + yc0 * s));
+        r.pad = 0.0f;
+        sBB[al] = r;
     }
     __syncthreads();
-}
-
-// acc_m = sum_{d in S_q} mu_d p_vd y_dm and sens = sum_{d in S_q} mu_d p_vd for voxel (i, j, z),
-// mu_d the ray's multiplicative correction (1 without one).
-template <int M>
-__host__ __device__ __forceinline__ void gather(const AngleRec* sA, const ProjArgs& p, const float* __restrict__ y, int i, int j,
-                                       int z, float (&acc)[M], float& sens) {
-    const float xc = ((float)i - 0.5f * (float)(p.nx - 1)) * p.h;
-    const float yc = ((float)j - 0.5f * (float)(p.ny - 1)) * p.h;
-#pragma unroll
-    for (int m = 0; m < M; ++m) acc[m] = 0.0f;
-    sens = 0.0f;
-    const float* yz = y + (size_t)z * p.A_q * p.n_bin * M;
-    for (int al = 0; al < p.A_q; ++al) {
-        const float* ya = yz + (size_t)al * p.n_bin * M;
-        const float* mua = p.mult ? p.mult + ((size_t)z * p.n_ang + p.q + al * p.Q) * p.n_bin : nullptr;
-        pixel_footprint(sA[al], xc, yc, p.n_bin, p.du, p.inv_du, [&](int b, float len) {
-            if (mua) len *= mua[b];
-            float v[M];
-            load_record<M>(ya + (size_t)b * M, v);
-#pragma unroll
-            for (int m = 0; m < M; ++m) acc[m] = fmaf(len, v[m], acc[m]);
-            sens += len;
-        });
-    }
-}
-
-template <int M>
-__host__ __device__ __forceinline__ void backproject_voxel(const AngleRec* sA, const ProjArgs& p,
-                                                           const float* __restrict__ y, float* __restrict__ bout,
-                                                           float* __restrict__ sens_out, int i, int j, int z) {
-    float acc[M], sens;
-    gather<M>(sA, p, y, i, j, z, acc, sens);
-    const size_t v = ((size_t)z * p.ny + j) * p.nx + i;
-#pragma unroll
-    for (int m = 0; m < M; ++m) acc[m] *= p.fr.E[m];
-    store_record<M>(bout + v * M, acc);
-    if (sens_out) sens_out[v] = sens;
 }
 
 // Loads voxel v's TAC (xv) and, when the prior is on, its model TAC from Fm [N][M] (F).  The
@@ -135,18 +85,6 @@ __host__ __device__ __forceinline__ void osl_finish(const OslArgs& a, float* __r
     store_record<M>(x + v * M, xv);
 }
 
-template <int M>
-__host__ __device__ __forceinline__ void osl_voxel(const AngleRec* sA, const OslArgs& a, const float* __restrict__ ratio,
-                                                   const float* __restrict__ Fm, float* __restrict__ x, int i, int j,
-                                                   int z) {
-    const ProjArgs& p = a.g;
-    const size_t v = ((size_t)z * p.ny + j) * p.nx + i;
-    float acc[M], sens, xv[M], F[M];
-    osl_load<M>(a, Fm, x, v, xv, F);
-    gather<M>(sA, p, ratio, i, j, z, acc, sens);
-    osl_finish<M>(a, x, v, xv, F, acc, sens);
-}
-
 constexpr int kST = 16;                // staged voxel tile: kST x kST voxels, one per thread
 constexpr int kStageBytes = 20 * 1024;  // LDS for the staged bin records of one angle chunk
 
@@ -180,14 +118,14 @@ __host__ __device__ inline int stage_chunk(int M, int slots, int A_q) {
 // record of bin d holds mu_d y_d and, in its first padding float, mu_d (1 without a correction
 // sinogram).  All threads of the workgroup must call it (it synchronises).
 template <int M>
-__device__ __forceinline__ void staged_gather(const AngleRec* sA, const int2* sBB, float4* sR, const ProjArgs& p,
-                                              const float* __restrict__ y, int z, bool valid, int i, int j,
-                                              float (&acc)[M], float& sens) {
+__device__ __forceinline__ void staged_gather(const AngleRec* sA, const BinRange* sBB, float4* sR, const ProjArgs& p,
+                                              const float* __restrict__ y, int z, bool valid, int i, int j, int i0,
+                                              int j0, float (&acc)[M], float& sens) {
     const int slots = box_slots(kST, kST, p.h, p.du);
     const int chunk = stage_chunk(M, slots, p.A_q);
-    const float bc = 0.5f * (float)(p.n_bin - 1);
-    const float xc = ((float)i - 0.5f * (float)(p.nx - 1)) * p.h;
-    const float yc = ((float)j - 0.5f * (float)(p.ny - 1)) * p.h;
+    // the voxel's centre relative to the centre of the tile's corner pixel (exact small multiples)
+    const float dxc = (float)(i - i0) * p.h;
+    const float dyc = (float)(j - j0) * p.h;
     sens = 0.0f;
 #pragma unroll
     for (int m = 0; m < M; ++m) acc[m] = 0.0f;
@@ -197,9 +135,9 @@ __device__ __forceinline__ void staged_gather(const AngleRec* sA, const int2* sB
         __syncthreads();  // previous chunk consumed
         for (int rec = threadIdx.x; rec < na * slots; rec += blockDim.x) {
             const int ar = rec / slots, al = c0 + ar, slot = rec - ar * slots;
-            const int2 bb = sBB[al];
-            const int b = bb.x + slot;
-            if (b > bb.y) continue;
+            const BinRange bb = sBB[al];
+            const int b = bb.b0 + slot;
+            if (b > bb.b1) continue;
             const float4* src = yz + ((size_t)al * p.n_bin + b) * (M / 4);
             float4* dst = sR + rec * (stage_record(M) / 4);
             if (p.mult) {
@@ -221,20 +159,21 @@ __device__ __forceinline__ void staged_gather(const AngleRec* sA, const int2* sB
         for (int ac = 0; ac < na; ++ac) {
             const int al = c0 + ac;
             const AngleRec A = sA[al];
-            const int2 bb = sBB[al];
+            const BinRange bb = sBB[al];
             // the voxel's footprint as in pixel_footprint, clipped to the staged bins [b0, b1]
-            // (they hold every bin whose ray meets the tile, so the clip removes no chord)
-            const float tc = fmaf(xc, A.c, yc * A.s);
-            const float beta = fmaf(tc, p.inv_du, bc);
+            // (they hold every bin whose ray meets the tile, so the clip removes no chord); the
+            // distance from the voxel centre to ray b is t = t0 + (b - b0) du
+            const float t0 = bb.tb - fmaf(dxc, A.c, dyc * A.s);
+            const float beta = -t0 * p.inv_du;  // the voxel centre in bins from b0
             const float rb = A.w1 * p.inv_du;
-            const int lo = max((int)ceilf(beta - rb), bb.x);
-            const int hi = min((int)floorf(beta + rb), bb.y);
-            const float* rec = reinterpret_cast<const float*>(sR) + ((size_t)ac * slots + (lo - bb.x)) * stage_record(M);
-            float fb = (float)lo - bc;  // exact: integers and half-integers
+            const int lo = bb.b0 + max((int)ceilf(beta - rb), 0);
+            const int hi = min(bb.b0 + (int)floorf(beta + rb), bb.b1);
+            const float* rec = reinterpret_cast<const float*>(sR) + ((size_t)ac * slots + (lo - bb.b0)) * stage_record(M);
+            float fk = (float)(lo - bb.b0);
             // every lane holds the same angle, so the chord form is a uniform branch
             const bool oblique = __builtin_amdgcn_readfirstlane(A.axis) == 0;
-            for (int b = lo; b <= hi; ++b, fb += 1.0f, rec += stage_record(M)) {
-                const float t = fmaf(fb, p.du, -tc);
+            for (int b = lo; b <= hi; ++b, fk += 1.0f, rec += stage_record(M)) {
+                const float t = fmaf(fk, p.du, t0);
                 const float len = oblique ? chord_oblique(A, t) : chord_axis(A, t);
                 float v[M];
                 load_record<M>(rec, v);
@@ -273,11 +212,11 @@ __global__ __launch_bounds__(256) void kback_kernel(Src src) {
     const StagedTile t = staged_tile(w - J.w0, p.nx, p.ny, p.nz);
     if (t.z >= p.nz) return;  // whole workgroup
     AngleRec* sA = reinterpret_cast<AngleRec*>(lds);
-    int2* sBB = reinterpret_cast<int2*>(lds + (p.A_q * sizeof(AngleRec) + 15) / 16);
-    float4* sR = lds + (p.A_q * sizeof(AngleRec) + 15) / 16 + (p.A_q * sizeof(int2) + 15) / 16;
+    BinRange* sBB = reinterpret_cast<BinRange*>(lds + (p.A_q * sizeof(AngleRec) + 15) / 16);
+    float4* sR = lds + (p.A_q * sizeof(AngleRec) + 15) / 16 + (p.A_q * sizeof(BinRange) + 15) / 16;
     subset_angles_bins_to_lds(sA, sBB, p, t.i0, t.j0, min(kST, p.nx - t.i0), min(kST, p.ny - t.j0));
     float acc[M], sens;
-    staged_gather<M>(sA, sBB, sR, p, J.y, t.z, t.valid, t.i, t.j, acc, sens);
+    staged_gather<M>(sA, sBB, sR, p, J.y, t.z, t.valid, t.i, t.j, t.i0, t.j0, acc, sens);
     if (!t.valid) return;
     const size_t v = ((size_t)t.z * p.ny + t.j) * p.nx + t.i;
 #pragma unroll
@@ -296,18 +235,19 @@ __global__ __launch_bounds__(256) void kosl_kernel(Src src) {
     const StagedTile t = staged_tile(w - J.w0, p.nx, p.ny, p.nz);
     if (t.z >= p.nz) return;  // whole workgroup
     AngleRec* sA = reinterpret_cast<AngleRec*>(lds);
-    int2* sBB = reinterpret_cast<int2*>(lds + (p.A_q * sizeof(AngleRec) + 15) / 16);
-    float4* sR = lds + (p.A_q * sizeof(AngleRec) + 15) / 16 + (p.A_q * sizeof(int2) + 15) / 16;
+    BinRange* sBB = reinterpret_cast<BinRange*>(lds + (p.A_q * sizeof(AngleRec) + 15) / 16);
+    float4* sR = lds + (p.A_q * sizeof(AngleRec) + 15) / 16 + (p.A_q * sizeof(BinRange) + 15) / 16;
     subset_angles_bins_to_lds(sA, sBB, p, t.i0, t.j0, min(kST, p.nx - t.i0), min(kST, p.ny - t.j0));
     const size_t v = ((size_t)t.z * p.ny + t.j) * p.nx + t.i;
     float acc[M], sens, xv[M], F[M];
     if (t.valid) osl_load<M>(a, J.Fm, J.x, v, xv, F);
-    staged_gather<M>(sA, sBB, sR, p, J.ratio, t.z, t.valid, t.i, t.j, acc, sens);
+    staged_gather<M>(sA, sBB, sR, p, J.ratio, t.z, t.valid, t.i, t.j, t.i0, t.j0, acc, sens);
     if (t.valid) osl_finish<M>(a, J.x, v, xv, F, acc, sens);
 }
 
 static size_t staged_lds_bytes(int max_angles) {
-    return (max_angles * sizeof(AngleRec) + 15) / 16 * 16 + (max_angles * sizeof(int2) + 15) / 16 * 16 + kStageBytes;
+    return (max_angles * sizeof(AngleRec) + 15) / 16 * 16 + (max_angles * sizeof(BinRange) + 15) / 16 * 16 +
+           kStageBytes;
 }
 
 template <class K>

@@ -38,11 +38,10 @@ __host__ __device__ __forceinline__ void store_record(float* __restrict__ p, con
         reinterpret_cast<float4*>(p)[k] = make_float4(v[4 * k + 0], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
 }
 
-// Constants of projection angle a: t_a = ang0 + a pi / n_ang, cos and sin computed in FP64 and
-// snapped exactly at multiples of pi/2, then rounded to FP32.
-__host__ __device__ inline AngleRec make_angle(int a, int n_ang, double ang0, float h) {
+// cos and sin of projection angle a, t_a = ang0 + a pi / n_ang, in FP64, snapped exactly at
+// multiples of pi/2.
+__host__ __device__ inline void angle_cos_sin(int a, int n_ang, double ang0, double& c, double& s) {
     const double t = ang0 + (double)a * 3.141592653589793 / (double)n_ang;
-    double s, c;
     sincos(t, &s, &c);
     if (fabs(c) < 1e-12) {
         c = 0.0;
@@ -52,6 +51,10 @@ __host__ __device__ inline AngleRec make_angle(int a, int n_ang, double ang0, fl
         s = 0.0;
         c = c > 0.0 ? 1.0 : -1.0;
     }
+}
+
+// Constants of a projection angle from its FP64 cos and sin (rounded to FP32).
+__host__ __device__ inline AngleRec make_angle_cs(double c, double s, float h) {
     const double ac = fabs(c), as = fabs(s), hd = (double)h;
     AngleRec A;
     A.c = (float)c;
@@ -63,6 +66,13 @@ __host__ __device__ inline AngleRec make_angle(int a, int n_ang, double ang0, fl
     A.axis = s == 0.0 ? 1 : (c == 0.0 ? 2 : 0);
     A.inv_dw = A.axis == 0 ? (float)(1.0 / (hd * fmin(ac, as))) : 0.0f;
     return A;
+}
+
+// Constants of projection angle a.
+__host__ __device__ inline AngleRec make_angle(int a, int n_ang, double ang0, float h) {
+    double s, c;
+    angle_cos_sin(a, n_ang, ang0, c, s);
+    return make_angle_cs(c, s, h);
 }
 
 // 1 / b from the hardware reciprocal (1 ulp) for normal positive b; exact on the host.
@@ -95,8 +105,8 @@ __host__ __device__ __forceinline__ float pixel_chord(const AngleRec& A, float t
 
 // Incremental Siddon traversal of a ray through an nx x ny box of pixels: calls
 // visit(j * row + i * col, len) for every pixel (i, j) the ray crosses, in order, with the exact
-// intersection length (mm).  Coordinates are in pixel units relative to the box corner; (Xc, Yc) is the ray's foot
-// point and the point at parameter lam (pixel units of length) is (Xc - lam s, Yc + lam c).  The
+// intersection length (mm).  Coordinates are in pixel units relative to the box corner; (Xc, Yc) is a point
+// of the ray and the point at parameter lam (pixel units of length) is (Xc - lam s, Yc + lam c).  The
 // crossing parameters are re-derived from the grid-line index at each step, so the rounding
 // error does not accumulate along the ray.  At most nx + ny + 2 steps.
 template <class Visit>
@@ -169,15 +179,6 @@ __host__ __device__ __forceinline__ void siddon_traverse_box(const AngleRec& A, 
     }
 }
 
-// Ray (A, u) through the whole nx x ny grid of h-pixels centred on the origin.
-template <class Visit>
-__host__ __device__ __forceinline__ void siddon_traverse(const AngleRec& A, float u, int nx, int ny, float h,
-                                                         float inv_h, int row, int col, Visit&& visit) {
-    const float Xc = u * A.c * inv_h + 0.5f * (float)nx;
-    const float Yc = u * A.s * inv_h + 0.5f * (float)ny;
-    siddon_traverse_box(A, Xc, Yc, nx, ny, h, row, col, visit);
-}
-
 // Slots reserved per (tile, angle) for the bins whose rays can meet a T x T pixel tile:
 // b1 - b0 <= T h sqrt(2) / du + 0.02 for every angle (see box_bins).
 __host__ __device__ inline int tile_slots(int T, float h, float du) {
@@ -197,23 +198,6 @@ __host__ __device__ __forceinline__ void box_bins(const AngleRec& A, int i0, int
     const float bc = 0.5f * (float)(n_bin - 1);
     b0 = max((int)ceilf(fmaf(umin, inv_du, bc) - 0.01f), 0);
     b1 = min((int)floorf(fmaf(umax, inv_du, bc) + 0.01f), n_bin - 1);
-}
-
-// Bins whose rays cross the pixel centred at (xc, yc): calls visit(b, len) with the chord.
-// The footprint of a pixel on the detector is |t| < w1 around the centre's projection.
-template <class Visit>
-__host__ __device__ __forceinline__ void pixel_footprint(const AngleRec& A, float xc, float yc, int n_bin, float du,
-                                                         float inv_du, Visit&& visit) {
-    const float bc = 0.5f * (float)(n_bin - 1);
-    const float tc = fmaf(xc, A.c, yc * A.s);  // pixel centre on the detector axis
-    const float beta = fmaf(tc, inv_du, bc);    // ... in bin units
-    const float rb = A.w1 * inv_du;
-    const int b0 = max((int)ceilf(beta - rb), 0);
-    const int b1 = min((int)floorf(beta + rb), n_bin - 1);
-    for (int b = b0; b <= b1; ++b) {
-        const float len = pixel_chord(A, fmaf((float)b - bc, du, -tc));
-        if (len > 0.0f) visit(b, len);
-    }
 }
 
 }  // namespace kcs

@@ -12,6 +12,7 @@ struct ProjArgs {
     int32_t rays_per_plane;   // A_q * n_bin
     float h, inv_h, du, inv_du;
     double ang0;
+    double hd, dud;  // pixel side and bin width in FP64 (ray positions relative to tiles)
     const float* mult;  // [nz][n_ang][n_bin] multiplicative correction per ray, or NULL (ones)
     FrameTab fr;
 };
@@ -139,7 +140,6 @@ struct JobTable {
 // Workgroups each job needs.
 uint32_t proj_direct_groups(const ProjArgs& p);
 uint32_t proj_tile_groups(const ProjArgs& p, int T);
-uint32_t voxel_tile_groups(int nx, int ny, int nz);
 uint32_t staged_tile_groups(int nx, int ny, int nz);
 bool staged_fits(int M, float h, float du);  // one angle's staged bin records fit in the LDS
 uint32_t lm_groups(int nx, int ny, int nz);
@@ -167,6 +167,11 @@ hipError_t launch_osl(int M, const float* ratio, const float* Fm, float* x, cons
 hipError_t launch_lm(int M, const KinTab* K, const float* x, const float* xi_in, float* xi_out, float* lam,
                      float* state, const LmArgs& a, hipStream_t st);
 hipError_t launch_ki(const float* params, int64_t n, float* ki, hipStream_t st);
+
+// Streaming read (kind 0: one partial sum per thread into dst, stream_read_out_floats(groups)
+// floats) or copy (kind 1) of bytes (a multiple of 16) for bandwidth measurement.
+size_t stream_read_out_floats(int groups);
+hipError_t launch_stream(int kind, const void* src, void* dst, size_t bytes, int groups, hipStream_t st);
 hipError_t launch_model(int M, const KinTab* K, const FrameTab& fr, const float* params, int64_t n, float* F, float* J,
                         hipStream_t st);
 hipError_t launch_init(int M, const float* sino, int64_t rows, const FrameTab& fr, double denom_scale, int32_t nz_ny_nx,

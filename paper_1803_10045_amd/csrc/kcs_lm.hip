@@ -12,7 +12,7 @@
 // accepted, and those at the current maps stay valid when it is rejected.  A fit therefore
 // carries J^T J, J^T r and r^T r from one iteration to the next in a per-voxel state buffer: its
 // first iteration evaluates the model twice (with the Jacobian at the current and the trial
-// maps), the middle ones once with the Jacobian, the last one once without.
+// maps), the others once (with the Jacobian, at the trial maps).
 #include "kcs_device.h"
 #include "kcs_launch.h"
 #include "kcs_model.h"
@@ -167,16 +167,11 @@ __host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, 
     float unused[3];
     const float e1 = neighbour_energy<NBR3D>(xi_in, a, i, j, z, N, q0, q1, q2, unused);
 
-    // data term at the trial parameters (with the normal equations when the next iteration needs them)
-    Normal n1{};
-    if (a.need_state) {
-        n1 = normal_equations<M>(a.fr, *K, xv, q0, q1, q2);
-    } else {
-        model_frames<M, false, false>(a.fr, *K, q0, q1, q2, [&](int m, float F, float, float, float) {
-            const float r = xv[m] - F;
-            n1.rr = fmaf(r, r, n1.rr);
-        });
-    }
+    // data term at the trial parameters, with its normal equations (the next iteration's when
+    // the step is kept).  The last iteration of a fit needs only r'^T r', but evaluating it the
+    // same way in every iteration makes a fit of n iterations round exactly like n calls of one
+    // iteration each, whatever the call pattern.
+    const Normal n1 = normal_equations<M>(a.fr, *K, xv, q0, q1, q2);
     const float dphi = fmaf(a.beta_h, e1 - e0, 0.5f * (n1.rr - n0.rr));
     const float phi0 = fmaf(a.beta_h, e0, 0.5f * n0.rr);
     const bool accept = dphi < -a.eta * phi0;

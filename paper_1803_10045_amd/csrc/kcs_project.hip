@@ -23,6 +23,20 @@
 
 namespace kcs {
 
+// A point of ray (FP64 cos c, sin s of its angle; bin b0) near the centre (cx, cy) of a pixel box whose corner is pixel
+// (i0, j0), in pixel units relative to that corner, computed in FP64 and rounded to FP32.  The
+// ray's position is known to the FP64 rounding of the geometry, and near the box the FP32 point
+// carries an error of the order of ulp(box size) instead of ulp(distance to the image centre):
+// the corner chords of pixels far from the centre then keep their FP64 lengths to ~1e-6 pixel.
+__host__ __device__ inline float2 ray_point_near(double c, double s, int b0, const ProjArgs& p, int i0, int j0,
+                                                 double cx, double cy) {
+    const double u = ((double)b0 - 0.5 * (double)(p.n_bin - 1)) * p.dud / p.hd;  // pixel units
+    const double X = u * c + 0.5 * (double)p.nx - (double)i0;  // foot point of the ray's normal
+    const double Y = u * s + 0.5 * (double)p.ny - (double)j0;
+    const double lam = (cx - X) * -s + (cy - Y) * c;  // along the ray direction (-s, c)
+    return make_float2((float)(X - lam * s), (float)(Y + lam * c));
+}
+
 // Expected counts or measured/expected ratio of ray (z, al, b) from its line integrals acc:
 // ybar_m = E_m mu acc_m + r_m, mu the ray's multiplicative correction (1 without one).
 template <int M, bool RATIO>
@@ -54,13 +68,16 @@ template <int M, bool RATIO>
 __host__ __device__ __forceinline__ void project_ray(const ProjArgs& p, const float* __restrict__ x,
                                                      const float* __restrict__ sino, float* __restrict__ out, int z,
                                                      int al, int b) {
-    const AngleRec A = make_angle(p.q + al * p.Q, p.n_ang, p.ang0, p.h);
+    double c, s;
+    angle_cos_sin(p.q + al * p.Q, p.n_ang, p.ang0, c, s);
+    const AngleRec A = make_angle_cs(c, s, p.h);
     float acc[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) acc[m] = 0.0f;
-    const float u = ((float)b - 0.5f * (float)(p.n_bin - 1)) * p.du;
+    // the ray's point nearest the image centre, in pixel units from the image corner
+    const float2 pt = ray_point_near(c, s, b, p, 0, 0, 0.5 * p.nx, 0.5 * p.ny);
     const float* plane = x + (size_t)z * p.nx * p.ny * M;
-    siddon_traverse(A, u, p.nx, p.ny, p.h, p.inv_h, p.nx * M, M, [&](int idx, float len) {
+    siddon_traverse_box(A, pt.x, pt.y, p.nx, p.ny, p.h, p.nx * M, M, [&](int idx, float len) {
         float v[M];
         load_record<M>(plane + idx, v);
 #pragma unroll
@@ -148,6 +165,14 @@ __host__ __device__ __forceinline__ size_t partial_offset(int g, size_t n_tiles,
     return ((((size_t)g * n_tiles + tile) * A_q + al) * slots + slot) * FG;
 }
 
+// Per-angle LDS table of the tile kernel: the angle's constants, the bins [b0, b1] whose rays
+// can meet the tile, and a point of ray b0 near the tile centre (see ray_point_near).
+struct TileAngle {
+    AngleRec A;
+    int32_t b0, b1;
+    float px, py;
+};
+
 template <int M, int T, class Src>
 __global__ __launch_bounds__(tile_threads(T)) void kproj_tile_kernel(Src src) {
     constexpr int FG = tile_frames(M, T), NG = M / FG, NT = tile_threads(T), TS = tile_row(M, T);
@@ -158,7 +183,7 @@ __global__ __launch_bounds__(tile_threads(T)) void kproj_tile_kernel(Src src) {
     const ProjArgs& p = J.p;
     const int slots = J.slots;
     float* tile = reinterpret_cast<float*>(lds4);
-    AngleRec* sA = reinterpret_cast<AngleRec*>(lds4 + T * TS / 4);
+    TileAngle* sT = reinterpret_cast<TileAngle*>(lds4 + T * TS / 4);
     const int ntx = (p.nx + T - 1) / T, nty = (p.ny + T - 1) / T;
     const uint32_t lw = w - J.w0;
     const int g = (int)(lw % NG);
@@ -175,28 +200,37 @@ __global__ __launch_bounds__(tile_threads(T)) void kproj_tile_kernel(Src src) {
         load_frames<FG>(src_px + ((size_t)r * p.nx + c) * M, v);
         store_frames<FG>(tile + r * TS + c * FG, v);
     }
-    for (int al = threadIdx.x; al < p.A_q; al += NT) sA[al] = make_angle(p.q + al * p.Q, p.n_ang, p.ang0, p.h);
+    for (int al = threadIdx.x; al < p.A_q; al += NT) {
+        TileAngle t;
+        double c, s;
+        angle_cos_sin(p.q + al * p.Q, p.n_ang, p.ang0, c, s);
+        t.A = make_angle_cs(c, s, p.h);
+        box_bins(t.A, i0, j0, tw, th, p.nx, p.ny, p.h, p.inv_du, p.n_bin, t.b0, t.b1);
+        const float2 pt = ray_point_near(c, s, t.b0, p, i0, j0, 0.5 * tw, 0.5 * th);
+        t.px = pt.x;
+        t.py = pt.y;
+        sT[al] = t;
+    }
     __syncthreads();
-    const float bc = 0.5f * (float)(p.n_bin - 1);
     const size_t n_tiles = (size_t)p.nz * nty * ntx;
     float* out = J.psum + partial_offset(g, n_tiles, (size_t)z * nty * ntx + tr, p.A_q, 0, slots, 0, FG);
+    const float bin_step = p.du * p.inv_h;  // bin width in pixel units
+    // Work items: one ray segment each, angle-major (a wave's lanes share an angle and walk
+    // parallel rays through the tile).
     for (int it = threadIdx.x; it < p.A_q * slots; it += NT) {
         const int al = it / slots, slot = it - al * slots;
-        const AngleRec A = sA[al];
-        int b0, b1;
-        box_bins(A, i0, j0, tw, th, p.nx, p.ny, p.h, p.inv_du, p.n_bin, b0, b1);
-        const int b = b0 + slot;
-        if (b > b1) continue;
+        const TileAngle ta = sT[al];
+        if (ta.b0 + slot > ta.b1) continue;
         float acc[FG];
 #pragma unroll
         for (int m = 0; m < FG; ++m) acc[m] = 0.0f;
-        const float u = ((float)b - bc) * p.du;
-        const float Xc = u * A.c * p.inv_h + 0.5f * (float)p.nx - (float)i0;
-        const float Yc = u * A.s * p.inv_h + 0.5f * (float)p.ny - (float)j0;
+        // a point of ray b0 + slot: ray b0's point moved `slot` bins along the detector normal
+        const float off = (float)slot * bin_step;
+        const float Xc = fmaf(off, ta.A.c, ta.px), Yc = fmaf(off, ta.A.s, ta.py);
         // pixel offsets in bytes, so that the LDS address needs no scaling per crossing
-        siddon_traverse_box(A, Xc, Yc, tw, th, p.h, TS * 4, FG * 4, [&](int off, float len) {
+        siddon_traverse_box(ta.A, Xc, Yc, tw, th, p.h, TS * 4, FG * 4, [&](int o, float len) {
             float v[FG];
-            load_frames<FG>(reinterpret_cast<const float*>(reinterpret_cast<const char*>(tile) + off), v);
+            load_frames<FG>(reinterpret_cast<const float*>(reinterpret_cast<const char*>(tile) + o), v);
 #pragma unroll
             for (int m = 0; m < FG; ++m) acc[m] = fmaf(len, v[m], acc[m]);
         });
@@ -274,7 +308,7 @@ static hipError_t launch_tile(Src src, uint32_t groups, int max_angles, hipStrea
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr_set = true;
     }
-    const size_t lds = (size_t)T * tile_row(M, T) * sizeof(float) + (size_t)max_angles * sizeof(AngleRec);
+    const size_t lds = (size_t)T * tile_row(M, T) * sizeof(float) + (size_t)max_angles * sizeof(TileAngle);
     hipLaunchKernelGGL((kproj_tile_kernel<M, T, Src>), dim3(xcd_round_up(groups)), dim3(tile_threads(T)), lds, st, src);
     return hipGetLastError();
 }

@@ -23,7 +23,7 @@ ENTRY_POINTS = ("kcs_workspace_bytes", "kcs_study_footprint_bytes", "kcs_project
                 "kcs_model_tac", "kcs_ki_map", "kcs_osl_update", "kcs_lm_fit", "kcs_init_state", "kcs_icm_sweep",
                 "kcs_icm_sweep_noalloc",
                 "kcs_plan_create", "kcs_plan_run", "kcs_plan_describe", "kcs_plan_destroy",
-                "kcs_timing_enable", "kcs_timing_collect", "kcs_last_error")
+                "kcs_timing_enable", "kcs_timing_collect", "kcs_stream_probe", "kcs_last_error")
 
 KCS_PLAN_GRAPH, KCS_PLAN_AUTOTUNE = 1, 2
 
@@ -111,6 +111,8 @@ def lib() -> ctypes.CDLL:
     L.kcs_timing_enable.restype = ctypes.c_int
     L.kcs_timing_collect.argtypes = [P(ctypes.c_double), P(ctypes.c_int64)]
     L.kcs_timing_collect.restype = ctypes.c_int
+    L.kcs_stream_probe.argtypes = [i32, vp, vp, sz, i32, vp]
+    L.kcs_stream_probe.restype = ctypes.c_int
     L.kcs_last_error.argtypes = []
     L.kcs_last_error.restype = ctypes.c_char_p
     return L
@@ -427,6 +429,24 @@ def kcs_timing_collect() -> dict:
     cnt = (ctypes.c_int64 * n)()
     _check(lib().kcs_timing_collect(ms, cnt))
     return {k: (ms[i], int(cnt[i])) for i, k in enumerate(TIMING_KINDS)}
+
+
+def kcs_stream_probe(kind: int, src, dst, groups: int, stream=None):
+    """Bandwidth probe: kind 0 reads all of src (uint8/float device tensor) into one partial sum
+    per thread in dst (float32, groups * 256); kind 1 copies src into dst (same byte size)."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    if kind == 0:
+        need = groups * 256
+        if dst.dtype != torch.float32 or dst.numel() < need:
+            raise ValueError(f"dst must hold {need} float32")
+    elif dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst is smaller than src")
+    for t in (src, dst):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("src and dst must be contiguous device tensors")
+    _check(lib().kcs_stream_probe(kind, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nbytes,
+                                  groups, _stream(stream)))
 
 
 def kcs_last_error() -> str:

@@ -1,4 +1,6 @@
 """Helpers shared by the GPU parity tests: oracle study -> binding objects and device tensors."""
+import dataclasses
+
 import numpy as np
 
 import oracle
@@ -45,3 +47,114 @@ def default_frames(M=24, seed=0):
     E = (t1 - t0) * rng.uniform(0.5, 2.0)
     r = rng.uniform(0.01, 0.3, M)
     return oracle.Frames(t0, t1, E, r)
+
+
+# ---------------------------------------------------------------------------------------------
+# MAP-LM decisions of whole ICM schedules.  The accept test compares Phi(xi') - Phi(xi) with
+# -eta Phi(xi); the FP32 kernel evaluates both objectives with the FP32 model, whose relative L2
+# error over the frames is at most E_F inside the parameter box (asserted by the model parity
+# test), and sums 24 squares in FP32.  Writing r = x - F and r' = x - F' for the data residuals,
+#   |dPhi_fp32 - dPhi_exact| <= E_F (||F|| ||r|| + ||F'|| ||r'||) + M u (||r||^2 + ||r'||^2)
+# (first order in E_F; u = 2^-24), with ||F|| <= ||x|| + ||r|| and ||r||^2 <= 2 Phi since the
+# Huber energy is >= 0.  A decision whose exact margin |dPhi + eta Phi| exceeds this bound is
+# resolved in FP32 and must agree with the oracle's.
+E_F = 5e-6
+U32 = 2.0 ** -24
+
+
+def decision_bound(x, phi0, phi1):
+    """FP32 evaluation bound of the accept test per voxel; x (..., M), phi0/phi1 (...)."""
+    M = x.shape[-1]
+    xn = np.linalg.norm(x, axis=-1)
+    r0 = np.sqrt(2.0 * np.maximum(phi0, 0.0))
+    r1 = np.sqrt(2.0 * np.maximum(phi1, 0.0))
+    return E_F * ((xn + r0) * r0 + (xn + r1) * r1) + 2.0 * M * U32 * (phi0 + phi1)
+
+
+def oracle_decisions(st, opt, x, params, lam):
+    """One oracle MAP-LM iteration on (x, params, lam) with its decisions: returns the new maps and
+    lambda, accept (bool), phi0, phi1 and the damping the iteration started from (lambda <= 0
+    replaced by its initial value tau max diag(J^T J))."""
+    p1, l1, phi0, phi1 = oracle.lm_iteration(st.frames, st.kin, st.prior, opt, x, params, lam, with_objective=True)
+    acc = (phi1 - phi0) < -opt.eta * phi0
+    used = np.where(lam > 0, lam, np.where(acc, l1 * 10.0, l1 / 10.0))
+    return p1, l1, acc, phi0, phi1, used
+
+
+def gpu_accepted(l0, l1, used, lam_min):
+    """Accept decisions of a GPU iteration from its damping before (l0, 0 = initialise) and after
+    (l1): accept divides lambda by 10 (floor lam_min), reject multiplies it by 10.  `used` is the
+    damping the decision started from when l0 = 0 (the FP64 initial value; the FP32 one agrees
+    with it to far better than a factor of 10)."""
+    ref = np.where(l0 > 0, l0, used)
+    return (l1 < ref * 0.5) | ((l1 <= ref * 1.0001) & (ref <= lam_min * 1.0001))
+
+
+def oracle_schedule_vs_gpu(st, n_sweeps, eta, gpu_lam, gpu_x, state=None):
+    """The oracle's own ICM schedule of study `st` (from its initial state, lambda restarted every
+    sweep), compared decision by decision with a GPU run of the same schedule.  gpu_lam
+    (n_sweeps * n_iter, ...) holds the GPU's damping after every LM iteration and gpu_x
+    (n_sweeps, ...) its image after every sweep (the LM input of that sweep).  For every voxel the
+    first iteration whose decisions differ is found, with the oracle's margin there and the
+    bound of decision_bound widened by the difference of the two states' images,
+    (||r|| + ||r'||) ||x_gpu - x_oracle|| (first order in that difference).  Returns the oracle's final
+    (x, params, lam) and the arrays first (-1: never), margin, bound, inherited (the first
+    differing decision came after a neighbour's: see neighbour_diverged).  `state`: the initial
+    (x, params, lam) when it is not the oracle's initial state of `st` itself."""
+    opt = dataclasses.replace(st.lm, eta=eta, n_iter=1)
+    sino = st.sino.astype(np.float64)
+    x, p, lam = oracle.initial_state(st.geom, st.frames, sino) if state is None else state
+    n_it = st.lm.n_iter
+    first = np.full(lam.shape, -1)
+    inherited = np.zeros(lam.shape, dtype=bool)
+    margin = np.full(lam.shape, np.nan)
+    bound = np.full(lam.shape, np.nan)
+    for s in range(n_sweeps):
+        kp = st.prior.kp_on and s > 0
+        F = oracle.model_tac(p.reshape(3, -1).T, st.frames.t0, st.frames.t1, st.kin).reshape(x.shape) if kp else None
+        for q in range(st.cfg.Q):
+            x = oracle.osl_update(st.geom, st.frames, st.kin, st.prior, sino, p, x, q, st.cfg.Q, kp, None, F)
+        dx = np.linalg.norm(np.asarray(gpu_x[s], dtype=np.float64) - x, axis=-1)
+        lam = np.zeros_like(lam)
+        gl0 = np.zeros_like(lam)
+        for it in range(n_it):
+            k = s * n_it + it
+            p, l1, acc, phi0, phi1, used = oracle_decisions(st, opt, x, p, lam)
+            gl1 = np.asarray(gpu_lam[k], dtype=np.float64)
+            differ = (gpu_accepted(gl0, gl1, used, opt.lam_min) != acc) & (first < 0)
+            # a voxel whose neighbour already took another path reads other neighbour maps in its
+            # Huber terms: its divergence is inherited, not a near-tie of its own
+            inherited[differ] = neighbour_diverged(first, opt_nbr3d=st.prior.plane_ratio > 0)[differ]
+            first[differ] = k
+            margin[differ] = np.abs(phi1 - phi0 + eta * phi0)[differ]
+            r0, r1 = np.sqrt(2.0 * phi0), np.sqrt(2.0 * np.maximum(phi1, 0.0))
+            bound[differ] = (decision_bound(x, phi0, phi1) + (r0 + r1) * dx)[differ]
+            lam, gl0 = l1, gl1
+    return x, p, lam, first, margin, bound, inherited
+
+
+def neighbour_diverged(first, opt_nbr3d=False):
+    """Voxels with a neighbour (in-plane 8, or 26 with the 3x3x3 prior) that took another path at
+    an earlier iteration than now (first >= 0)."""
+    d = first >= 0
+    out = np.zeros_like(d)
+    nz, ny, nx = d.shape
+    dzs = (-1, 0, 1) if opt_nbr3d else (0,)
+    for dz in dzs:
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if dz == dy == dx == 0:
+                    continue
+                src = d[max(dz, 0):nz + min(dz, 0), max(dy, 0):ny + min(dy, 0), max(dx, 0):nx + min(dx, 0)]
+                out[max(-dz, 0):nz + min(-dz, 0), max(-dy, 0):ny + min(-dy, 0), max(-dx, 0):nx + min(-dx, 0)] |= src
+    return out
+
+
+def oracle_schedule_worker(args):
+    """Process-pool entry point of oracle_schedule_vs_gpu (results rounded to FP32 for the trip
+    back); sets the oracle's OpenMP thread count before its library loads."""
+    import os
+    st, n_sweeps, eta, gpu_lam, gpu_x, state, threads = args
+    os.environ["OMP_NUM_THREADS"] = str(threads)
+    x, p, lam, first, margin, bound, inherited = oracle_schedule_vs_gpu(st, n_sweeps, eta, gpu_lam, gpu_x, state)
+    return x.astype(np.float32), p, lam, first, margin, bound, inherited

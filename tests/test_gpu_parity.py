@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 from paper_1803_10045_amd import inputs
-from kcs_testutil import default_frames, geometry_pair, kcs_objects, rel_l2, make_image
+from kcs_testutil import decision_bound, default_frames, geometry_pair, kcs_objects, rel_l2, make_image
 
 torch = pytest.importorskip("torch")
 from paper_1803_10045_amd import kcs  # noqa: E402
@@ -188,8 +188,12 @@ def test_osl_update_parity(kp):
         assert err < 1e-5
 
 
-def test_lm_fit_parity():
+@pytest.mark.parametrize("eta", [inputs.LM_ETA, 0.0])
+def test_lm_fit_parity(eta):
+    """A 5-iteration fit of the 64x64 slice from the initial maps, with the relative sufficient
+    decrease (eta = 1e-3) and with the plain strict decrease (eta = 0)."""
     st = disk64_study()
+    st = dataclasses.replace(st, lm=dataclasses.replace(st.lm, eta=eta))
     g, f, k, p, lm = kcs_objects(st)
     rng = np.random.default_rng(6)
     x = st.truth_x * (1 + 0.05 * rng.standard_normal(st.truth_x.shape))
@@ -209,10 +213,14 @@ def test_lm_fit_parity():
     keep = mask & same
     for i in range(3):
         e = rel_l2(gp[i][keep], op[i][keep])
-        print(f"lm param {i}: relL2 over object voxels with the oracle's LM path {e:.2e} "
+        print(f"eta={eta} lm param {i}: relL2 over object voxels with the oracle's LM path {e:.2e} "
               f"(all object voxels {rel_l2(gp[i][mask], op[i][mask]):.2e}; other path {int((mask & ~same).sum())})")
         assert e < 1e-4
-    assert same[mask].mean() > 0.99
+    # under the strict decrease a voxel at its optimum ties every iteration (dPhi = 0 to FP32
+    # resolution), so many voxels take the other branch somewhere in the fit; their decisions are
+    # checked one by one against the FP32 bound in test_gpu_schedule.py
+    if eta > 0:
+        assert same[mask].mean() > 0.99
 
 
 def test_lm_fit_parity_3x3x3_neighbourhood():
@@ -243,79 +251,6 @@ def test_lm_fit_parity_3x3x3_neighbourhood():
               f"({int((st.mask & ~same).sum())} of {int(st.mask.sum())} on another)")
         assert e < 1e-4
     assert same[st.mask].mean() > 0.99
-
-
-def compare_icm(gx, gp, glam, ox, op, olam, frames, label, tol_img=1e-3, tol_maps=1e-3):
-    """Whole-schedule comparison: relative L2 of the image over all voxels and of each map over the
-    voxels above 10 % of peak activity.  Also reports how many voxels took a different MAP-LM
-    accept/reject path (their final lambda differs by a power of 10)."""
-    ex = rel_l2(gx, ox)
-    act = (ox * (frames.t1 - frames.t0)).sum(axis=-1)
-    mask = act >= 0.1 * act.max()
-    same = np.abs(glam / olam - 1.0) < 1e-3
-    maps = [rel_l2(gp[i][mask], op[i][mask]) for i in range(3)]
-    print(f"{label}: image relL2 {ex:.2e}; maps over active voxels {['%.2e' % e for e in maps]}; "
-          f"voxels with a different LM path {int((~same & mask).sum())} of {int(mask.sum())}")
-    assert ex < tol_img
-    assert max(maps) < tol_maps
-
-
-def test_icm_full_schedule_disk64():
-    """The whole 64x64 schedule (10 sweeps x (4 subsets + 5 LM)) from the same initial state: the
-    image over all voxels, the maps over the active voxels whose accept/reject path matched the
-    oracle's in every sweep (at most 2 % of them on another path)."""
-    st = disk64_study()
-    gx, gp, ox, op, diverged = run_schedule_tracking_decisions(st, st.cfg.n_sweeps)
-    act = (ox * (st.frames.t1 - st.frames.t0)).sum(axis=-1)
-    mask = act >= 0.1 * act.max()
-    keep = mask & ~diverged
-    ex = rel_l2(gx, ox)
-    all_maps = [rel_l2(gp[i][mask], op[i][mask]) for i in range(3)]
-    kept = [rel_l2(gp[i][keep], op[i][keep]) for i in range(3)]
-    frac = diverged[mask].mean()
-    print(f"64x64 ICM: image relL2 {ex:.2e}; maps over active voxels {['%.2e' % e for e in all_maps]}; over "
-          f"decision-consistent voxels {['%.2e' % e for e in kept]}; {int((diverged & mask).sum())} of "
-          f"{int(mask.sum())} active voxels on another LM path")
-    assert ex < 1e-3
-    assert frac < 0.02
-    assert max(kept) < 1e-3
-
-
-def run_tiled_plane(cfg_full, n_sweeps, n_distinct=1):
-    """GPU run at the full size of cfg_full whose sinogram repeats the oracle-synthesised planes of
-    `n_distinct` single-plane studies (seeds 1..n_distinct); returns the GPU state, the plane
-    studies and the repetition index of every plane."""
-    planes = [oracle.make_study(inputs.scaled(cfg_full, nz=1, seed=1 + i)) for i in range(n_distinct)]
-    st0 = planes[0]
-    nz = cfg_full.nz
-    which = np.arange(nz) % n_distinct
-    sino = np.concatenate([planes[w].sino for w in which], axis=0)
-    g = kcs.Geometry.from_config(cfg_full)
-    _, f, k, p, lm = kcs_objects(st0)  # scales and background of the single-plane study
-    sd = dev(sino)
-    x = torch.empty((g.nz, g.ny, g.nx, M), device=DEV)
-    params = torch.empty((3, g.nz, g.ny, g.nx), device=DEV)
-    lam = torch.empty((g.nz, g.ny, g.nx), device=DEV)
-    work = kcs.alloc_workspace(g, M, cfg_full.Q, DEV)
-    kcs.kcs_init_state(g, f, sd, inputs.XI0, x, params, lam, work)
-    for s in range(n_sweeps):
-        kcs.kcs_icm_sweep(g, f, k, p, lm, sd, cfg_full.Q, s, x, params, lam, work)
-    torch.cuda.synchronize()
-    return x.cpu().numpy(), params.cpu().numpy(), lam.cpu().numpy(), planes, which
-
-
-@pytest.mark.parametrize("cfg_name,n_sweeps", [("brain128", 3), ("brain344", 1)])
-def test_icm_full_size_sampled_planes(cfg_name, n_sweeps):
-    """Full-size study in the benchmark's launch configuration; planes are independent, so each
-    sampled plane is checked against the oracle run on that plane alone, and planes with the
-    same input must come out bit-identical."""
-    cfg = inputs.CONFIGS[cfg_name]()
-    gx, gp, gl, planes, which = run_tiled_plane(cfg, n_sweeps)
-    st = planes[0]
-    for zz in range(1, cfg.nz):
-        assert np.array_equal(gx[zz], gx[0]) and np.array_equal(gp[:, zz], gp[:, 0])
-    ox, op, ol = oracle.icm(st.geom, st.frames, st.kin, st.prior, st.lm, st.sino.astype(np.float64), cfg.Q, n_sweeps)
-    compare_icm(gx[:1], gp[:, :1], gl[:1], ox, op, ol, st.frames, f"{cfg_name} full size, plane 0, {n_sweeps} sweeps")
 
 
 @pytest.mark.parametrize("tile", ["0", "16", "32", "64"])
@@ -349,10 +284,8 @@ def test_osl_update_projector_variants(tile, monkeypatch):
 # ---------------------------------------------------------------------------------------------
 # MAP-LM accept decisions.  The accept test compares the change of the voxel objective with a
 # fraction eta of it; where the two lie within the FP32 evaluation error of each other either
-# branch is a result of the method, and the voxel then follows another (equally valid) path.
-# The checks below (a) pin every decision that differs from the oracle's to such a near-tie and
-# (b) compare whole schedules over the voxels whose decisions agreed in every sweep, bounding
-# how many did not.
+# branch is a result of the method.  Every decision that differs from the oracle's on the same
+# state must be such a near-tie (whole schedules: test_gpu_schedule.py).
 
 def low_count_plane_state(n_iter_before=3):
     """A mid-fit MAP-LM state on a low-count 128x128 plane (the batch recipe's counts per plane):
@@ -384,58 +317,14 @@ def test_lm_decisions_differ_only_at_near_ties():
     o_acc = ol < lam
     differ = g_acc != o_acc
     eta = st.lm.eta
-    margin = np.abs(phi1 - phi0 + eta * phi0) / (eta * phi0)
+    ratio = np.abs(phi1 - phi0 + eta * phi0) / decision_bound(x, phi0, phi1)
     print(f"one LM iteration on {x.shape[1]}x{x.shape[2]}: {int(differ.sum())} of {differ.size} decisions differ; "
-          f"their oracle margins {np.sort(margin[differ])[:10]}")
+          f"their oracle margins in units of the FP32 bound {np.sort(ratio[differ])[:10]}")
     assert differ.mean() < 1e-3
-    assert np.all(margin[differ] < 2e-2)
+    assert np.all(ratio[differ] <= 1.0)
     gp = pd.cpu().numpy()
     same = ~differ
     for i in range(3):
         e = rel_l2(gp[i][same], op[i][same])
         print(f"  map {i} over voxels with the same decision: relL2 {e:.2e}")
         assert e < 1e-4
-
-
-def run_schedule_tracking_decisions(st, n_sweeps):
-    """Both sides sweep by sweep from their own initial states; a voxel whose final lambda of a
-    sweep differs from the oracle's took another accept/reject path in that sweep."""
-    cfg = st.cfg
-    g, f, k, p, lm = kcs_objects(st)
-    sino_d = dev(st.sino)
-    x = torch.empty((g.nz, g.ny, g.nx, M), device=DEV)
-    params = torch.empty((3, g.nz, g.ny, g.nx), device=DEV)
-    lamd = torch.empty((g.nz, g.ny, g.nx), device=DEV)
-    work = kcs.alloc_workspace(g, M, cfg.Q, DEV)
-    kcs.kcs_init_state(g, f, sino_d, inputs.XI0, x, params, lamd, work)
-    sino = st.sino.astype(np.float64)
-    ox, op, ol = oracle.initial_state(st.geom, st.frames, sino)
-    diverged = np.zeros(ol.shape, dtype=bool)
-    for s in range(n_sweeps):
-        kcs.kcs_icm_sweep(g, f, k, p, lm, sino_d, cfg.Q, s, x, params, lamd, work)
-        ox, op, ol = oracle.icm_sweep(st.geom, st.frames, st.kin, st.prior, st.lm, sino, ox, op, ol, cfg.Q, s)
-        diverged |= np.abs(lamd.cpu().numpy() / ol - 1.0) > 1e-3
-    torch.cuda.synchronize()
-    return x.cpu().numpy(), params.cpu().numpy(), ox, op, diverged
-
-
-def test_icm_full_schedule_low_count_decision_consistent():
-    """10 sweeps on two 64x64 planes at the batch recipe's 4e5 counts per plane (noisier fits than
-    the 64x64 single-slice study, so more near-tie decisions)."""
-    cfg = inputs.StudyConfig("low_count_64x64x2", 64, 64, 2, 4.0, 4.0, 60, 64, 4.0, 8e5, 0.1, Q=6, n_sweeps=10,
-                             phantom="brain", n_lesions=3, seed=31)
-    st = oracle.make_study(cfg)
-    gx, gp, ox, op, diverged = run_schedule_tracking_decisions(st, cfg.n_sweeps)
-    act = (ox * (st.frames.t1 - st.frames.t0)).sum(axis=-1)
-    mask = act >= 0.1 * act.max()
-    keep = mask & ~diverged
-    ex = rel_l2(gx, ox)
-    all_maps = [rel_l2(gp[i][mask], op[i][mask]) for i in range(3)]
-    kept_maps = [rel_l2(gp[i][keep], op[i][keep]) for i in range(3)]
-    frac = diverged[mask].mean()
-    print(f"low-count 64x64x2, 10 sweeps: image {ex:.2e}; maps over active voxels {['%.2e' % e for e in all_maps]}; "
-          f"over decision-consistent voxels {['%.2e' % e for e in kept_maps]}; diverged {frac:.4f} of "
-          f"{int(mask.sum())} active voxels")
-    assert ex < 1e-3
-    assert frac < 0.02
-    assert max(kept_maps) < 1e-3
