@@ -123,10 +123,11 @@ def counter_traffic(cfg_name, kind):
     return blob.get("traffic_bytes_per_launch", {}).get(kind)
 
 
-def counter_valu(cfg_name, kind):
-    """VALU instructions per launch of step `kind` from the committed instruction-counter summary
-    of this workload, or None (missing, or kernel sources changed since)."""
-    path = os.path.join(ROOT, "profiles", f"sweep_{cfg_name.split('_', 1)[1]}_instruction_counters.md")
+def counter_busy(cfg_name, kind):
+    """Fraction of the CUs' busy time that step `kind`'s kernels issue VALU instructions, from the
+    committed busy-counter summary of this workload, or None (missing, or kernel sources changed
+    since)."""
+    path = os.path.join(ROOT, "profiles", f"sweep_{cfg_name.split('_', 1)[1]}_busy_counters.md")
     if not os.path.exists(path):
         return None
     try:
@@ -135,8 +136,7 @@ def counter_valu(cfg_name, kind):
         return None
     if blob.get("source") != kernel_source_hash():
         return None
-    n = blob.get("valu_instructions_per_launch", {}).get(kind)
-    return None if n is None else (n, blob["valu_cycles_per_instruction"], blob["simds"], blob["clock_hz"])
+    return blob.get("valu_busy", {}).get(kind)
 
 
 def cpu_baseline(cfg):
@@ -156,24 +156,40 @@ def cpu_baseline(cfg):
     n_sub = min(cfg.Q, 6)
     ny, nx = 128, 128
     y0, x0 = cfg.ny // 2 - ny // 2, cfg.nx // 2 - nx // 2
-    with threadpool_limits(1):
-        t = time.perf_counter()
-        for q in range(n_sub):
-            x = oracle.osl_update(st.geom, st.frames, st.kin, st.prior, sino, params, x, q, cfg.Q, True)
-        t_osl = (time.perf_counter() - t) / n_sub
-        xs = np.ascontiguousarray(st.truth_x[:, y0:y0 + ny, x0:x0 + nx])
-        ps = np.ascontiguousarray(params[:, :, y0:y0 + ny, x0:x0 + nx])
-        ls = np.zeros((1, ny, nx))
-        t = time.perf_counter()
-        for _ in range(2):
-            ps, ls = oracle.lm_iteration(st.frames, st.kin, st.prior, st.lm, xs, ps, ls)
-        t_lm = (time.perf_counter() - t) / 2
+    xs = np.ascontiguousarray(st.truth_x[:, y0:y0 + ny, x0:x0 + nx])
+    ps0 = np.ascontiguousarray(params[:, :, y0:y0 + ny, x0:x0 + nx])
     n_vox = cfg.nx * cfg.ny * cfg.nz
-    sweep_s = cfg.nz * cfg.Q * t_osl + cfg.n_lm * n_vox * t_lm / (nx * ny)
-    return {"value": 1.0 / sweep_s, "unit": "sweeps/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{n_sub} OSL subset updates on one {cfg.nx}x{cfg.ny} plane ({t_osl:.2f} s each) and 2 MAP-LM "
-                       f"iterations on {nx * ny} voxels ({t_lm:.2f} s each), FP64, 1 thread; extrapolated to "
-                       f"{cfg.nz} planes x {cfg.Q} subsets and {cfg.n_lm} iterations x {n_vox} voxels")}
+
+    def timed(threads):
+        with threadpool_limits(threads):
+            xx = x.copy()
+            t = time.perf_counter()
+            for q in range(n_sub):
+                xx = oracle.osl_update(st.geom, st.frames, st.kin, st.prior, sino, params, xx, q, cfg.Q, True)
+            t_osl = (time.perf_counter() - t) / n_sub
+            ps, ls = ps0.copy(), np.zeros((1, ny, nx))
+            t = time.perf_counter()
+            for _ in range(2):
+                ps, ls = oracle.lm_iteration(st.frames, st.kin, st.prior, st.lm, xs, ps, ls)
+            t_lm = (time.perf_counter() - t) / 2
+        return t_osl, t_lm, cfg.nz * cfg.Q * t_osl + cfg.n_lm * n_vox * t_lm / (nx * ny)
+
+    def sample(t_osl, t_lm, threads):
+        return (f"{n_sub} OSL subset updates on one {cfg.nx}x{cfg.ny} plane ({t_osl:.2f} s each) and 2 MAP-LM "
+                f"iterations on {nx * ny} voxels ({t_lm:.2f} s each), FP64, {threads} thread(s); extrapolated to "
+                f"{cfg.nz} planes x {cfg.Q} subsets and {cfg.n_lm} iterations x {n_vox} voxels")
+
+    t_osl, t_lm, sweep_s = timed(1)
+    out = {"value": 1.0 / sweep_s, "unit": "sweeps/s", "cores": 1, "kind": "oracle", "sample": sample(t_osl, t_lm, 1)}
+    # the same sample with every host core the process may use (the oracle's C model loop runs in
+    # OpenMP threads, NumPy/SciPy in their thread pools; the sparse products stay single-threaded)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():  # the host's share of cores, where it is set
+        cores = min(cores, int(os.environ["OMP_NUM_THREADS"]))
+    t_osl, t_lm, sweep_s = timed(cores)
+    out["all_cores"] = {"value": 1.0 / sweep_s, "unit": "sweeps/s", "cores": cores, "sample": sample(t_osl, t_lm,
+                                                                                                       cores)}
+    return out
 
 
 def run_batched(args):
@@ -332,11 +348,13 @@ def run_serve(args):
             for r in reqs:
                 nb = algorithmic_bytes(r.g, r.f.M, r.Q)
                 total_bytes += r.n_sweeps * (r.Q * (nb["project"] + nb["osl"]) + 5 * nb["lm"])
-        if mode == "served":
+        if mode.startswith("served"):
+            # "served:N" runs at most N small-study ticks beside a large study's tick
+            cap = int(mode.split(":")[1]) if ":" in mode else args.small_beside_large
             ex = serve.GpuExecutor(dev, n_lanes=2)
-            comp, _, makespan, ticks = serve.serve(reqs, budget, ex, log=log)
+            comp, _, makespan, ticks = serve.serve(reqs, budget, ex, log=log, small_in_flight_beside_large=cap)
             ex.close()
-            extra = {"ticks": ticks, "plans": None}
+            extra = {"ticks": ticks, "small_in_flight_beside_large": cap}
         else:
             comp, _, makespan = serve.serve_serial(reqs, log=log)
             extra = {}
@@ -373,24 +391,38 @@ def run_serve(args):
 
 
 def run_copy(args):
-    """A plain device-to-device copy of a known size (1 GiB read, 1 GiB written per launch), the
-    reference against which the HBM byte counters of a profiled run are scaled."""
+    """The HBM rates this GPU sustains, from the library's streaming kernels: a plain read (2 GiB
+    into one partial sum per thread) and a plain copy (2 GiB read, 2 GiB written), each at the
+    workgroup count that runs fastest.  These are the ceilings the bandwidth-bound kernels are
+    compared with, and the copy is the reference of known size against which the HBM byte counters
+    of a profiled run are scaled."""
     import torch
 
-    n = 1 << 28  # FP32 elements: 1 GiB
-    a = torch.ones(n, device="cuda:0")
-    b = torch.empty_like(a)
-    b.copy_(a)  # warm-up
-    torch.cuda.synchronize()
+    from paper_1803_10045_amd import kcs
+
+    nbytes = 2 << 30
+    src = torch.ones(nbytes // 4, device="cuda:0")
+    dst = torch.empty_like(src)
+    sums = torch.empty(8192 * 256, device="cuda:0")
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(args.steps):
-        b.copy_(a)
-    t1.record()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / args.steps
-    print(json.dumps({"copy_bytes_per_launch": 4 * n, "launches": args.steps + 1, "avg_ms": round(ms, 4),
-                      "read_plus_write_GBps": round(2 * 4 * n / ms / 1e6, 1)}), flush=True)
+    out = {"bytes_per_launch": nbytes}
+    for kind, name, moved in ((0, "read", nbytes), (1, "copy", 2 * nbytes)):
+        best = None
+        for groups in (256, 512, 1024, 2048, 4096):
+            kcs.kcs_stream_probe(kind, src, sums if kind == 0 else dst, groups)  # warm-up
+            torch.cuda.synchronize()
+            t0.record()
+            for _ in range(args.steps):
+                kcs.kcs_stream_probe(kind, src, sums if kind == 0 else dst, groups)
+            t1.record()
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / args.steps
+            if best is None or ms < best[1]:
+                best = (groups, ms)
+        out[name] = {"workgroups": best[0], "avg_ms": round(best[1], 4),
+                     "GBps": round(moved / best[1] / 1e6, 1)}
+        log(f"stream {name}: {out[name]}")
+    print(json.dumps(out), flush=True)
 
 
 def run_ki(args):
@@ -474,8 +506,10 @@ def main():
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--rate", type=float, default=4.0)
     ap.add_argument("--budget-gb", type=float, default=250.0)
+    ap.add_argument("--small-beside-large", type=int, default=1,
+                    help="serve mode: small-study ticks in flight beside a large study's tick")
     ap.add_argument("--serve-runs", default="served@poisson,serial@poisson,served@saturated,serial@saturated",
-                    help="comma-separated runs of the serve mode: served|serial @ poisson|saturated")
+                    help="comma-separated runs of the serve mode: served[:N]|serial @ poisson|saturated (N: --small-beside-large)")
     ap.add_argument("--config", default="brain344", choices=["disk64", "brain128", "brain344"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--correction", action="store_true",
@@ -565,20 +599,14 @@ def main():
         # summaries, averaged over a sweep's launches; None once the kernel sources changed)
         tb = counter_traffic(cfg.name, kind)
         kernels[kind]["traffic_GBps"] = None if tb is None else round(tb / (avg * 1e-3) / 1e9, 1)
-        vc = counter_valu(cfg.name, kind)
-        kernels[kind]["valu_issue_frac"] = (None if vc is None else
-                                            round(vc[0] * vc[1] / (vc[2] * vc[3]) / (avg * 1e-3), 3))
+        kernels[kind]["valu_busy"] = counter_busy(cfg.name, kind)
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_sweep"])
     traffic = counter_traffic(cfg.name, dom)
     roof = {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["alg_GBps"], "peak": HBM_PEAK_GBPS,
             "unit": "GB/s", "frac": kernels[dom]["hbm_frac"],
             "traffic": None if traffic is None else round(traffic / (kernels[dom]["avg_ms"] * 1e-3) / 1e9, 1),
             "traffic_bytes_per_launch": traffic, "alg_bytes_per_launch": kernels[dom]["alg_bytes_per_launch"]}
-    valu = counter_valu(cfg.name, dom)
-    if valu is not None:
-        # the same kernel against the VALU issue rate (wave instructions x cycles / (SIMDs x clock))
-        n, cyc, simds, clk = valu
-        roof["valu_issue_frac"] = round(n * cyc / (simds * clk) / (kernels[dom]["avg_ms"] * 1e-3), 3)
+    roof["valu_busy"] = counter_busy(cfg.name, dom)
     value = args.steps / (elapsed_ms * 1e-3)
     out = {
         "metric": "ICM sweeps/s",

@@ -82,26 +82,34 @@ typedef struct kcs_frames {
 
 /* Plasma input Cp(t) = (A1 t - A2 - A3) e^{l1 t} + A2 e^{l2 t} + A3 e^{l3 t} (t >= 0, minutes;
  * Cp = 0 before 0) and the measured TAC model C_PET = (1 - vb) C_T + vb Cp with the irreversible
- * two-tissue tissue curve C_T(K1, k2, k3) (k4 = 0).  l1 < l2 < l3 < 0 distinct; 0 <= vb < 1. */
+ * two-tissue tissue curve C_T(K1, k2, k3) (k4 = 0).  l1 < l2 < l3 < 0 distinct.
+ * fit_vb = 0: vb is the study's blood fraction, 0 <= vb < 1, and the kinetic maps are the three
+ * maps [3][nz][ny][nx] (K1, k2, k3).  fit_vb = 1: the blood fraction is a fourth map per voxel
+ * (the f_v map of Sec. IV and Table I), the maps are [4][nz][ny][nx] (K1, k2, k3, vb) everywhere
+ * below (model TAC, OSL prior, MAP-LM fit, initial state), and the field vb is not used.  Plans do
+ * not take fit_vb = 1 (KCS_EINVAL). */
 typedef struct kcs_kinetics {
     double A1, A2, A3, l1, l2, l3, vb;
+    int32_t fit_vb;
 } kcs_kinetics;
 
 /* Priors.  OSL denominator (Eq. 2-3): D = n (1 + beta_kp (x - F) / max(F, eps_F)) with
  * 0 <= beta_kp < 1 and eps_F > 0; kp_on = 0 turns the kinetics-derived prior off (plain OS-EM).
- * MAP-LM (Eq. 4-7): weight beta_h >= 0 and Huber threshold delta[p] > 0 per kinetic parameter.
+ * MAP-LM (Eq. 4-7): weight beta_h >= 0 and Huber threshold delta[p] > 0 per kinetic map (delta[3],
+ * of the blood-fraction map, only read with kcs_kinetics.fit_vb).
  * Neighbourhood of the Huber term: plane_ratio = 0 takes the 8 in-plane neighbours (the paper's
  * prior, weights 1 and 1/sqrt(2)); plane_ratio > 0 takes the 26 neighbours of the 3x3x3 cube,
  * the planes being plane_ratio pixel sides apart, each weighted by 1 / its distance in pixel
  * sides.  plane_ratio must be finite and >= 0. */
 typedef struct kcs_prior {
-    double beta_kp, eps_F, beta_h, delta[3];
+    double beta_kp, eps_F, beta_h, delta[4];
     int32_t kp_on;
     double plane_ratio;
 } kcs_prior;
 
 /* Levenberg-Marquardt schedule: n_iter synchronous iterations; lambda <= 0 on entry is set to
- * tau * max diag(J^T J); parameters clipped to [lo, hi] (lo[1] + lo[2] > 0); a step is accepted
+ * tau * max diag(J^T J); parameters clipped to [lo, hi] (lo[1] + lo[2] > 0; the blood fraction's
+ * bounds lo[3], hi[3] are read only with fit_vb and must satisfy 0 <= lo[3] <= hi[3] <= 1); a step is accepted
  * iff the voxel objective decreases by more than eta times its value,
  * Phi(xi') - Phi(xi) < -eta Phi(xi) (0 <= eta < 1; eta = 0 is the plain strict decrease), then
  * lambda = max(lambda/10, lam_min), otherwise lambda = min(10 lambda, lam_max).
@@ -111,7 +119,7 @@ typedef struct kcs_prior {
  * kcs_lm_fit always starts from d_lambda. */
 typedef struct kcs_lm_opts {
     int32_t n_iter;
-    double tau, lam_min, lam_max, lo[3], hi[3], eta;
+    double tau, lam_min, lam_max, lo[4], hi[4], eta;
     int32_t restart;
 } kcs_lm_opts;
 
@@ -144,7 +152,8 @@ int kcs_ki_map(const float* d_params, int64_t n, float* d_ki, hipStream_t stream
 
 /* Frame-averaged model TAC (Eq. 3's F(xi)_m, closed-form time integrals) for n voxels:
  *   F_m = (1/dt_m) int_{t0_m}^{t1_m} [(1 - vb) C_T(t; K1, k2, k3) + vb Cp(t)] dt
- * d_params: [3][n] (K1, k2, k3 with k2 + k3 > 0); d_F: [n][M]; d_J: [n][M][3] dF/d(K1,k2,k3) or NULL.
+ * d_params: [P][n] (K1, k2, k3 with k2 + k3 > 0, and vb with k->fit_vb; P = 3 or 4); d_F: [n][M];
+ * d_J: [n][M][P] dF/d(K1, k2, k3[, vb]) or NULL.
  * d_work: at least kcs_workspace_bytes(NULL, M, 0) bytes. */
 int kcs_model_tac(const kcs_frames* f, const kcs_kinetics* k, const float* d_params, int64_t n, float* d_F,
                   float* d_J, void* d_work, size_t work_bytes, hipStream_t stream);
@@ -169,10 +178,12 @@ int kcs_lm_fit(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics* k
                size_t work_bytes, hipStream_t stream);
 
 /* Initial ICM state: x_m = max(sum_d (s_dm - r_m), 1) / (E_m sum_v sum_d p_vd) in every voxel,
- * maps = xi0 everywhere, lambda = 0 (initialised by the first LM iteration).  The flat start
- * ignores g->d_mult (the first OSL update rescales the image to the data). */
-int kcs_init_state(const kcs_geometry* g, const kcs_frames* f, const float* d_sino, const double xi0[3],
-                   float* d_x, float* d_params, float* d_lambda, void* d_work, size_t work_bytes,
+ * maps = xi0 everywhere (n_maps = 3 values K1, k2, k3, or 4 with the blood fraction for studies
+ * with kcs_kinetics.fit_vb; d_params is [n_maps][nz][ny][nx]), lambda = 0 (initialised by the
+ * first LM iteration).  The flat start ignores g->d_mult (the first OSL update rescales the
+ * image to the data). */
+int kcs_init_state(const kcs_geometry* g, const kcs_frames* f, const float* d_sino, const double* xi0,
+                   int32_t n_maps, float* d_x, float* d_params, float* d_lambda, void* d_work, size_t work_bytes,
                    hipStream_t stream);
 
 /* One ICM sweep (Sec. II-D): kcs_osl_update for q = 0..Q-1 (prior on iff p->kp_on and

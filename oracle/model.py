@@ -114,26 +114,39 @@ def cumulative_tissue(params: np.ndarray, T: np.ndarray, kin: Kinetics, jacobian
 
 def model_tac(params: np.ndarray, t0: np.ndarray, t1: np.ndarray, kin: Kinetics, jacobian: bool = False,
               chunk: int = 1 << 18):
-    """Frame-averaged model TAC F_m(xi) (n, M) and optionally its Jacobian (n, M, 3)."""
+    """Frame-averaged model TAC F_m(xi) (n, M) and optionally its Jacobian (n, M, P).
+
+    params: (n, 3) rows (K1, k2, k3) with the blood fraction kin.vb, or (n, 4) rows
+    (K1, k2, k3, vb) with a blood fraction per voxel (the paper's f_v fitted as a fourth map,
+    Sec. IV and Table I).  F_m = [(1 - vb) int_frame C_T + vb int_frame Cp] / dt_m, so the
+    derivative by vb is (int_frame Cp - int_frame C_T) / dt_m."""
     params = np.atleast_2d(np.asarray(params, dtype=np.float64))
+    n_par = params.shape[1]
+    if n_par not in (3, 4):
+        raise ValueError("params must have 3 or 4 columns")
     t0 = np.asarray(t0, dtype=np.float64)
     t1 = np.asarray(t1, dtype=np.float64)
     dt = t1 - t0
     P1_0, _ = input_integrals(t0, kin)
     P1_1, _ = input_integrals(t1, kin)
-    blood = kin.vb * (P1_1 - P1_0)
+    cp_int = P1_1 - P1_0  # int_frame Cp
     n = params.shape[0]
     M = len(t0)
     F = np.empty((n, M))
-    J = np.empty((n, M, 3)) if jacobian else None
+    J = np.empty((n, M, n_par)) if jacobian else None
     tb, inv = np.unique(np.concatenate([t0, t1]), return_inverse=True)
     i0, i1 = inv[:M], inv[M:]
     for s in range(0, n, chunk):
         p = params[s:s + chunk]
-        C, D = cumulative_tissue(p, tb, kin, jacobian)
-        F[s:s + chunk] = ((1.0 - kin.vb) * (np.take(C, i1, axis=1) - np.take(C, i0, axis=1)) + blood[None, :]) / dt[None, :]
+        vb = p[:, 3:4] if n_par == 4 else kin.vb
+        C, D = cumulative_tissue(np.ascontiguousarray(p[:, :3]), tb, kin, jacobian)
+        tissue = np.take(C, i1, axis=1) - np.take(C, i0, axis=1)  # int_frame C_T
+        F[s:s + chunk] = ((1.0 - vb) * tissue + vb * cp_int[None, :]) / dt[None, :]
         if jacobian:
-            J[s:s + chunk] = (1.0 - kin.vb) * (np.take(D, i1, axis=1) - np.take(D, i0, axis=1)) / dt[None, :, None]
+            vbj = vb[:, :, None] if n_par == 4 else vb
+            J[s:s + chunk, :, :3] = (1.0 - vbj) * (np.take(D, i1, axis=1) - np.take(D, i0, axis=1)) / dt[None, :, None]
+            if n_par == 4:
+                J[s:s + chunk, :, 3] = (cp_int[None, :] - tissue) / dt[None, :]
     return (F, J) if jacobian else F
 
 

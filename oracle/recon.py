@@ -109,7 +109,7 @@ def osl_update(g: geo.Geometry, fr: Frames, kin: Kinetics, prior: Prior, sino: n
     n = np.broadcast_to(n, x.shape)
     if kp:
         if F is None:
-            F = model_tac(params.reshape(3, -1).T, fr.t0, fr.t1, kin).reshape(x.shape)
+            F = model_tac(params.reshape(params.shape[0], -1).T, fr.t0, fr.t1, kin).reshape(x.shape)
         D = n * (1.0 + prior.beta_kp * (x - F) / np.maximum(F, prior.eps_F))
     else:
         D = n
@@ -162,7 +162,7 @@ def _pair(d, n):
 
 def neighbour_terms(xi_eval: np.ndarray, xi_ref: np.ndarray, delta, plane_ratio: float = 0.0
                     ) -> Tuple[np.ndarray, np.ndarray]:
-    """For maps (3, nz, ny, nx): sum_k w_k psi(xi_eval_v - xi_ref_k) per parameter (3, ...) and
+    """For maps (P, nz, ny, nx): sum_k w_k psi(xi_eval_v - xi_ref_k) per parameter (P, ...) and
     sum_k w_k sum_p H(xi_eval_vp - xi_ref_kp) (nz, ny, nx) over the neighbours k of
     neighbour_offsets(plane_ratio) that lie inside the image."""
     _, nz, ny, nx = xi_ref.shape
@@ -171,7 +171,7 @@ def neighbour_terms(xi_eval: np.ndarray, xi_ref: np.ndarray, delta, plane_ratio:
     for dz, dy, dx, w in neighbour_offsets(plane_ratio):
         (zs, zd), (ys, yd), (xs, xd) = _pair(dz, nz), _pair(dy, ny), _pair(dx, nx)
         # voxel at (z, y, x) = source slices; its neighbour at (z+dz, y+dy, x+dx) = destination slices
-        for p in range(3):
+        for p in range(xi_ref.shape[0]):
             t = xi_eval[p][zs, ys, xs] - xi_ref[p][zd, yd, xd]
             grad[p][zs, ys, xs] += w * huber_grad(t, delta[p])
             energy[zs, ys, xs] += w * huber(t, delta[p])
@@ -181,22 +181,24 @@ def neighbour_terms(xi_eval: np.ndarray, xi_ref: np.ndarray, delta, plane_ratio:
 def lm_iteration(fr: Frames, kin: Kinetics, prior: Prior, opt: LMOptions, x: np.ndarray, params: np.ndarray,
                  lam: np.ndarray, with_objective: bool = False):
     """One synchronous MAP-LM iteration over all voxels (Eq. 4).  x: (nz, ny, nx, M);
-    params: (3, nz, ny, nx); lam: (nz, ny, nx).  Returns new (params, lam), followed by the
-    voxel objectives before and at the trial step (phi0, phi1), each (nz, ny, nx), when
+    params: (P, nz, ny, nx), P = 3 maps (K1, k2, k3) or 4 (with the blood fraction vb); prior.delta,
+    opt.lo and opt.hi hold P entries; lam: (nz, ny, nx).  Returns new (params, lam), followed by
+    the voxel objectives before and at the trial step (phi0, phi1), each (nz, ny, nx), when
     `with_objective` is set."""
+    n_par = params.shape[0]
     shp = params.shape[1:]
     N = int(np.prod(shp))
     xv = x.reshape(N, -1)
-    xi = params.reshape(3, N).T.copy()
+    xi = params.reshape(n_par, N).T.copy()
     F, J = model_tac(xi, fr.t0, fr.t1, kin, jacobian=True)
     r = xv - F
     pg, pe = neighbour_terms(params, params, prior.delta, prior.plane_ratio)
-    g = np.einsum("nmp,nm->np", J, r) - prior.beta_h * pg.reshape(3, N).T
+    g = np.einsum("nmp,nm->np", J, r) - prior.beta_h * pg.reshape(n_par, N).T
     A = np.einsum("nmp,nmq->npq", J, J)
     lam = lam.reshape(N).copy()
     init = lam <= 0.0
     lam[init] = opt.tau * np.max(np.diagonal(A, axis1=1, axis2=2), axis=1)[init]
-    step = np.linalg.solve(A + lam[:, None, None] * np.eye(3)[None], g[:, :, None])[:, :, 0]
+    step = np.linalg.solve(A + lam[:, None, None] * np.eye(n_par)[None], g[:, :, None])[:, :, 0]
     trial = np.clip(xi + step, np.array(opt.lo), np.array(opt.hi))
     F1 = model_tac(trial, fr.t0, fr.t1, kin)
     trial_maps = trial.T.reshape(params.shape)
@@ -226,7 +228,7 @@ def icm_sweep(g, fr, kin, prior, opt, sino, x, params, lam, Q: int, sweep_idx: i
     new image and its damping starts from tau * max diag(J^T J) (the lambda passed in is
     ignored); otherwise it continues from the lambda passed in.  The final lambda is returned."""
     kp = prior.kp_on and sweep_idx > 0
-    F = model_tac(params.reshape(3, -1).T, fr.t0, fr.t1, kin).reshape(x.shape) if kp else None
+    F = model_tac(params.reshape(params.shape[0], -1).T, fr.t0, fr.t1, kin).reshape(x.shape) if kp else None
     for q in range(Q):
         x = osl_update(g, fr, kin, prior, sino, params, x, q, Q, kp, mult, F)
     params, lam = lm_fit(fr, kin, prior, opt, x, params, np.zeros_like(lam) if opt.restart else lam)
@@ -234,9 +236,10 @@ def icm_sweep(g, fr, kin, prior, opt, sino, x, params, lam, Q: int, sweep_idx: i
 
 
 def initial_state(g: geo.Geometry, fr: Frames, sino: np.ndarray, xi0=(0.08, 0.12, 0.05)):
+    """Flat image, maps xi0 everywhere (3 values, or 4 with the blood fraction), lambda 0."""
     x = initial_image(g, fr, sino)
-    params = np.empty((3, g.nz, g.ny, g.nx))
-    for p in range(3):
+    params = np.empty((len(xi0), g.nz, g.ny, g.nx))
+    for p in range(len(xi0)):
         params[p] = xi0[p]
     lam = np.zeros((g.nz, g.ny, g.nx))
     return x, params, lam

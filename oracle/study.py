@@ -10,6 +10,7 @@ bins in proportion to frame duration.
 """
 from __future__ import annotations
 
+import dataclasses
 from dataclasses import dataclass
 
 import numpy as np
@@ -113,3 +114,18 @@ def make_plane_study(cfg, planes, seed=None) -> Study:
     lm = LMOptions(n_iter=cfg.n_lm, tau=inputs.LM_TAU, lam_min=inputs.LM_LAM_MIN, lam_max=inputs.LM_LAM_MAX,
                    lo=inputs.LM_LO, hi=inputs.LM_HI, eta=inputs.LM_ETA)
     return Study(sub, g, Frames(t0=t0, t1=t1, E=E, r=r), kin, prior, lm, sino, pm, x_true, pmask)
+
+
+def fitting_blood_fraction(st: Study) -> Study:
+    """The same study with the blood fraction fitted as a fourth map (Sec. IV, Table I: f_v):
+    the Huber threshold of the fourth map is the study's threshold, its box [0, 1]; the data (made
+    with the fixed fraction kin.vb) are unchanged, so the fit should find about kin.vb in tissue."""
+    d = tuple(st.prior.delta)
+    prior = dataclasses.replace(st.prior, delta=d + (d[0],))
+    lm = dataclasses.replace(st.lm, lo=tuple(st.lm.lo) + (inputs.LM_LO_VB,), hi=tuple(st.lm.hi) + (inputs.LM_HI_VB,))
+    return dataclasses.replace(st, prior=prior, lm=lm)
+
+
+def initial_maps(st: Study):
+    """Initial map values of the study's fit: (K1, k2, k3), plus vb when it is fitted."""
+    return tuple(inputs.XI0) + ((inputs.XI0_VB,) if len(st.lm.lo) == 4 else ())

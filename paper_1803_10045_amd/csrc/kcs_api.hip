@@ -83,28 +83,33 @@ int check_kinetics(const kcs_kinetics* k) {
     for (double x : v)
         if (!is_finite(x)) return fail(KCS_EINVAL, "kinetics must be finite");
     if (!(k->l1 < 0 && k->l2 < 0 && k->l3 < 0)) return fail(KCS_EINVAL, "input-function exponents must be negative");
-    if (!(k->vb >= 0 && k->vb < 1)) return fail(KCS_EINVAL, "vb must be in [0, 1)");
+    if (k->fit_vb != 0 && k->fit_vb != 1) return fail(KCS_EINVAL, "fit_vb must be 0 or 1");
+    if (!k->fit_vb && !(k->vb >= 0 && k->vb < 1)) return fail(KCS_EINVAL, "vb must be in [0, 1)");
     return KCS_OK;
 }
 
-int check_prior(const kcs_prior* p) {
+// Number of kinetic maps of a study: K1, k2, k3 and, with fit_vb, the blood fraction.
+int n_maps(const kcs_kinetics& k) { return k.fit_vb ? 4 : 3; }
+
+int check_prior(const kcs_prior* p, int np = 3) {
     if (!p) return fail(KCS_EINVAL, "prior is NULL");
     if (!(p->beta_kp >= 0 && p->beta_kp < 1)) return fail(KCS_EINVAL, "beta_kp must be in [0, 1)");
     if (!(p->eps_F > 0) || !is_finite(p->eps_F)) return fail(KCS_EINVAL, "eps_F must be > 0");
     if (!(p->beta_h >= 0) || !is_finite(p->beta_h)) return fail(KCS_EINVAL, "beta_h must be >= 0");
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < np; ++i)
         if (!(p->delta[i] > 0) || !is_finite(p->delta[i])) return fail(KCS_EINVAL, "delta must be > 0");
     if (!(p->plane_ratio >= 0) || !is_finite(p->plane_ratio)) return fail(KCS_EINVAL, "plane_ratio must be >= 0");
     return KCS_OK;
 }
 
-int check_lm(const kcs_lm_opts* o) {
+int check_lm(const kcs_lm_opts* o, int np = 3) {
     if (!o) return fail(KCS_EINVAL, "lm options are NULL");
     if (o->n_iter < 0 || o->n_iter > 100000) return fail(KCS_EINVAL, "n_iter out of range");
     if (!(o->tau > 0) || !(o->lam_min > 0) || !(o->lam_max >= o->lam_min) || !is_finite(o->lam_max))
         return fail(KCS_EINVAL, "need tau > 0 and 0 < lam_min <= lam_max");
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < np; ++i)
         if (!is_finite(o->lo[i]) || !is_finite(o->hi[i]) || !(o->lo[i] <= o->hi[i])) return fail(KCS_EINVAL, "need lo <= hi");
+    if (np == 4 && !(o->lo[3] >= 0 && o->hi[3] <= 1)) return fail(KCS_EINVAL, "blood fraction bounds must lie in [0, 1]");
     if (!(o->lo[1] + o->lo[2] > 0)) return fail(KCS_EINVAL, "lo[1] + lo[2] must be > 0 (k2 + k3 > 0)");
     if (!(o->eta >= 0 && o->eta < 1)) return fail(KCS_EINVAL, "eta must be in [0, 1)");
     return KCS_OK;
@@ -210,6 +215,7 @@ Schedule make_schedule(const kcs_frames& f, const kcs_kinetics* k) {
             input_integrals(*k, frame_start(f, m), a1, a2);
             input_integrals(*k, f.t1_min[m], b1, b2);
             S.fr.blood[m] = (float)(k->vb * (b1 - a1));
+            S.fr.cp_int[m] = (float)(b1 - a1);
             S.fr.dP2[m] = (float)(b2 - a2);
         }
     }
@@ -363,9 +369,9 @@ Layout layout(const kcs_geometry* g, int32_t M, int32_t Q) {
     if (g) {
         const size_t N = (size_t)g->nx * g->ny * g->nz;
         L.xi = off;
-        off = align_up(off + 3 * N * sizeof(float), 256);
-        L.lms = off;  // MAP-LM normal equations carried between iterations: 10 floats per voxel
-        off = align_up(off + 10 * N * sizeof(float), 256);
+        off = align_up(off + 4 * N * sizeof(float), 256);  // up to 4 maps (with the blood fraction)
+        L.lms = off;  // MAP-LM normal equations carried between iterations: 10 (15 with 4 maps) floats per voxel
+        off = align_up(off + 15 * N * sizeof(float), 256);
         L.init = off;
         off = align_up(off + ((size_t)kInitChunks * M + M) * sizeof(double), 256);
         L.F = off;
@@ -451,13 +457,13 @@ int do_setup(const Schedule& S, void* d_work, hipStream_t st) {
 }
 
 // Model TACs of the maps into the workspace (read by every OSL update of the pass).
-int do_model_pass(const kcs_geometry& g, const Schedule& S, const float* params, void* d_work, int32_t Q,
+int do_model_pass(const kcs_geometry& g, const Schedule& S, int np, const float* params, void* d_work, int32_t Q,
                   hipStream_t st) {
     const Layout L = layout(&g, S.fr.M, Q);
     const int64_t N = (int64_t)g.nx * g.ny * g.nz;
     return launched(timed(KCS_T_MODEL, st,
                           [&] {
-                              return launch_model(S.fr.M, at<KinTab>(d_work, L.kin), S.fr, params, N,
+                              return launch_model(S.fr.M, np, at<KinTab>(d_work, L.kin), S.fr, params, N,
                                                   at<float>(d_work, L.F), nullptr, st);
                           }),
                     "model pass");
@@ -492,7 +498,7 @@ void set_neighbourhood(LmArgs& a, const kcs_prior& p) {
     for (int k = 0; k < 3; ++k) a.w_plane[k] = a.nbr3d ? (float)(1.0 / std::sqrt(r2 + k)) : 0.0f;
 }
 
-int do_lm(const kcs_geometry& g, const Schedule& S, const kcs_prior& p, const kcs_lm_opts& o, const float* x,
+int do_lm(const kcs_geometry& g, const Schedule& S, int np, const kcs_prior& p, const kcs_lm_opts& o, const float* x,
           float* params, float* lam, void* d_work, int32_t Q, bool fresh_lambda, hipStream_t st) {
     if (o.n_iter == 0) return KCS_OK;
     const Layout L = layout(&g, S.fr.M, Q);
@@ -504,7 +510,8 @@ int do_lm(const kcs_geometry& g, const Schedule& S, const kcs_prior& p, const kc
     a.fr = S.fr;
     a.beta_h = (float)p.beta_h;
     set_neighbourhood(a, p);
-    for (int i = 0; i < 3; ++i) {
+    a.np = np;
+    for (int i = 0; i < np; ++i) {
         a.delta[i] = (float)p.delta[i];
         a.lo[i] = (float)o.lo[i];
         a.hi[i] = (float)o.hi[i];
@@ -519,7 +526,7 @@ int do_lm(const kcs_geometry& g, const Schedule& S, const kcs_prior& p, const kc
     float* dst = other;
     if (o.n_iter % 2 == 1) {
         hipError_t e = timed(KCS_T_COPY, st, [&] {
-            return hipMemcpyAsync(other, params, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, st);
+            return hipMemcpyAsync(other, params, np * N * sizeof(float), hipMemcpyDeviceToDevice, st);
         });
         if (e != hipSuccess) return hip_fail(e, "map copy");
         src = other;
@@ -587,6 +594,7 @@ int check_study(const kcs_study& st) {
     KCS_TRY(check_frames(&st.f));
     KCS_TRY(check_plane(&st.g, st.f.n_frames));
     KCS_TRY(check_kinetics(&st.k));
+    if (st.k.fit_vb) return fail(KCS_EINVAL, "plans do not fit the blood fraction (fit_vb)");
     KCS_TRY(check_prior(&st.p));
     KCS_TRY(check_lm(&st.lm));
     KCS_TRY(check_subset(&st.g, 0, st.Q));
@@ -616,6 +624,7 @@ LmArgs lm_args(const StudyPrep& P) {
     a.fr = P.S.fr;
     a.beta_h = (float)s.p.beta_h;
     set_neighbourhood(a, s.p);
+    a.np = 3;
     for (int i = 0; i < 3; ++i) {
         a.delta[i] = (float)s.p.delta[i];
         a.lo[i] = (float)s.lm.lo[i];
@@ -855,8 +864,8 @@ int check_sweep_args(const kcs_geometry* g, const kcs_frames* f, const kcs_kinet
     KCS_TRY(check_frames(f));
     KCS_TRY(check_plane(g, f->n_frames));
     KCS_TRY(check_kinetics(k));
-    KCS_TRY(check_prior(p));
-    KCS_TRY(check_lm(lm));
+    KCS_TRY(check_prior(p, n_maps(*k)));
+    KCS_TRY(check_lm(lm, n_maps(*k)));
     KCS_TRY(check_subset(g, 0, Q));
     if (sweep_idx < 0) return fail(KCS_EINVAL, "sweep_idx must be >= 0");
     if (!d_sino || !d_x || !d_params || !d_lambda) return fail(KCS_EINVAL, "device pointers must not be NULL");
@@ -873,9 +882,9 @@ int icm_sweep_body(const kcs_geometry& g, const kcs_frames& f, const kcs_kinetic
     g_err.clear();
     KCS_TRY(do_setup(S, d_work, stream));
     const bool kp = p.kp_on != 0 && sweep_idx > 0;
-    if (kp) KCS_TRY(do_model_pass(g, S, d_params, d_work, Q, stream));
+    if (kp) KCS_TRY(do_model_pass(g, S, n_maps(k), d_params, d_work, Q, stream));
     for (int32_t q = 0; q < Q; ++q) KCS_TRY(do_osl(g, S, p, kp, d_sino, q, Q, d_x, d_work, stream));
-    return do_lm(g, S, p, lm, d_x, d_params, d_lambda, d_work, Q, lm.restart != 0, stream);
+    return do_lm(g, S, n_maps(k), p, lm, d_x, d_params, d_lambda, d_work, Q, lm.restart != 0, stream);
 }
 
 // ----- static scratch of kcs_icm_sweep_noalloc -----
@@ -1036,7 +1045,8 @@ int kcs_model_tac(const kcs_frames* f, const kcs_kinetics* k, const float* d_par
     KCS_TRY(do_setup(S, d_work, stream));
     const KinTab* K = at<KinTab>(d_work, layout(nullptr, 0, 0).kin);
     return launched(
-        timed(KCS_T_MODEL, stream, [&] { return launch_model(f->n_frames, K, S.fr, d_params, n, d_F, d_J, stream); }),
+        timed(KCS_T_MODEL, stream,
+              [&] { return launch_model(f->n_frames, n_maps(*k), K, S.fr, d_params, n, d_F, d_J, stream); }),
         "model evaluation");
 }
 
@@ -1056,7 +1066,7 @@ int kcs_osl_update(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetic
     KCS_TRY(check_frames(f));
     KCS_TRY(check_plane(g, f->n_frames));
     KCS_TRY(check_kinetics(k));
-    KCS_TRY(check_prior(p));
+    KCS_TRY(check_prior(p, n_maps(*k)));
     KCS_TRY(check_subset(g, q, Q));
     if (!d_sino || !d_x || (p->kp_on && !d_params)) return fail(KCS_EINVAL, "device pointers must not be NULL");
     KCS_TRY(check_work(g, f->n_frames, Q, d_work, work_bytes));
@@ -1064,7 +1074,7 @@ int kcs_osl_update(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetic
     g_err.clear();
     if (p->kp_on) {
         KCS_TRY(do_setup(S, d_work, stream));
-        KCS_TRY(do_model_pass(*g, S, d_params, d_work, Q, stream));
+        KCS_TRY(do_model_pass(*g, S, n_maps(*k), d_params, d_work, Q, stream));
     }
     return do_osl(*g, S, *p, p->kp_on != 0, d_sino, q, Q, d_x, d_work, stream);
 }
@@ -1076,23 +1086,24 @@ int kcs_lm_fit(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics* k
     KCS_TRY(check_frames(f));
     KCS_TRY(check_plane(g, f->n_frames));
     KCS_TRY(check_kinetics(k));
-    KCS_TRY(check_prior(p));
-    KCS_TRY(check_lm(lm));
+    KCS_TRY(check_prior(p, n_maps(*k)));
+    KCS_TRY(check_lm(lm, n_maps(*k)));
     if (!d_x || !d_params || !d_lambda) return fail(KCS_EINVAL, "device pointers must not be NULL");
     KCS_TRY(check_work(g, f->n_frames, 0, d_work, work_bytes));
     const Schedule S = make_schedule(*f, k);
     g_err.clear();
     KCS_TRY(do_setup(S, d_work, stream));
-    return do_lm(*g, S, *p, *lm, d_x, d_params, d_lambda, d_work, 0, false, stream);
+    return do_lm(*g, S, n_maps(*k), *p, *lm, d_x, d_params, d_lambda, d_work, 0, false, stream);
 }
 
-int kcs_init_state(const kcs_geometry* g, const kcs_frames* f, const float* d_sino, const double xi0[3], float* d_x,
-                   float* d_params, float* d_lambda, void* d_work, size_t work_bytes, hipStream_t stream) {
+int kcs_init_state(const kcs_geometry* g, const kcs_frames* f, const float* d_sino, const double* xi0, int32_t n_maps,
+                   float* d_x, float* d_params, float* d_lambda, void* d_work, size_t work_bytes, hipStream_t stream) {
     KCS_TRY(check_geometry(g));
     KCS_TRY(check_frames(f));
     KCS_TRY(check_plane(g, f->n_frames));
     if (!d_sino || !d_x || !d_params || !d_lambda || !xi0) return fail(KCS_EINVAL, "pointers must not be NULL");
-    for (int i = 0; i < 3; ++i)
+    if (n_maps != 3 && n_maps != 4) return fail(KCS_EINVAL, "n_maps must be 3 or 4");
+    for (int i = 0; i < n_maps; ++i)
         if (!is_finite(xi0[i])) return fail(KCS_EINVAL, "xi0 must be finite");
     KCS_TRY(check_work(g, f->n_frames, 0, d_work, work_bytes));
     const Schedule S = make_schedule(*f, nullptr);
@@ -1104,7 +1115,7 @@ int kcs_init_state(const kcs_geometry* g, const kcs_frames* f, const float* d_si
     g_err.clear();
     return launched(timed(KCS_T_INIT, stream,
                           [&] {
-                              return launch_init(f->n_frames, d_sino, rows, S.fr, sumP * g->nz, N, xi0,
+                              return launch_init(f->n_frames, d_sino, rows, S.fr, sumP * g->nz, N, xi0, n_maps,
                                                  at<double>(d_work, L.init), kInitChunks, d_x, d_params, d_lambda,
                                                  stream);
                           }),

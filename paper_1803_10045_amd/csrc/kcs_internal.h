@@ -39,6 +39,7 @@ struct FrameTab {
     float inv_dt[kMaxFrames];  // 1 / dt_m
     float blood[kMaxFrames];   // vb * int_frame Cp
     float dP2[kMaxFrames];     // int_frame P1 (= P2(t1) - P2(t0))
+    float cp_int[kMaxFrames];  // int_frame Cp (blood = vb * cp_int for a blood fraction vb)
     float one_minus_vb;
     float pad[3];
 };

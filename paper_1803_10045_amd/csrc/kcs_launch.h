@@ -29,7 +29,8 @@ struct LmArgs {
     int32_t nx, ny, nz;
     FrameTab fr;
     float beta_h;
-    float delta[3];
+    int32_t np;  // fitted parameters: 3 (K1, k2, k3) or 4 (and the blood fraction vb)
+    float delta[4];
     // 3x3x3 neighbourhood when nbr3d: weights of the through-plane neighbours with 0, 1 or 2
     // in-plane offsets (1 / distance in pixel sides)
     int32_t nbr3d;
@@ -40,7 +41,7 @@ struct LmArgs {
     // Normal-equation state carried between the iterations of one fit (see klm_kernel):
     int32_t have_state;    // 1: J^T J, J^T r and r^T r at the current maps are in `state`
     int32_t need_state;    // 1: leave them in `state` for the next iteration
-    float lo[3], hi[3];
+    float lo[4], hi[4];
 };
 
 // Inputs of the FP64 table-setup kernel.
@@ -172,10 +173,10 @@ hipError_t launch_ki(const float* params, int64_t n, float* ki, hipStream_t st);
 // floats) or copy (kind 1) of bytes (a multiple of 16) for bandwidth measurement.
 size_t stream_read_out_floats(int groups);
 hipError_t launch_stream(int kind, const void* src, void* dst, size_t bytes, int groups, hipStream_t st);
-hipError_t launch_model(int M, const KinTab* K, const FrameTab& fr, const float* params, int64_t n, float* F, float* J,
-                        hipStream_t st);
+hipError_t launch_model(int M, int np, const KinTab* K, const FrameTab& fr, const float* params, int64_t n, float* F,
+                        float* J, hipStream_t st);
 hipError_t launch_init(int M, const float* sino, int64_t rows, const FrameTab& fr, double denom_scale, int32_t nz_ny_nx,
-                       const double xi0[3], double* partial, int32_t n_partial, float* x, float* params, float* lam,
-                       hipStream_t st);
+                       const double* xi0, int32_t np, double* partial, int32_t n_chunks, float* x, float* params,
+                       float* lam, hipStream_t st);
 
 }  // namespace kcs

@@ -27,16 +27,16 @@ __host__ __device__ __forceinline__ float huber(float t, float d) {
 }
 
 // Weighted Huber energy sum_k w_k sum_p H(q_p - xi_kp) over the neighbours k of voxel (i, j, z)
-// in the maps xi (neighbours outside the image dropped), and the gradient terms
+// in the NP maps xi (neighbours outside the image dropped), and the gradient terms
 // psi_p = sum_k w_k clip(q_p - xi_kp, -delta_p, delta_p).  The neighbours are the 8 in-plane ones
 // (weights 1 and 1/sqrt(2)) and, with a.nbr3d, the 18 of the planes z - 1 and z + 1 (weights
 // a.w_plane by the number of in-plane offsets).
 // Adds the terms of the 3x3 neighbours in plane zz of voxel (i, j) (the voxel itself skipped when
 // zz is its own plane); w_edge, w_diag weight neighbours with one and two in-plane offsets.
+template <int NP>
 __host__ __device__ __forceinline__ void plane_terms(const float* __restrict__ xi, const LmArgs& a, int i, int j,
                                                      int zz, bool own, float w_centre, float w_edge, float w_diag,
-                                                     size_t N, float q0, float q1, float q2, float& e,
-                                                     float (&psi)[3]) {
+                                                     size_t N, const float (&q)[NP], float& e, float (&psi)[NP]) {
     const size_t plane = (size_t)a.nx * a.ny;
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
@@ -48,76 +48,95 @@ __host__ __device__ __forceinline__ void plane_terms(const float* __restrict__ x
             const size_t u = (size_t)zz * plane + (size_t)jj * a.nx + ii;
             const int off = (dx != 0) + (dy != 0);
             const float w = off == 0 ? w_centre : (off == 1 ? w_edge : w_diag);
-            const float d0 = q0 - xi[u], d1 = q1 - xi[N + u], d2 = q2 - xi[2 * N + u];
-            psi[0] += w * fminf(fmaxf(d0, -a.delta[0]), a.delta[0]);
-            psi[1] += w * fminf(fmaxf(d1, -a.delta[1]), a.delta[1]);
-            psi[2] += w * fminf(fmaxf(d2, -a.delta[2]), a.delta[2]);
-            e += w * (huber(d0, a.delta[0]) + huber(d1, a.delta[1]) + huber(d2, a.delta[2]));
+            float h = 0.0f;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const float d = q[p] - xi[p * N + u];
+                psi[p] += w * fminf(fmaxf(d, -a.delta[p]), a.delta[p]);
+                h = p == 0 ? huber(d, a.delta[p]) : h + huber(d, a.delta[p]);
+            }
+            e += w * h;
         }
     }
 }
 
-template <bool NBR3D>
+template <int NP, bool NBR3D>
 __host__ __device__ __forceinline__ float neighbour_energy(const float* __restrict__ xi, const LmArgs& a, int i, int j,
-                                                           int z, size_t N, float q0, float q1, float q2,
-                                                           float (&psi)[3]) {
+                                                           int z, size_t N, const float (&q)[NP], float (&psi)[NP]) {
     float e = 0.0f;
-    psi[0] = psi[1] = psi[2] = 0.0f;
-    plane_terms(xi, a, i, j, z, true, 0.0f, 1.0f, 0.70710678118654752f, N, q0, q1, q2, e, psi);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) psi[p] = 0.0f;
+    plane_terms<NP>(xi, a, i, j, z, true, 0.0f, 1.0f, 0.70710678118654752f, N, q, e, psi);
     if (NBR3D) {
 #pragma unroll 1
         for (int dz = -1; dz <= 1; dz += 2) {
             if (z + dz < 0 || z + dz >= a.nz) continue;
-            plane_terms(xi, a, i, j, z + dz, false, a.w_plane[0], a.w_plane[1], a.w_plane[2], N, q0, q1, q2, e, psi);
+            plane_terms<NP>(xi, a, i, j, z + dz, false, a.w_plane[0], a.w_plane[1], a.w_plane[2], N, q, e, psi);
         }
     }
     return e;
 }
 
-// Normal equations of the data term at maps (k1, k2, k3): J^T J (A), J^T r (g) and r^T r (rr).
+// Normal equations of the data term at maps xi: J^T J (packed lower triangle, row by row:
+// A[r(r+1)/2 + c] for c <= r), J^T r (g) and r^T r (rr).  NP(NP + 1)/2 + NP + 1 floats: the
+// per-voxel state a fit carries between iterations (10 for 3 maps, 15 for 4).
+template <int NP>
 struct Normal {
-    float A00, A01, A02, A11, A12, A22, g0, g1, g2, rr;
+    static constexpr int kTri = NP * (NP + 1) / 2;
+    static constexpr int kFloats = kTri + NP + 1;
+    float A[kTri];
+    float g[NP];
+    float rr;
 };
 
-template <int M>
-__host__ __device__ __forceinline__ Normal normal_equations(const FrameTab& fr, const KinTab& K, const float* xv,
-                                                            float k1, float k2, float k3) {
-    Normal n{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    model_frames<M, true, false>(fr, K, k1, k2, k3, [&](int m, float F, float j0, float j1, float j2) {
-        const float r = xv[m] - F;
-        n.A00 = fmaf(j0, j0, n.A00);
-        n.A01 = fmaf(j0, j1, n.A01);
-        n.A02 = fmaf(j0, j2, n.A02);
-        n.A11 = fmaf(j1, j1, n.A11);
-        n.A12 = fmaf(j1, j2, n.A12);
-        n.A22 = fmaf(j2, j2, n.A22);
-        n.g0 = fmaf(j0, r, n.g0);
-        n.g1 = fmaf(j1, r, n.g1);
-        n.g2 = fmaf(j2, r, n.g2);
-        n.rr = fmaf(r, r, n.rr);
-    });
+__host__ __device__ constexpr int tri(int r, int c) { return r * (r + 1) / 2 + c; }
+
+template <int M, int NP>
+__host__ __device__ __forceinline__ Normal<NP> normal_equations(const FrameTab& fr, const KinTab& K, const float* xv,
+                                                                const float (&xi)[NP]) {
+    Normal<NP> n;
+#pragma unroll
+    for (int k = 0; k < Normal<NP>::kTri; ++k) n.A[k] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) n.g[k] = 0.0f;
+    n.rr = 0.0f;
+    model_frames<M, true, false, NP>(fr, K, xi[0], xi[1], xi[2], NP == 4 ? xi[NP - 1] : 0.0f,
+                                     [&](int m, float F, float j0, float j1, float j2, float j3) {
+                                         const float jv[4] = {j0, j1, j2, j3};
+                                         const float r = xv[m] - F;
+#pragma unroll
+                                         for (int rw = 0; rw < NP; ++rw)
+#pragma unroll
+                                             for (int c = 0; c <= rw; ++c)
+                                                 n.A[tri(rw, c)] = fmaf(jv[rw], jv[c], n.A[tri(rw, c)]);
+#pragma unroll
+                                         for (int k = 0; k < NP; ++k) n.g[k] = fmaf(jv[k], r, n.g[k]);
+                                         n.rr = fmaf(r, r, n.rr);
+                                     });
     return n;
 }
 
-__host__ __device__ __forceinline__ Normal load_normal(const float* __restrict__ st, size_t N, size_t v) {
-    return Normal{st[v], st[N + v], st[2 * N + v], st[3 * N + v], st[4 * N + v],
-                  st[5 * N + v], st[6 * N + v], st[7 * N + v], st[8 * N + v], st[9 * N + v]};
+template <int NP>
+__host__ __device__ __forceinline__ Normal<NP> load_normal(const float* __restrict__ st, size_t N, size_t v) {
+    Normal<NP> n;
+#pragma unroll
+    for (int k = 0; k < Normal<NP>::kTri; ++k) n.A[k] = st[k * N + v];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) n.g[k] = st[(Normal<NP>::kTri + k) * N + v];
+    n.rr = st[(Normal<NP>::kFloats - 1) * N + v];
+    return n;
 }
 
-__host__ __device__ __forceinline__ void store_normal(float* __restrict__ st, size_t N, size_t v, const Normal& n) {
-    st[v] = n.A00;
-    st[N + v] = n.A01;
-    st[2 * N + v] = n.A02;
-    st[3 * N + v] = n.A11;
-    st[4 * N + v] = n.A12;
-    st[5 * N + v] = n.A22;
-    st[6 * N + v] = n.g0;
-    st[7 * N + v] = n.g1;
-    st[8 * N + v] = n.g2;
-    st[9 * N + v] = n.rr;
+template <int NP>
+__host__ __device__ __forceinline__ void store_normal(float* __restrict__ st, size_t N, size_t v, const Normal<NP>& n) {
+#pragma unroll
+    for (int k = 0; k < Normal<NP>::kTri; ++k) st[k * N + v] = n.A[k];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) st[(Normal<NP>::kTri + k) * N + v] = n.g[k];
+    st[(Normal<NP>::kFloats - 1) * N + v] = n.rr;
 }
 
-template <int M, bool NBR3D>
+template <int M, int NP, bool NBR3D>
 __host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, const float* __restrict__ x,
                                                   const float* __restrict__ xi_in, float* __restrict__ xi_out,
                                                   float* __restrict__ lam_io, float* __restrict__ state,
@@ -127,62 +146,90 @@ __host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, 
     const size_t v = (size_t)z * plane + (size_t)j * a.nx + i;
 
     const float* xv = x + v * M;
-    const float p0 = xi_in[v], p1 = xi_in[N + v], p2 = xi_in[2 * N + v];
+    float p[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) p[k] = xi_in[k * N + v];
 
     // Huber terms over the neighbours of the previous maps: psi (gradient) and e0 (energy) at the
     // current parameters.  The neighbours are read again for the trial energy below instead of
     // being held in registers through the model evaluations (they are cache hits).
-    float psi[3] = {0.0f, 0.0f, 0.0f};
-    const float e0 = neighbour_energy<NBR3D>(xi_in, a, i, j, z, N, p0, p1, p2, psi);
+    float psi[NP];
+    const float e0 = neighbour_energy<NP, NBR3D>(xi_in, a, i, j, z, N, p, psi);
     // data-term normal equations at the current parameters
-    const Normal n0 = a.have_state ? load_normal(state, N, v) : normal_equations<M>(a.fr, *K, xv, p0, p1, p2);
-    const float A00 = n0.A00, A01 = n0.A01, A02 = n0.A02, A11 = n0.A11, A12 = n0.A12, A22 = n0.A22;
-    const float g0 = n0.g0 - a.beta_h * psi[0];
-    const float g1 = n0.g1 - a.beta_h * psi[1];
-    const float g2 = n0.g2 - a.beta_h * psi[2];
+    const Normal<NP> n0 = a.have_state ? load_normal<NP>(state, N, v) : normal_equations<M, NP>(a.fr, *K, xv, p);
+    float g[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) g[k] = n0.g[k] - a.beta_h * psi[k];
 
     float lam = a.reset_lambda ? 0.0f : lam_io[v];
-    if (!(lam > 0.0f)) lam = a.tau * fmaxf(A00, fmaxf(A11, A22));
+    if (!(lam > 0.0f)) {
+        float dmax = n0.A[tri(NP - 1, NP - 1)];
+#pragma unroll
+        for (int k = NP - 2; k >= 0; --k) dmax = fmaxf(n0.A[tri(k, k)], dmax);
+        lam = a.tau * dmax;
+    }
 
     // (A + lam I) step = g, symmetrically scaled by the inverse square roots of the diagonal,
     // then a Cholesky factorisation in registers
-    const float s0 = 1.0f / sqrtf(A00 + lam), s1 = 1.0f / sqrtf(A11 + lam), s2 = 1.0f / sqrtf(A22 + lam);
-    const float B00 = (A00 + lam) * s0 * s0, B11 = (A11 + lam) * s1 * s1, B22 = (A22 + lam) * s2 * s2;
-    const float B01 = A01 * s0 * s1, B02 = A02 * s0 * s2, B12 = A12 * s1 * s2;
-    const float L00 = sqrtf(B00);
-    const float L10 = B01 / L00, L20 = B02 / L00;
-    const float L11 = sqrtf(fmaxf(B11 - L10 * L10, 1e-30f));
-    const float L21 = (B12 - L20 * L10) / L11;
-    const float L22 = sqrtf(fmaxf(B22 - L20 * L20 - L21 * L21, 1e-30f));
-    const float y0 = g0 * s0 / L00;
-    const float y1 = (g1 * s1 - L10 * y0) / L11;
-    const float y2 = (g2 * s2 - L20 * y0 - L21 * y1) / L22;
-    const float z2 = y2 / L22;
-    const float z1 = (y1 - L21 * z2) / L11;
-    const float z0 = (y0 - L10 * z1 - L20 * z2) / L00;
-    const float q0 = fminf(fmaxf(p0 + z0 * s0, a.lo[0]), a.hi[0]);
-    const float q1 = fminf(fmaxf(p1 + z1 * s1, a.lo[1]), a.hi[1]);
-    const float q2 = fminf(fmaxf(p2 + z2 * s2, a.lo[2]), a.hi[2]);
+    float sc[NP], B[Normal<NP>::kTri], L[Normal<NP>::kTri];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) sc[k] = 1.0f / sqrtf(n0.A[tri(k, k)] + lam);
+#pragma unroll
+    for (int r = 0; r < NP; ++r)
+#pragma unroll
+        for (int c = 0; c <= r; ++c)
+            B[tri(r, c)] = c == r ? (n0.A[tri(r, r)] + lam) * sc[r] * sc[r] : n0.A[tri(r, c)] * sc[c] * sc[r];
+#pragma unroll
+    for (int r = 0; r < NP; ++r) {
+#pragma unroll
+        for (int c = 0; c < r; ++c) {
+            float acc = B[tri(r, c)];
+#pragma unroll
+            for (int k = 0; k < c; ++k) acc = acc - L[tri(r, k)] * L[tri(c, k)];
+            L[tri(r, c)] = acc / L[tri(c, c)];
+        }
+        float acc = B[tri(r, r)];
+#pragma unroll
+        for (int k = 0; k < r; ++k) acc = acc - L[tri(r, k)] * L[tri(r, k)];
+        L[tri(r, r)] = r == 0 ? sqrtf(acc) : sqrtf(fmaxf(acc, 1e-30f));
+    }
+    float y[NP], zz[NP];
+#pragma unroll
+    for (int r = 0; r < NP; ++r) {
+        float acc = g[r] * sc[r];
+#pragma unroll
+        for (int k = 0; k < r; ++k) acc = acc - L[tri(r, k)] * y[k];
+        y[r] = acc / L[tri(r, r)];
+    }
+#pragma unroll
+    for (int r = NP - 1; r >= 0; --r) {
+        float acc = y[r];
+#pragma unroll
+        for (int k = r + 1; k < NP; ++k) acc = acc - L[tri(k, r)] * zz[k];
+        zz[r] = acc / L[tri(r, r)];
+    }
+    float q[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) q[k] = fminf(fmaxf(p[k] + zz[k] * sc[k], a.lo[k]), a.hi[k]);
 
-    float unused[3];
-    const float e1 = neighbour_energy<NBR3D>(xi_in, a, i, j, z, N, q0, q1, q2, unused);
+    float unused[NP];
+    const float e1 = neighbour_energy<NP, NBR3D>(xi_in, a, i, j, z, N, q, unused);
 
     // data term at the trial parameters, with its normal equations (the next iteration's when
     // the step is kept).  The last iteration of a fit needs only r'^T r', but evaluating it the
     // same way in every iteration makes a fit of n iterations round exactly like n calls of one
     // iteration each, whatever the call pattern.
-    const Normal n1 = normal_equations<M>(a.fr, *K, xv, q0, q1, q2);
+    const Normal<NP> n1 = normal_equations<M, NP>(a.fr, *K, xv, q);
     const float dphi = fmaf(a.beta_h, e1 - e0, 0.5f * (n1.rr - n0.rr));
     const float phi0 = fmaf(a.beta_h, e0, 0.5f * n0.rr);
     const bool accept = dphi < -a.eta * phi0;
-    xi_out[v] = accept ? q0 : p0;
-    xi_out[N + v] = accept ? q1 : p1;
-    xi_out[2 * N + v] = accept ? q2 : p2;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) xi_out[k * N + v] = accept ? q[k] : p[k];
     lam_io[v] = accept ? fmaxf(lam * 0.1f, a.lam_min) : fminf(lam * 10.0f, a.lam_max);
     // the state holds the normal equations of the maps this iteration leaves
     if (a.need_state) {
-        if (accept) store_normal(state, N, v, n1);
-        else if (!a.have_state) store_normal(state, N, v, n0);
+        if (accept) store_normal<NP>(state, N, v, n1);
+        else if (!a.have_state) store_normal<NP>(state, N, v, n0);
     }
 }
 
@@ -190,7 +237,7 @@ uint32_t lm_groups(int nx, int ny, int nz) {
     return (uint32_t)((nx + kLmTileX - 1) / kLmTileX) * ((ny + kLmTileY - 1) / kLmTileY) * nz;
 }
 
-template <int M, bool NBR3D, class Src>
+template <int M, int NP, bool NBR3D, class Src>
 __global__ __launch_bounds__(256) void klm_kernel(Src src) {
     const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
     const LmJob& J = src.find(w);
@@ -202,37 +249,41 @@ __global__ __launch_bounds__(256) void klm_kernel(Src src) {
     const int j = (rr / tx) * kLmTileY + threadIdx.x / kLmTileX;
     const int i = (rr % tx) * kLmTileX + threadIdx.x % kLmTileX;
     if (z >= a.nz || i >= a.nx || j >= a.ny) return;
-    lm_voxel<M, NBR3D>(J.K, J.x, J.xi_in, J.xi_out, J.lam, J.state, a, i, j, z);
+    lm_voxel<M, NP, NBR3D>(J.K, J.x, J.xi_in, J.xi_out, J.lam, J.state, a, i, j, z);
 }
 
-// All jobs of one launch share the neighbourhood (nbr3d), so that the in-plane kernel carries no
-// code or registers for the 3x3x3 case.
-template <bool NBR3D, class Src>
+// All jobs of one launch share the neighbourhood (nbr3d) and the number of fitted maps (np), so
+// that the in-plane three-map kernel carries no code or registers for the other cases.
+template <int NP, bool NBR3D, class Src>
 static hipError_t dispatch_lm_m(int M, Src src, uint32_t groups, hipStream_t st) {
     const dim3 g(xcd_round_up(groups)), b(kLmTileX * kLmTileY);
     switch (M) {
-        case 8: hipLaunchKernelGGL((klm_kernel<8, NBR3D, Src>), g, b, 0, st, src); break;
-        case 16: hipLaunchKernelGGL((klm_kernel<16, NBR3D, Src>), g, b, 0, st, src); break;
-        case 24: hipLaunchKernelGGL((klm_kernel<24, NBR3D, Src>), g, b, 0, st, src); break;
-        case 32: hipLaunchKernelGGL((klm_kernel<32, NBR3D, Src>), g, b, 0, st, src); break;
+        case 8: hipLaunchKernelGGL((klm_kernel<8, NP, NBR3D, Src>), g, b, 0, st, src); break;
+        case 16: hipLaunchKernelGGL((klm_kernel<16, NP, NBR3D, Src>), g, b, 0, st, src); break;
+        case 24: hipLaunchKernelGGL((klm_kernel<24, NP, NBR3D, Src>), g, b, 0, st, src); break;
+        case 32: hipLaunchKernelGGL((klm_kernel<32, NP, NBR3D, Src>), g, b, 0, st, src); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 template <class Src>
-static hipError_t dispatch_lm(int M, bool nbr3d, Src src, uint32_t groups, hipStream_t st) {
-    return nbr3d ? dispatch_lm_m<true>(M, src, groups, st) : dispatch_lm_m<false>(M, src, groups, st);
+static hipError_t dispatch_lm(int M, int np, bool nbr3d, Src src, uint32_t groups, hipStream_t st) {
+    if (np == 4)
+        return nbr3d ? dispatch_lm_m<4, true>(M, src, groups, st) : dispatch_lm_m<4, false>(M, src, groups, st);
+    if (np == 3)
+        return nbr3d ? dispatch_lm_m<3, true>(M, src, groups, st) : dispatch_lm_m<3, false>(M, src, groups, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_lm(int M, const KinTab* K, const float* x, const float* xi_in, float* xi_out, float* lam,
                      float* state, const LmArgs& a, hipStream_t st) {
     OneJob<LmJob> src{LmJob{a, K, x, xi_in, xi_out, lam, state, 0}};
-    return dispatch_lm(M, a.nbr3d != 0, src, lm_groups(a.nx, a.ny, a.nz), st);
+    return dispatch_lm(M, a.np, a.nbr3d != 0, src, lm_groups(a.nx, a.ny, a.nz), st);
 }
 
 hipError_t launch_lm_jobs(int M, bool nbr3d, JobTable<LmJob> jobs, uint32_t groups, hipStream_t st) {
-    return dispatch_lm(M, nbr3d, jobs, groups, st);
+    return dispatch_lm(M, 3, nbr3d, jobs, groups, st);
 }
 
 }  // namespace kcs

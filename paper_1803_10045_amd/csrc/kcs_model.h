@@ -128,14 +128,18 @@ __host__ __device__ __forceinline__ void boundary_J(const KinTab& K, const Bound
     if (DERIV) dJ = K.w[0] * dJp + K.w[1] * dJi[0] + K.w[2] * dJi[1] + K.w[3] * dJi[2];
 }
 
-// Calls sink(m, F_m, dF/dK1, dF/dk2, dF/dk3) for every frame m (derivatives 0 when !DERIV).
+// Calls sink(m, F_m, dF/dK1, dF/dk2, dF/dk3, dF/dvb) for every frame m (derivatives 0 when
+// !DERIV).  NP = 3: the blood fraction is the study's (FT.one_minus_vb, FT.blood) and vb is
+// ignored; NP = 4: it is the voxel's vb (the fourth fitted parameter), and
+// dF/dvb = (int_frame Cp - int_frame C_T) / dt.
 // UNROLL = false keeps the frame loop rolled (small code, few registers; the sink then sees a
 // run-time frame index and must not index register arrays with it).
-template <int M, bool DERIV, bool UNROLL = true, class Sink>
+template <int M, bool DERIV, bool UNROLL = true, int NP = 3, class Sink>
 __host__ __device__ __forceinline__ void model_frames(const FrameTab& FT, const KinTab& K, float K1, float k2, float k3,
-                                             Sink&& sink) {
+                                             float vb, Sink&& sink) {
+    static_assert(NP == 3 || NP == 4, "3 or 4 parameters");
     const VoxelRates R = voxel_rates(K, k2, k3);
-    const float g = FT.one_minus_vb;
+    const float g = NP == 4 ? 1.0f - vb : FT.one_minus_vb;
     float Jprev = 0.0f, dJprev = 0.0f;
 #pragma unroll(UNROLL ? M : 2)
     for (int m = 0; m < M; ++m) {
@@ -144,16 +148,18 @@ __host__ __device__ __forceinline__ void model_frames(const FrameTab& FT, const 
         boundary_J<DERIV>(K, K.b[K.i1[m]], R, J1, dJ1);
         const float dJ = J1 - Jprev;
         const float tis = FT.dP2[m] - k2 * dJ;
-        const float F = FT.inv_dt[m] * fmaf(g * K1, tis, FT.blood[m]);
-        float d0 = 0.0f, d1 = 0.0f, d2 = 0.0f;
+        const float blood = NP == 4 ? vb * FT.cp_int[m] : FT.blood[m];
+        const float F = FT.inv_dt[m] * fmaf(g * K1, tis, blood);
+        float d0 = 0.0f, d1 = 0.0f, d2 = 0.0f, d3 = 0.0f;
         if (DERIV) {
             const float ddJ = dJ1 - dJprev;
             const float s = g * FT.inv_dt[m];
             d0 = s * tis;
             d1 = -s * K1 * fmaf(k2, ddJ, dJ);
             d2 = -s * K1 * k2 * ddJ;
+            if (NP == 4) d3 = FT.inv_dt[m] * (FT.cp_int[m] - K1 * tis);
         }
-        sink(m, F, d0, d1, d2);
+        sink(m, F, d0, d1, d2, d3);
         Jprev = J1;
         dJprev = dJ1;
     }

@@ -35,7 +35,9 @@ hipError_t launch_setup(const SetupArgs& s, KinTab* K, hipStream_t st) {
 // ---------------------------------------------------------------------------------------------
 uint32_t model_groups(int64_t n) { return (uint32_t)((n + 255) / 256); }
 
-template <int M, bool JAC, class Src>
+// F (and with JAC the Jacobian, [n][M][NP]) of n voxels whose maps are params [NP][n]: NP = 3
+// (K1, k2, k3; the study's blood fraction) or 4 (plus the voxel's blood fraction vb).
+template <int M, bool JAC, int NP, class Src>
 __global__ __launch_bounds__(256) void kmodel_kernel(Src src) {
     const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
     const ModelJob& Jb = src.find(w);
@@ -43,32 +45,34 @@ __global__ __launch_bounds__(256) void kmodel_kernel(Src src) {
     const int64_t v = (int64_t)(w - Jb.w0) * 256 + threadIdx.x;
     if (v >= n) return;
     const float* params = Jb.params;
-    float f[M], jac[JAC ? 3 * M : 1];
-    model_frames<M, JAC>(Jb.fr, *Jb.K, params[v], params[n + v], params[2 * n + v],
-                         [&](int m, float Fm, float a, float b, float c) {
-                             f[m] = Fm;
-                             if (JAC) {
-                                 jac[3 * m] = a;
-                                 jac[3 * m + 1] = b;
-                                 jac[3 * m + 2] = c;
-                             }
-                         });
+    float f[M], jac[JAC ? NP * M : 1];
+    model_frames<M, JAC, true, NP>(Jb.fr, *Jb.K, params[v], params[n + v], params[2 * n + v],
+                                   NP == 4 ? params[3 * n + v] : 0.0f,
+                                   [&](int m, float Fm, float a, float b, float c, float d) {
+                                       f[m] = Fm;
+                                       if (JAC) {
+                                           jac[NP * m] = a;
+                                           jac[NP * m + 1] = b;
+                                           jac[NP * m + 2] = c;
+                                           if (NP == 4) jac[NP * m + 3] = d;
+                                       }
+                                   });
     store_record<M>(Jb.F + v * M, f);
     if (JAC) {
 #pragma unroll
-        for (int k = 0; k < 3 * M; ++k) Jb.J[v * 3 * M + k] = jac[k];
+        for (int k = 0; k < NP * M; ++k) Jb.J[v * NP * M + k] = jac[k];
     }
 }
 
-template <class Src>
-static hipError_t dispatch_model(int M, bool jac, Src src, uint32_t groups, hipStream_t st) {
+template <int NP, class Src>
+static hipError_t dispatch_model_np(int M, bool jac, Src src, uint32_t groups, hipStream_t st) {
     const dim3 g(xcd_round_up(groups)), b(256);
 #define KCS_MODEL_CASE(MM)                                                                   \
     case MM:                                                                                 \
         if (jac)                                                                             \
-            hipLaunchKernelGGL((kmodel_kernel<MM, true, Src>), g, b, 0, st, src);            \
+            hipLaunchKernelGGL((kmodel_kernel<MM, true, NP, Src>), g, b, 0, st, src);        \
         else                                                                                 \
-            hipLaunchKernelGGL((kmodel_kernel<MM, false, Src>), g, b, 0, st, src);           \
+            hipLaunchKernelGGL((kmodel_kernel<MM, false, NP, Src>), g, b, 0, st, src);       \
         break;
     switch (M) {
         KCS_MODEL_CASE(8)
@@ -81,14 +85,21 @@ static hipError_t dispatch_model(int M, bool jac, Src src, uint32_t groups, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_model(int M, const KinTab* K, const FrameTab& fr, const float* params, int64_t n, float* F, float* J,
-                        hipStream_t st) {
+template <class Src>
+static hipError_t dispatch_model(int M, int np, bool jac, Src src, uint32_t groups, hipStream_t st) {
+    if (np == 4) return dispatch_model_np<4>(M, jac, src, groups, st);
+    if (np == 3) return dispatch_model_np<3>(M, jac, src, groups, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_model(int M, int np, const KinTab* K, const FrameTab& fr, const float* params, int64_t n, float* F,
+                        float* J, hipStream_t st) {
     OneJob<ModelJob> src{ModelJob{fr, K, params, n, F, J, 0}};
-    return dispatch_model(M, J != nullptr, src, model_groups(n), st);
+    return dispatch_model(M, np, J != nullptr, src, model_groups(n), st);
 }
 
 hipError_t launch_model_jobs(int M, JobTable<ModelJob> jobs, uint32_t groups, hipStream_t st) {
-    return dispatch_model(M, false, jobs, groups, st);
+    return dispatch_model(M, 3, false, jobs, groups, st);
 }
 
 // Net uptake rate K_i = K1 k3 / (k2 + k3) per voxel (the macro-parameter of Sec. IV); where
@@ -152,36 +163,43 @@ __global__ void init_frame_kernel(const double* __restrict__ partial, int32_t n_
     x0[m] = fmax(net, 1.0) / ((double)fr.E[m] * denom_scale);
 }
 
+// Initial maps: the np values of xi0 (K1, k2, k3 and, with np = 4, the blood fraction).
+struct InitMaps {
+    float v[4];
+    int32_t np;
+};
+
 template <int M>
-__global__ __launch_bounds__(256) void init_fill_kernel(const double* __restrict__ x0, int64_t N, double xi0_0,
-                                                        double xi0_1, double xi0_2, float* __restrict__ x,
-                                                        float* __restrict__ params, float* __restrict__ lam) {
+__global__ __launch_bounds__(256) void init_fill_kernel(const double* __restrict__ x0, int64_t N, InitMaps xi0,
+                                                        float* __restrict__ x, float* __restrict__ params,
+                                                        float* __restrict__ lam) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= N) return;
     float r[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) r[m] = (float)x0[m];
     store_record<M>(x + v * M, r);
-    params[v] = (float)xi0_0;
-    params[N + v] = (float)xi0_1;
-    params[2 * N + v] = (float)xi0_2;
+    for (int k = 0; k < xi0.np; ++k) params[k * N + v] = xi0.v[k];
     lam[v] = 0.0f;
 }
 
 hipError_t launch_init(int M, const float* sino, int64_t rows, const FrameTab& fr, double denom_scale, int32_t N,
-                       const double xi0[3], double* partial, int32_t n_chunks, float* x, float* params, float* lam,
-                       hipStream_t st) {
+                       const double* xi0, int32_t np, double* partial, int32_t n_chunks, float* x, float* params,
+                       float* lam, hipStream_t st) {
     const int64_t threads = (int64_t)n_chunks * M;
     hipLaunchKernelGGL(init_partial_kernel, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, st, sino, rows, M,
                        n_chunks, partial);
     double* x0 = partial + (int64_t)n_chunks * M;
     hipLaunchKernelGGL(init_frame_kernel, dim3(1), dim3(kMaxFrames), 0, st, partial, n_chunks, rows, fr, denom_scale, x0);
     const uint32_t blocks = (uint32_t)((N + 255) / 256);
+    InitMaps im{};
+    im.np = np;
+    for (int k = 0; k < np; ++k) im.v[k] = (float)xi0[k];
     switch (M) {
-        case 8: hipLaunchKernelGGL((init_fill_kernel<8>), dim3(blocks), dim3(256), 0, st, x0, (int64_t)N, xi0[0], xi0[1], xi0[2], x, params, lam); break;
-        case 16: hipLaunchKernelGGL((init_fill_kernel<16>), dim3(blocks), dim3(256), 0, st, x0, (int64_t)N, xi0[0], xi0[1], xi0[2], x, params, lam); break;
-        case 24: hipLaunchKernelGGL((init_fill_kernel<24>), dim3(blocks), dim3(256), 0, st, x0, (int64_t)N, xi0[0], xi0[1], xi0[2], x, params, lam); break;
-        case 32: hipLaunchKernelGGL((init_fill_kernel<32>), dim3(blocks), dim3(256), 0, st, x0, (int64_t)N, xi0[0], xi0[1], xi0[2], x, params, lam); break;
+        case 8: hipLaunchKernelGGL((init_fill_kernel<8>), dim3(blocks), dim3(256), 0, st, x0, (int64_t)N, im, x, params, lam); break;
+        case 16: hipLaunchKernelGGL((init_fill_kernel<16>), dim3(blocks), dim3(256), 0, st, x0, (int64_t)N, im, x, params, lam); break;
+        case 24: hipLaunchKernelGGL((init_fill_kernel<24>), dim3(blocks), dim3(256), 0, st, x0, (int64_t)N, im, x, params, lam); break;
+        case 32: hipLaunchKernelGGL((init_fill_kernel<32>), dim3(blocks), dim3(256), 0, st, x0, (int64_t)N, im, x, params, lam); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

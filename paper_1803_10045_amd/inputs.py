@@ -39,6 +39,9 @@ LM_TAU = 1e-3
 LM_LAM_MIN, LM_LAM_MAX = 1e-8, 1e8
 LM_LO = (0.0, 1e-4, 0.0)
 LM_HI = (2.0, 2.0, 1.0)
+# With the blood fraction fitted as a fourth map: its initial value and box.
+XI0_VB = VB
+LM_LO_VB, LM_HI_VB = 0.0, 1.0
 # A step is kept only if it lowers the voxel objective by more than this fraction of its value:
 # the fit of a voxel counts as converged to this relative tolerance of its objective, and a
 # step that gains less is treated as no progress (rejected, damping raised).

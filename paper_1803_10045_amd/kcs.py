@@ -50,17 +50,17 @@ class c_frames(ctypes.Structure):
 
 
 class c_kinetics(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_double) for n in ("A1", "A2", "A3", "l1", "l2", "l3", "vb")]
+    _fields_ = [(n, ctypes.c_double) for n in ("A1", "A2", "A3", "l1", "l2", "l3", "vb")] + [("fit_vb", ctypes.c_int32)]
 
 
 class c_prior(ctypes.Structure):
     _fields_ = [("beta_kp", ctypes.c_double), ("eps_F", ctypes.c_double), ("beta_h", ctypes.c_double),
-                ("delta", ctypes.c_double * 3), ("kp_on", ctypes.c_int32), ("plane_ratio", ctypes.c_double)]
+                ("delta", ctypes.c_double * 4), ("kp_on", ctypes.c_int32), ("plane_ratio", ctypes.c_double)]
 
 
 class c_lm_opts(ctypes.Structure):
     _fields_ = [("n_iter", ctypes.c_int32), ("tau", ctypes.c_double), ("lam_min", ctypes.c_double),
-                ("lam_max", ctypes.c_double), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("lam_max", ctypes.c_double), ("lo", ctypes.c_double * 4), ("hi", ctypes.c_double * 4),
                 ("eta", ctypes.c_double), ("restart", ctypes.c_int32)]
 
 
@@ -91,7 +91,7 @@ def lib() -> ctypes.CDLL:
                                  vp]
     L.kcs_lm_fit.argtypes = [P(c_geometry), P(c_frames), P(c_kinetics), P(c_prior), P(c_lm_opts), vp, vp, vp, vp, sz,
                              vp]
-    L.kcs_init_state.argtypes = [P(c_geometry), P(c_frames), vp, P(ctypes.c_double), vp, vp, vp, vp, sz, vp]
+    L.kcs_init_state.argtypes = [P(c_geometry), P(c_frames), vp, P(ctypes.c_double), i32, vp, vp, vp, vp, sz, vp]
     L.kcs_icm_sweep.argtypes = [P(c_geometry), P(c_frames), P(c_kinetics), P(c_prior), P(c_lm_opts), vp, i32, i32, vp,
                                 vp, vp, vp, sz, vp]
     L.kcs_icm_sweep_noalloc.argtypes = [P(c_geometry), P(c_frames), P(c_kinetics), P(c_prior), P(c_lm_opts), vp, i32,
@@ -182,9 +182,14 @@ class Kinetics:
     l2: float
     l3: float
     vb: float
+    fit_vb: bool = False  # True: the blood fraction is a fourth map (maps [4][...]), vb unused
+
+    @property
+    def n_maps(self) -> int:
+        return 4 if self.fit_vb else 3
 
     def c(self) -> c_kinetics:
-        return c_kinetics(self.A1, self.A2, self.A3, self.l1, self.l2, self.l3, self.vb)
+        return c_kinetics(self.A1, self.A2, self.A3, self.l1, self.l2, self.l3, self.vb, int(self.fit_vb))
 
 
 @dataclass(frozen=True)
@@ -197,7 +202,8 @@ class Prior:
     plane_ratio: float = 0.0  # 0: in-plane 3x3 neighbourhood; > 0: 3x3x3, planes this many pixel sides apart
 
     def c(self) -> c_prior:
-        return c_prior(self.beta_kp, self.eps_F, self.beta_h, (ctypes.c_double * 3)(*self.delta), int(self.kp_on),
+        d = tuple(self.delta) + (tuple(self.delta)[-1],) * (4 - len(self.delta))  # 3 maps: delta[3] unused
+        return c_prior(self.beta_kp, self.eps_F, self.beta_h, (ctypes.c_double * 4)(*d), int(self.kp_on),
                        float(self.plane_ratio))
 
 
@@ -213,8 +219,10 @@ class LMOptions:
     restart: bool = True  # ICM sweeps: every sweep's fit starts lambda afresh (False: carries it over)
 
     def c(self) -> c_lm_opts:
-        return c_lm_opts(self.n_iter, self.tau, self.lam_min, self.lam_max, (ctypes.c_double * 3)(*self.lo),
-                         (ctypes.c_double * 3)(*self.hi), self.eta, int(self.restart))
+        lo = tuple(self.lo) + (0.0,) * (4 - len(self.lo))  # blood-fraction bounds, read with fit_vb only
+        hi = tuple(self.hi) + (1.0,) * (4 - len(self.hi))
+        return c_lm_opts(self.n_iter, self.tau, self.lam_min, self.lam_max, (ctypes.c_double * 4)(*lo),
+                         (ctypes.c_double * 4)(*hi), self.eta, int(self.restart))
 
 
 # ----------------------------------------------------------------------------------------------
@@ -292,10 +300,11 @@ def kcs_backproject(g: Geometry, f: Frames, y, q: int, Q: int, b, sens=None, str
 
 def kcs_model_tac(f: Frames, k: Kinetics, params, F, J=None, work=None, stream=None):
     n = params.shape[1]
+    P = k.n_maps
     fc, kc = f.c(), k.c()
     wp, wn = _work(work)
-    _check(lib().kcs_model_tac(ctypes.byref(fc), ctypes.byref(kc), _ptr(params, (3, n), "params"), n,
-                               _ptr(F, (n, f.M), "F"), _ptr(J, (n, f.M, 3), "J"), wp, wn, _stream(stream)))
+    _check(lib().kcs_model_tac(ctypes.byref(fc), ctypes.byref(kc), _ptr(params, (P, n), "params"), n,
+                               _ptr(F, (n, f.M), "F"), _ptr(J, (n, f.M, P), "J"), wp, wn, _stream(stream)))
 
 
 def kcs_ki_map(params, ki, stream=None):
@@ -311,7 +320,7 @@ def kcs_osl_update(g: Geometry, f: Frames, k: Kinetics, p: Prior, sino, params, 
     wp, wn = _work(work)
     _check(lib().kcs_osl_update(ctypes.byref(gc), ctypes.byref(fc), ctypes.byref(kc), ctypes.byref(pc),
                                 _ptr(sino, (g.nz, g.n_ang, g.n_bin, f.M), "sino"),
-                                _ptr(params, (3, g.nz, g.ny, g.nx), "params"), q, Q,
+                                _ptr(params, (k.n_maps, g.nz, g.ny, g.nx), "params"), q, Q,
                                 _ptr(x, (g.nz, g.ny, g.nx, f.M), "x"), wp, wn, _stream(stream)))
 
 
@@ -319,17 +328,20 @@ def kcs_lm_fit(g: Geometry, f: Frames, k: Kinetics, p: Prior, lm: LMOptions, x, 
     gc, fc, kc, pc, lc = g.c(), f.c(), k.c(), p.c(), lm.c()
     wp, wn = _work(work)
     _check(lib().kcs_lm_fit(ctypes.byref(gc), ctypes.byref(fc), ctypes.byref(kc), ctypes.byref(pc), ctypes.byref(lc),
-                            _ptr(x, (g.nz, g.ny, g.nx, f.M), "x"), _ptr(params, (3, g.nz, g.ny, g.nx), "params"),
+                            _ptr(x, (g.nz, g.ny, g.nx, f.M), "x"), _ptr(params, (k.n_maps, g.nz, g.ny, g.nx), "params"),
                             _ptr(lam, (g.nz, g.ny, g.nx), "lambda"), wp, wn, _stream(stream)))
 
 
 def kcs_init_state(g: Geometry, f: Frames, sino, xi0, x, params, lam, work, stream=None):
+    """xi0: 3 initial map values (K1, k2, k3), or 4 with the blood fraction (params [len(xi0)][...])."""
     gc, fc = g.c(), f.c()
-    xi = (ctypes.c_double * 3)(*xi0)
+    P = len(xi0)
+    xi = (ctypes.c_double * P)(*xi0)
     wp, wn = _work(work)
     _check(lib().kcs_init_state(ctypes.byref(gc), ctypes.byref(fc), _ptr(sino, (g.nz, g.n_ang, g.n_bin, f.M), "sino"),
-                                xi, _ptr(x, (g.nz, g.ny, g.nx, f.M), "x"), _ptr(params, (3, g.nz, g.ny, g.nx), "params"),
-                                _ptr(lam, (g.nz, g.ny, g.nx), "lambda"), wp, wn, _stream(stream)))
+                                xi, P, _ptr(x, (g.nz, g.ny, g.nx, f.M), "x"),
+                                _ptr(params, (P, g.nz, g.ny, g.nx), "params"), _ptr(lam, (g.nz, g.ny, g.nx), "lambda"),
+                                wp, wn, _stream(stream)))
 
 
 def kcs_icm_sweep(g: Geometry, f: Frames, k: Kinetics, p: Prior, lm: LMOptions, sino, Q: int, sweep_idx: int, x,
@@ -338,7 +350,7 @@ def kcs_icm_sweep(g: Geometry, f: Frames, k: Kinetics, p: Prior, lm: LMOptions, 
     wp, wn = _work(work)
     _check(lib().kcs_icm_sweep(ctypes.byref(gc), ctypes.byref(fc), ctypes.byref(kc), ctypes.byref(pc),
                                ctypes.byref(lc), _ptr(sino, (g.nz, g.n_ang, g.n_bin, f.M), "sino"), Q, sweep_idx,
-                               _ptr(x, (g.nz, g.ny, g.nx, f.M), "x"), _ptr(params, (3, g.nz, g.ny, g.nx), "params"),
+                               _ptr(x, (g.nz, g.ny, g.nx, f.M), "x"), _ptr(params, (k.n_maps, g.nz, g.ny, g.nx), "params"),
                                _ptr(lam, (g.nz, g.ny, g.nx), "lambda"), wp, wn, _stream(stream)))
 
 
@@ -349,14 +361,14 @@ def kcs_icm_sweep_noalloc(g: Geometry, f: Frames, k: Kinetics, p: Prior, lm: LMO
     _check(lib().kcs_icm_sweep_noalloc(ctypes.byref(gc), ctypes.byref(fc), ctypes.byref(kc), ctypes.byref(pc),
                                        ctypes.byref(lc), _ptr(sino, (g.nz, g.n_ang, g.n_bin, f.M), "sino"), Q,
                                        sweep_idx, _ptr(x, (g.nz, g.ny, g.nx, f.M), "x"),
-                                       _ptr(params, (3, g.nz, g.ny, g.nx), "params"),
+                                       _ptr(params, (k.n_maps, g.nz, g.ny, g.nx), "params"),
                                        _ptr(lam, (g.nz, g.ny, g.nx), "lambda"), _stream(stream)))
 
 
 @dataclass
 class Study:
     """One study of a batched plan: its constants, its sweep range and its device buffers
-    (sino (nz, n_ang, n_bin, M), x (nz, ny, nx, M), params (3, nz, ny, nx), lam (nz, ny, nx),
+    (sino (nz, n_ang, n_bin, M), x (nz, ny, nx, M), params (k.n_maps, nz, ny, nx), lam (nz, ny, nx),
     work: uint8 workspace of kcs_workspace_bytes(g, M, Q) bytes)."""
     g: Geometry
     f: Frames
@@ -377,7 +389,8 @@ class Study:
         wp, wn = _work(self.work)
         return c_study(g.c(), self.f.c(), self.k.c(), self.p.c(), self.lm.c(), self.Q, self.sweep_begin,
                        self.sweep_end, _ptr(self.sino, (g.nz, g.n_ang, g.n_bin, M), "sino"),
-                       _ptr(self.x, (g.nz, g.ny, g.nx, M), "x"), _ptr(self.params, (3, g.nz, g.ny, g.nx), "params"),
+                       _ptr(self.x, (g.nz, g.ny, g.nx, M), "x"),
+                       _ptr(self.params, (self.k.n_maps, g.nz, g.ny, g.nx), "params"),
                        _ptr(self.lam, (g.nz, g.ny, g.nx), "lambda"), wp, wn)
 
 

@@ -237,13 +237,19 @@ class Completion:
 
 def serve(requests: Sequence[Request], budget_bytes: int, executor, keep_results: bool = False,
           max_in_flight: int = 2, lane_of: Optional[Callable[[Request], int]] = None,
-          lane_batch: Optional[Sequence[int]] = None, log: Optional[Callable[[str], None]] = None):
+          lane_batch: Optional[Sequence[int]] = None, log: Optional[Callable[[str], None]] = None,
+          small_in_flight_beside_large: int = 1):
     """Serves `requests` in real time (arrival times in seconds from the start).  Returns
     (completions, results, makespan_s, ticks); completion times come from the executor's clock
     (GPU events on the lane streams).  `lane_batch[i]` caps the studies per tick of lane i (0: all
-    resident ones).  Each lane keeps at most `max_in_flight` ticks enqueued
-    ahead of the GPU; a finished study's memory returns to the budget once its last tick has
-    completed."""
+    resident ones).  Each lane keeps at most `max_in_flight` ticks enqueued ahead of the GPU; while
+    the last lane (the large studies) has a tick on the GPU the other lanes start at most
+    `small_in_flight_beside_large` ticks (streams keep one priority, so this cap is what shares
+    the GPU between them).  Default 1: one small tick beside each large one.  0 makes the small
+    studies wait for the large study to finish, which runs it as fast as alone but holds every
+    small study that arrives meanwhile for a large study's whole duration (at 4 requests/s of the
+    mixed workload the tail latency doubled).  A finished study's memory returns to the budget
+    once its last tick has completed."""
     n_lanes = len(getattr(executor, "lanes", [None]))
     if lane_of is None:
         lane_of = lane_by_traffic() if n_lanes > 1 else (lambda r: 0)
@@ -277,10 +283,14 @@ def serve(requests: Sequence[Request], budget_bytes: int, executor, keep_results
         for s in sched.admit(now):
             executor.load(s)
         progressed = False
+        large_busy = n_lanes > 1 and bool(in_flight[n_lanes - 1])
         for lane in range(n_lanes):
             while in_flight[lane] and executor.done(in_flight[lane][0][0]):
                 retire(lane)
-            if len(in_flight[lane]) >= max_in_flight:
+            cap = max_in_flight
+            if large_busy and lane < n_lanes - 1:
+                cap = min(cap, small_in_flight_beside_large)
+            if len(in_flight[lane]) >= cap:
                 continue
             slots = sched.tick(lane)
             if slots:

@@ -7,7 +7,7 @@ import numpy as np
 import torch
 
 import oracle
-from paper_1803_10045_amd import inputs, kcs
+from paper_1803_10045_amd import kcs
 from kcs_testutil import decision_bound, gpu_accepted, kcs_objects, oracle_decisions, rel_l2
 
 DEV = "cuda"
@@ -32,10 +32,10 @@ class GpuSchedule:
         g, M = self.g, st.frames.M
         self.sino = dev(st.sino)
         self.x = torch.empty((g.nz, g.ny, g.nx, M), device=DEV)
-        self.params = torch.empty((3, g.nz, g.ny, g.nx), device=DEV)
+        self.params = torch.empty((self.k.n_maps, g.nz, g.ny, g.nx), device=DEV)
         self.lam = torch.empty((g.nz, g.ny, g.nx), device=DEV)
         self.work = kcs.alloc_workspace(g, M, st.cfg.Q, DEV)
-        kcs.kcs_init_state(g, self.f, self.sino, inputs.XI0, self.x, self.params, self.lam, self.work)
+        kcs.kcs_init_state(g, self.f, self.sino, oracle.initial_maps(st), self.x, self.params, self.lam, self.work)
         self.init = (self.x.clone(), self.params.clone(), self.lam.clone())
 
     def osl_pass(self, s):
@@ -95,7 +95,7 @@ def run_gpu(st, n_sweeps, eta, lockstep, osl_lockstep_sweeps=None):
         if lockstep and s < n_osl:
             ox, op = host(run.x), host(run.params)
             kp = bool(st.prior.kp_on and s > 0)
-            F = oracle.model_tac(op.reshape(3, -1).T, st.frames.t0, st.frames.t1, st.kin).reshape(ox.shape) if kp else None
+            F = oracle.model_tac(op.reshape(len(op), -1).T, st.frames.t0, st.frames.t1, st.kin).reshape(ox.shape) if kp else None
             for q in range(st.cfg.Q):
                 ox = oracle.osl_update(st.geom, st.frames, st.kin, st.prior, sino, op, ox, q, st.cfg.Q, kp, None, F)
         run.osl_pass(s)
@@ -118,7 +118,7 @@ def run_gpu(st, n_sweeps, eta, lockstep, osl_lockstep_sweeps=None):
                     ratio = np.abs(phi1 - phi0 + eta * phi0) / decision_bound(x, phi0, phi1)
                     worst = max(worst, float(ratio[differ].max()))
                 same = ~differ
-                map_err = max(map_err, max(rel_l2(p1[i][same], op[i][same]) for i in range(3)))
+                map_err = max(map_err, max(rel_l2(p1[i][same], op[i][same]) for i in range(len(op))))
     torch.cuda.synchronize()
     return run, np.stack(lams), np.stack(xs), (n_diff, n_dec, worst, map_err, osl_err)
 
@@ -138,13 +138,21 @@ def check_lockstep(label, eta, stats, max_frac, osl_tol=1e-5):
 
 def check_independent(label, eta, st, gx, gp, ox, op, first, margin, bound, inherited, max_diverged,
                       image_tol=1e-3, margin_check=True):
+    """The oracle's own schedule against the GPU's: the image within image_tol, the maps of the
+    active voxels whose decisions all agreed within 1e-3, every first differing decision of a
+    voxel's own within its bound (margin_check).  The fraction of active voxels that took another
+    path is a measure of how far the near-ties cascade (a flipped fit moves the voxel's maps, the
+    kinetics prior carries them into the image, the neighbours' states follow), not of the kernel's
+    accuracy: it varies with the rounding of every step (e.g. 1.4 % to 2.3 % of the 128x128
+    planes between two builds of the same kernels that round differently), and max_diverged only
+    bounds it loosely."""
     act = (ox * (st.frames.t1 - st.frames.t0)).sum(axis=-1)
     mask = act >= 0.1 * act.max()
     diverged = first >= 0
     keep = mask & ~diverged
     ex = rel_l2(gx, ox)
-    literal = [rel_l2(gp[i][mask], op[i][mask]) for i in range(3)]
-    kept = [rel_l2(gp[i][keep], op[i][keep]) for i in range(3)]
+    literal = [rel_l2(gp[i][mask], op[i][mask]) for i in range(len(op))]
+    kept = [rel_l2(gp[i][keep], op[i][keep]) for i in range(len(op))]
     frac = float(diverged[mask].mean())
     own = diverged & ~inherited
     ratio = margin[own] / bound[own]
@@ -160,3 +168,23 @@ def check_independent(label, eta, st, gx, gp, ox, op, first, margin, bound, inhe
     assert frac <= max_diverged
 
 
+
+
+def gpu_fit_history(g, f, k, p, lm, x, params0, lam0):
+    """A MAP-LM fit through kcs_lm_fit one iteration at a time (host arrays in, lambda recorded
+    after every iteration), checked bit for bit against the same fit in one call.  Returns the
+    final host (params, lam) and the lambda history (n_iter, ...)."""
+    M = x.shape[-1]
+    work = kcs.alloc_workspace(g, M, 0, DEV)
+    xd = dev(x)
+    one = dataclasses.replace(lm, n_iter=1)
+    pd, ld = dev(params0), dev(lam0)
+    hist = []
+    for _ in range(lm.n_iter):
+        kcs.kcs_lm_fit(g, f, k, p, one, xd, pd, ld, work)
+        hist.append(ld.cpu().numpy())
+    pf, lf = dev(params0), dev(lam0)
+    kcs.kcs_lm_fit(g, f, k, p, lm, xd, pf, lf, work)
+    torch.cuda.synchronize()
+    assert torch.equal(pf, pd) and torch.equal(lf, ld), "a fit in one call must round like its iterations"
+    return pd.cpu().numpy(), ld.cpu().numpy(), np.stack(hist)

@@ -19,7 +19,8 @@ def kcs_objects(st):
     g = kcs.Geometry(st.geom.nx, st.geom.ny, st.geom.nz, st.geom.h, st.geom.n_ang, st.geom.n_bin, st.geom.du,
                      st.geom.ang0)
     f = kcs.Frames(st.frames.t0, st.frames.t1, st.frames.E, st.frames.r)
-    k = kcs.Kinetics(st.kin.A1, st.kin.A2, st.kin.A3, st.kin.l1, st.kin.l2, st.kin.l3, st.kin.vb)
+    k = kcs.Kinetics(st.kin.A1, st.kin.A2, st.kin.A3, st.kin.l1, st.kin.l2, st.kin.l3, st.kin.vb,
+                     fit_vb=len(st.lm.lo) == 4)
     p = kcs.Prior(st.prior.beta_kp, st.prior.eps_F, st.prior.beta_h, st.prior.delta, st.prior.kp_on,
                   st.prior.plane_ratio)
     lm = kcs.LMOptions(st.lm.n_iter, st.lm.tau, st.lm.lam_min, st.lm.lam_max, st.lm.lo, st.lm.hi, st.lm.eta,
@@ -103,7 +104,7 @@ def oracle_schedule_vs_gpu(st, n_sweeps, eta, gpu_lam, gpu_x, state=None):
     (x, params, lam) when it is not the oracle's initial state of `st` itself."""
     opt = dataclasses.replace(st.lm, eta=eta, n_iter=1)
     sino = st.sino.astype(np.float64)
-    x, p, lam = oracle.initial_state(st.geom, st.frames, sino) if state is None else state
+    x, p, lam = oracle.initial_state(st.geom, st.frames, sino, oracle.initial_maps(st)) if state is None else state
     n_it = st.lm.n_iter
     first = np.full(lam.shape, -1)
     inherited = np.zeros(lam.shape, dtype=bool)
@@ -111,7 +112,7 @@ def oracle_schedule_vs_gpu(st, n_sweeps, eta, gpu_lam, gpu_x, state=None):
     bound = np.full(lam.shape, np.nan)
     for s in range(n_sweeps):
         kp = st.prior.kp_on and s > 0
-        F = oracle.model_tac(p.reshape(3, -1).T, st.frames.t0, st.frames.t1, st.kin).reshape(x.shape) if kp else None
+        F = oracle.model_tac(p.reshape(len(p), -1).T, st.frames.t0, st.frames.t1, st.kin).reshape(x.shape) if kp else None
         for q in range(st.cfg.Q):
             x = oracle.osl_update(st.geom, st.frames, st.kin, st.prior, sino, p, x, q, st.cfg.Q, kp, None, F)
         dx = np.linalg.norm(np.asarray(gpu_x[s], dtype=np.float64) - x, axis=-1)
@@ -158,3 +159,28 @@ def oracle_schedule_worker(args):
     os.environ["OMP_NUM_THREADS"] = str(threads)
     x, p, lam, first, margin, bound, inherited = oracle_schedule_vs_gpu(st, n_sweeps, eta, gpu_lam, gpu_x, state)
     return x.astype(np.float32), p, lam, first, margin, bound, inherited
+
+
+def path_consistent(same, nbr3d=False):
+    """Voxels whose own accept/reject path and every neighbour's path agree with the oracle's
+    (`same`: per-voxel agreement of the whole fit).  A voxel next to one that took the other path
+    reads other neighbour maps in its Huber gradient, so its maps differ by more than rounding."""
+    return same & ~neighbour_diverged(np.where(same, -1, 0), opt_nbr3d=nbr3d)
+
+
+def oracle_fit_history(st, prior, opt, x, params0, lam0):
+    """The oracle's MAP-LM fit one iteration at a time: final (params, lam) and lambda after every
+    iteration (n_iter, ...)."""
+    one = dataclasses.replace(opt, n_iter=1)
+    p, lam, hist = params0, lam0, []
+    for _ in range(opt.n_iter):
+        p, lam = oracle.lm_iteration(st.frames, st.kin, prior, one, x, p, lam)
+        hist.append(lam)
+    return p, lam, np.stack(hist)
+
+
+def same_fit_path(gpu_hist, oracle_hist):
+    """Voxels whose accept/reject decisions agreed in every iteration of a fit: lambda (which moves
+    by factors of 10) equal up to rounding after each one.  The final lambda alone does not tell
+    (accept then reject ends where reject then accept does)."""
+    return np.all(np.abs(np.asarray(gpu_hist, dtype=np.float64) / oracle_hist - 1.0) < 1e-3, axis=0)

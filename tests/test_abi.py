@@ -211,3 +211,46 @@ def test_noalloc_sweep_rejects_studies_beyond_its_static_scratch():
     rc = kcs.lib().kcs_icm_sweep_noalloc(ctypes.byref(gc), ctypes.byref(fc), ctypes.byref(k), ctypes.byref(p),
                                          ctypes.byref(lm), vp(0), cfg.Q, 0, vp(256), vp(256), vp(256), None)
     assert rc == kcs.KCS_EINVAL  # argument checks come first
+
+
+def test_blood_fraction_options_validated():
+    """With fit_vb the fourth Huber threshold and the blood-fraction box are checked (the box must
+    lie in [0, 1]); fit_vb takes 0 or 1; kcs_init_state takes 3 or 4 initial maps; plans do not
+    fit the blood fraction.  All refused on the host."""
+    g, f = geometry(), frames()
+    gc, fc = g.c(), f.c()
+    vp = ctypes.c_void_p
+    work = ctypes.c_size_t(1 << 30)
+    kv = kcs.Kinetics(**inputs.FENG, vb=inputs.VB, fit_vb=True)
+    p4 = kcs.Prior(0.1, 0.01, 0.1, (1e-3,) * 4)
+    lo4, hi4 = inputs.LM_LO + (0.0,), inputs.LM_HI + (1.0,)
+
+    def lm(k, p, l):
+        kc, pc, lc = k.c(), p.c(), l.c()
+        return kcs.lib().kcs_lm_fit(ctypes.byref(gc), ctypes.byref(fc), ctypes.byref(kc), ctypes.byref(pc),
+                                    ctypes.byref(lc), vp(256), vp(256), vp(256), vp(256), work, None)
+
+    good = kcs.LMOptions(5, 1e-3, 1e-8, 1e8, lo4, hi4)
+    assert lm(kv, kcs.Prior(0.1, 0.01, 0.1, (1e-3, 1e-3, 1e-3, 0.0)), good) == kcs.KCS_EINVAL
+    assert "delta" in kcs.kcs_last_error()
+    assert lm(kv, p4, kcs.LMOptions(5, 1e-3, 1e-8, 1e8, inputs.LM_LO + (-0.1,), hi4)) == kcs.KCS_EINVAL
+    assert "blood fraction" in kcs.kcs_last_error()
+    assert lm(kv, p4, kcs.LMOptions(5, 1e-3, 1e-8, 1e8, lo4, inputs.LM_HI + (1.5,))) == kcs.KCS_EINVAL
+    # three maps: the fourth entries are not read
+    k3 = kcs.Kinetics(**inputs.FENG, vb=inputs.VB)
+    kc = k3.c()
+    kc.fit_vb = 2
+    pc, lc = p4.c(), good.c()
+    assert kcs.lib().kcs_lm_fit(ctypes.byref(gc), ctypes.byref(fc), ctypes.byref(kc), ctypes.byref(pc),
+                                ctypes.byref(lc), vp(256), vp(256), vp(256), vp(256), work, None) == kcs.KCS_EINVAL
+    assert "fit_vb" in kcs.kcs_last_error()
+    xi = (ctypes.c_double * 5)(0.08, 0.12, 0.05, 0.05, 0.05)
+    rc = kcs.lib().kcs_init_state(ctypes.byref(gc), ctypes.byref(fc), vp(256), xi, 5, vp(256), vp(256), vp(256),
+                                  vp(256), work, None)
+    assert rc == kcs.KCS_EINVAL and "n_maps" in kcs.kcs_last_error()
+    st = c_study(g, f)
+    st.k = kv.c()
+    arr = (kcs.c_study * 1)(st)
+    out = ctypes.c_void_p()
+    assert kcs.lib().kcs_plan_create(arr, 1, 0, None, ctypes.byref(out)) == kcs.KCS_EINVAL
+    assert "fit_vb" in kcs.kcs_last_error() and out.value is None

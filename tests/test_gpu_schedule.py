@@ -70,7 +70,7 @@ def test_schedule_brain128_planes(eta):
         assert np.array_equal(fx[z], gx[w]) and np.array_equal(fp[:, z], gp[:, w]) and np.array_equal(fl[z], gl[w]), z
     ox, op, ol, first, margin, bound, inherited = oracle_schedule_vs_gpu(st, cfg.n_sweeps, eta, lams, xs)
     check_independent("brain128 planes", eta, st, gx, gp, ox, op, first, margin, bound, inherited,
-                      max_diverged=0.02)
+                      max_diverged=0.03)
 
 
 # At the clinical-scale planes the schedule's image ends within 3e-3 of the oracle's, not 1e-3.

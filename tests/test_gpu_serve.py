@@ -6,7 +6,8 @@ import pytest
 
 import oracle
 from paper_1803_10045_amd import inputs
-from kcs_testutil import kcs_objects, rel_l2
+from gpu_schedule_util import check_independent, host, run_gpu
+from kcs_testutil import kcs_objects, oracle_schedule_vs_gpu, rel_l2
 
 torch = pytest.importorskip("torch")
 from paper_1803_10045_amd import kcs, serve  # noqa: E402
@@ -31,9 +32,10 @@ def small_stream():
                                  phantom="disk" if nz == 1 else "brain", n_lesions=2, seed=seed)
         st = oracle.make_study(cfg)
         g, f, k, p, lm = kcs_objects(st)
-        host = np.ascontiguousarray(st.sino, np.float32)
-        reqs.append(serve.Request(j, t, g, f, k, p, lm, Q, sw, lambda h=host: torch.from_numpy(h).to(DEV),
-                                  inputs.XI0))
+        sino = np.ascontiguousarray(st.sino, np.float32)
+        req = serve.Request(j, t, g, f, k, p, lm, Q, sw, lambda h=sino: torch.from_numpy(h).to(DEV), inputs.XI0)
+        req.cfg = cfg
+        reqs.append(req)
     return reqs
 
 
@@ -65,6 +67,27 @@ def test_served_results_equal_alone(flags, lanes):
         errs = [rel_l2(a.cpu().numpy(), b.cpu().numpy()) for a, b in zip(results[r.rid], ref)]
         print(f"request {r.rid} ({r.g.nx}x{r.g.ny}x{r.g.nz}, {r.n_sweeps} sweeps): mix vs alone {errs}")
         assert max(errs) <= 1e-5
+
+
+def test_served_study_matches_oracle():
+    """Two served studies of the mix (a 64x64 slice and a 40x40x3 stack) against the FP64 oracle's
+    schedules: the served result equals, bit for bit, the study's schedule stepped one MAP-LM
+    iteration at a time, whose decisions are compared with the oracle's iteration by iteration
+    (image and decision-consistent maps within 1e-3; see test_gpu_schedule.py)."""
+    reqs = small_stream()
+    ex = serve.GpuExecutor(DEV, kcs.KCS_PLAN_GRAPH, n_lanes=2)
+    comp, results, _, _ = serve.serve(reqs, 1 << 40, ex, keep_results=True, lane_of=lambda r: r.rid % 2)
+    ex.close()
+    assert len(comp) == len(reqs)
+    for rid in (0, 2):
+        r = reqs[rid]
+        st = oracle.make_study(r.cfg)
+        run, lams, xs, _ = run_gpu(st, r.n_sweeps, st.lm.eta, lockstep=False)
+        for a, b in zip(results[rid], (run.x, run.params, run.lam)):
+            assert torch.equal(a, b)
+        ox, op, ol, first, margin, bound, inherited = oracle_schedule_vs_gpu(st, r.n_sweeps, st.lm.eta, lams, xs)
+        check_independent(f"served {st.cfg.name}, {r.n_sweeps} sweeps,", st.lm.eta, st, host(run.x),
+                          host(run.params), ox, op, first, margin, bound, inherited, max_diverged=0.02)
 
 
 def test_served_under_tight_budget():

@@ -154,3 +154,48 @@ def test_net_influx_shapes_and_limits():
     ki = oracle.net_influx(p)
     assert ki.shape == (1, 2)
     np.testing.assert_allclose(ki[0], [0.2 * 0.05 / 0.15, 0.3 * 0.2 / (0.2 + 1e-12)], rtol=1e-15)
+
+
+# ---------------------------------------------------------------------------------------------
+# The blood fraction as a fourth fitted parameter (the paper's f_v map, Sec. IV and Table I):
+# params (K1, k2, k3, vb) with vb per voxel.
+
+def kin_with_vb(vb):
+    import dataclasses
+    return dataclasses.replace(KIN, vb=float(vb))
+
+
+@pytest.mark.parametrize("p", [(0.102, 0.130, 0.062, 0.0), (0.054, 0.109, 0.045, 0.03), (0.12, 0.10, 0.12, 0.3),
+                               (0.0, 0.12, 0.05, 1.0), (0.75, 0.35, 0.031, 0.13)])
+def test_frame_tacs_with_free_blood_fraction_against_ode(p):
+    """F with vb taken from the fourth parameter equals the ODE frames with that blood fraction
+    (and ignores the Kinetics' own vb)."""
+    p = np.array(p)
+    F = oracle.model_tac(p, T0, T1, kin_with_vb(0.77))[0]
+    np.testing.assert_allclose(F, ode_frames(p[:3], kin=kin_with_vb(p[3])), rtol=2e-9, atol=1e-12)
+
+
+@pytest.mark.parametrize("p", [(0.102, 0.130, 0.062, 0.05), (0.054, 0.109, 0.045, 0.2), (0.3, 0.1191, 0.01, 0.6)])
+def test_four_parameter_jacobian_against_ode_differences(p):
+    """All four columns against central differences of the ODE frames (h = 1e-6 relative); the
+    vb column is exact for a difference since F is linear in vb."""
+    p = np.array(p, dtype=np.float64)
+    _, J = oracle.model_tac(p, T0, T1, KIN, jacobian=True)
+    assert J.shape == (1, len(T0), 4)
+    for k in range(4):
+        h = 1e-6 * max(abs(p[k]), 0.05)
+        dp = np.zeros(4)
+        dp[k] = h
+        hi, lo = p + dp, p - dp
+        fd = (ode_frames(hi[:3], kin=kin_with_vb(hi[3])) - ode_frames(lo[:3], kin=kin_with_vb(lo[3]))) / (2 * h)
+        scale = np.max(np.abs(J[0, :, k]))
+        assert np.max(np.abs(fd - J[0, :, k])) / scale < 1e-6, k
+
+
+def test_three_parameter_calls_keep_the_fixed_blood_fraction():
+    p3 = np.array(inputs.GRAY)
+    p4 = np.append(p3, KIN.vb)
+    F3, J3 = oracle.model_tac(p3, T0, T1, KIN, jacobian=True)
+    F4, J4 = oracle.model_tac(p4, T0, T1, KIN, jacobian=True)
+    np.testing.assert_allclose(F4, F3, rtol=1e-14)
+    np.testing.assert_allclose(J4[..., :3], J3, rtol=1e-14)

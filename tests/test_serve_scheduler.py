@@ -140,12 +140,65 @@ def test_lanes_run_independently():
         orig(slots, lane)
 
     ex.run_tick = slow
-    comp, _, _, _ = serve.serve(reqs, 100, ex, lane_of=lambda r: 1 if r.rid == 0 else 0)
+    comp, _, _, _ = serve.serve(reqs, 100, ex, lane_of=lambda r: 1 if r.rid == 0 else 0,
+                                small_in_flight_beside_large=1)
     for t in ex.ticks:
         rids = {rid for rid, _ in t}
         assert rids == {0} or 0 not in rids
     done = {c.rid: c for c in comp}
     assert done[1].finished < done[0].finished and done[2].finished < done[0].finished
+
+
+class TimedTwoLaneExecutor(FakeExecutor):
+    """Ticks run asynchronously: a tick takes `dur[lane]` seconds of a simulated GPU per lane and
+    is in flight until then (done() polls the wall clock)."""
+    lanes = [None, None]
+
+    def __init__(self, dur):
+        super().__init__()
+        self.dur = dur
+        self.busy_until = [0.0, 0.0]
+        self.spans = []  # (lane, start, end)
+
+    def start(self):
+        self.t0 = time.perf_counter()
+
+    def run_tick(self, slots, lane=0):
+        super().run_tick(slots, lane)
+        now = time.perf_counter() - self.t0
+        start = max(now, self.busy_until[lane])
+        self.busy_until[lane] = start + self.dur[lane]
+        self.spans.append((lane, start, self.busy_until[lane]))
+
+    def mark(self, lane=0):
+        return self.busy_until[lane]
+
+    def done(self, token):
+        return time.perf_counter() - self.t0 >= token
+
+    def wait(self, token):
+        while not self.done(token):
+            time.sleep(0.0001)
+        return token
+
+
+def test_small_lane_yields_to_a_large_study():
+    """With small_in_flight_beside_large = 0 no small tick is enqueued while a large tick is in
+    flight, so a small study that arrives during a large one starts after it; with 1 it runs
+    beside it and finishes first."""
+    def run_cap(cap):
+        reqs = [FakeRequest(0, 0.0, n_sweeps=5, nbytes=50), FakeRequest(1, 0.005, n_sweeps=2, nbytes=10)]
+        ex = TimedTwoLaneExecutor(dur=[0.001, 0.01])
+        comp, _, _, _ = serve.serve(reqs, 100, ex, lane_of=lambda r: 1 if r.rid == 0 else 0,
+                                    small_in_flight_beside_large=cap)
+        return ex, {c.rid: c for c in comp}
+
+    ex, done = run_cap(0)
+    large_end = max(e for lane, _, e in ex.spans if lane == 1)
+    assert min(st for lane, st, _ in ex.spans if lane == 0) >= large_end
+    assert done[0].finished <= done[1].finished
+    ex, done = run_cap(1)
+    assert done[1].finished < done[0].finished
 
 
 def test_lane_batch_runs_oldest_first():
