@@ -507,6 +507,7 @@ int do_lm(const kcs_geometry& g, const Schedule& S, int np, const kcs_prior& p, 
     a.nx = g.nx;
     a.ny = g.ny;
     a.nz = g.nz;
+    a.tile_x = lm_tile_x(g.nx, g.ny);
     a.fr = S.fr;
     a.beta_h = (float)p.beta_h;
     set_neighbourhood(a, p);
@@ -621,6 +622,7 @@ LmArgs lm_args(const StudyPrep& P) {
     a.nx = s.g.nx;
     a.ny = s.g.ny;
     a.nz = s.g.nz;
+    a.tile_x = lm_tile_x(s.g.nx, s.g.ny);
     a.fr = P.S.fr;
     a.beta_h = (float)s.p.beta_h;
     set_neighbourhood(a, s.p);
@@ -758,7 +760,7 @@ void build_schedule(TableBuilder& tb, std::vector<StudyPrep>& preps) {
                     a.need_state = it + 1 < s.lm.n_iter ? 1 : 0;
                     jobs.push_back(LmJob{a, at<KinTab>(s.d_work, P->L.kin), s.d_x, src, dst, s.d_lambda,
                                          at<float>(s.d_work, P->L.lms), 0});
-                    g.push_back(lm_groups(s.g.nx, s.g.ny, s.g.nz));
+                    g.push_back(lm_groups(s.g.nx, s.g.ny, s.g.nz, a.tile_x));
                 }
                 tb.add(PH_LM, M, nb, jobs, g, 0);
             }

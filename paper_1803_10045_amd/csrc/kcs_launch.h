@@ -42,6 +42,7 @@ struct LmArgs {
     int32_t have_state;    // 1: J^T J, J^T r and r^T r at the current maps are in `state`
     int32_t need_state;    // 1: leave them in `state` for the next iteration
     float lo[4], hi[4];
+    int32_t tile_x;  // voxel rows of tile_x voxels, 256 / tile_x of them per workgroup (see lm_tile_x)
 };
 
 // Inputs of the FP64 table-setup kernel.
@@ -87,7 +88,7 @@ struct LmJob {
     const float* xi_in;
     float* xi_out;
     float* lam;
-    float* state;  // [10][N]: J^T J (6), J^T r (3), r^T r at the current maps
+    float* state;  // [10][N] (3 maps) or [15][N] (4): J^T J, J^T r, r^T r at the current maps
     uint32_t w0;
 };
 struct ModelJob {
@@ -143,7 +144,8 @@ uint32_t proj_direct_groups(const ProjArgs& p);
 uint32_t proj_tile_groups(const ProjArgs& p, int T);
 uint32_t staged_tile_groups(int nx, int ny, int nz);
 bool staged_fits(int M, float h, float du);  // one angle's staged bin records fit in the LDS
-uint32_t lm_groups(int nx, int ny, int nz);
+int lm_tile_x(int nx, int ny);
+uint32_t lm_groups(int nx, int ny, int nz, int tile_x);
 uint32_t model_groups(int64_t n);
 uint32_t copy_groups(int64_t n);
 

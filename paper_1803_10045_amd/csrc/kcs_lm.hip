@@ -12,14 +12,14 @@
 // accepted, and those at the current maps stay valid when it is rejected.  A fit therefore
 // carries J^T J, J^T r and r^T r from one iteration to the next in a per-voxel state buffer: its
 // first iteration evaluates the model twice (with the Jacobian at the current and the trial
-// maps), the others once (with the Jacobian, at the trial maps).
+// maps), the others once (at the trial maps, with the Jacobian unless it is the fit's last).
 #include "kcs_device.h"
 #include "kcs_launch.h"
 #include "kcs_model.h"
 
 namespace kcs {
 
-constexpr int kLmTileX = 64, kLmTileY = 4;
+constexpr int kLmThreads = 256;
 
 __host__ __device__ __forceinline__ float huber(float t, float d) {
     const float at = fabsf(t);
@@ -114,6 +114,20 @@ __host__ __device__ __forceinline__ Normal<NP> normal_equations(const FrameTab& 
                                          n.rr = fmaf(r, r, n.rr);
                                      });
     return n;
+}
+
+// r^T r of the data term at maps xi, from the model without its Jacobian.  F and the sum are
+// formed by the same operations as in normal_equations, so the two round identically.
+template <int M, int NP>
+__host__ __device__ __forceinline__ float residual_norm(const FrameTab& fr, const KinTab& K, const float* xv,
+                                                        const float (&xi)[NP]) {
+    float rr = 0.0f;
+    model_frames<M, false, false, NP>(fr, K, xi[0], xi[1], xi[2], NP == 4 ? xi[NP - 1] : 0.0f,
+                                      [&](int m, float F, float, float, float, float) {
+                                          const float r = xv[m] - F;
+                                          rr = fmaf(r, r, rr);
+                                      });
+    return rr;
 }
 
 template <int NP>
@@ -215,12 +229,19 @@ __host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, 
     float unused[NP];
     const float e1 = neighbour_energy<NP, NBR3D>(xi_in, a, i, j, z, N, q, unused);
 
-    // data term at the trial parameters, with its normal equations (the next iteration's when
-    // the step is kept).  The last iteration of a fit needs only r'^T r', but evaluating it the
-    // same way in every iteration makes a fit of n iterations round exactly like n calls of one
-    // iteration each, whatever the call pattern.
-    const Normal<NP> n1 = normal_equations<M, NP>(a.fr, *K, xv, q);
-    const float dphi = fmaf(a.beta_h, e1 - e0, 0.5f * (n1.rr - n0.rr));
+    // data term at the trial parameters, with its normal equations when another iteration follows
+    // (they are the next iteration's if the step is kept); the last iteration of a fit needs only
+    // r'^T r', which rounds like the normal equations' own, so a fit of n iterations still rounds
+    // exactly like n calls of one iteration each.
+    Normal<NP> n1;
+    float rr1;
+    if (a.need_state) {
+        n1 = normal_equations<M, NP>(a.fr, *K, xv, q);
+        rr1 = n1.rr;
+    } else {
+        rr1 = residual_norm<M, NP>(a.fr, *K, xv, q);
+    }
+    const float dphi = fmaf(a.beta_h, e1 - e0, 0.5f * (rr1 - n0.rr));
     const float phi0 = fmaf(a.beta_h, e0, 0.5f * n0.rr);
     const bool accept = dphi < -a.eta * phi0;
 #pragma unroll
@@ -233,21 +254,41 @@ __host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, 
     }
 }
 
-uint32_t lm_groups(int nx, int ny, int nz) {
-    return (uint32_t)((nx + kLmTileX - 1) / kLmTileX) * ((ny + kLmTileY - 1) / kLmTileY) * nz;
+// Width of the voxel tile of a workgroup (tile_x x 256 / tile_x voxels, one per thread): of 64,
+// 32, 16 and 8, the one that pads the plane least (idle lanes cost a whole lane's model
+// evaluations), the wider on a tie (a wavefront then reads longer contiguous runs of the image).
+// The tile does not change any voxel's result.
+int lm_tile_x(int nx, int ny) {
+    int best = 64;
+    long best_area = -1;
+    for (int tx : {64, 32, 16, 8}) {
+        const int ty = kLmThreads / tx;
+        const long area = (long)((nx + tx - 1) / tx * tx) * ((ny + ty - 1) / ty * ty);
+        if (best_area < 0 || area < best_area) {
+            best = tx;
+            best_area = area;
+        }
+    }
+    return best;
+}
+
+uint32_t lm_groups(int nx, int ny, int nz, int tile_x) {
+    const int ty = kLmThreads / tile_x;
+    return (uint32_t)((nx + tile_x - 1) / tile_x) * ((ny + ty - 1) / ty) * nz;
 }
 
 template <int M, int NP, bool NBR3D, class Src>
-__global__ __launch_bounds__(256) void klm_kernel(Src src) {
+__global__ __launch_bounds__(kLmThreads) void klm_kernel(Src src) {
     const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
     const LmJob& J = src.find(w);
     const LmArgs& a = J.a;
     const uint32_t lw = w - J.w0;
-    const uint32_t tx = (a.nx + kLmTileX - 1) / kLmTileX, ty = (a.ny + kLmTileY - 1) / kLmTileY;
+    const int TX = a.tile_x, TY = kLmThreads / TX;
+    const uint32_t tx = (a.nx + TX - 1) / TX, ty = (a.ny + TY - 1) / TY;
     const int z = lw / (tx * ty);
     const uint32_t rr = lw % (tx * ty);
-    const int j = (rr / tx) * kLmTileY + threadIdx.x / kLmTileX;
-    const int i = (rr % tx) * kLmTileX + threadIdx.x % kLmTileX;
+    const int j = (rr / tx) * TY + threadIdx.x / TX;
+    const int i = (rr % tx) * TX + threadIdx.x % TX;
     if (z >= a.nz || i >= a.nx || j >= a.ny) return;
     lm_voxel<M, NP, NBR3D>(J.K, J.x, J.xi_in, J.xi_out, J.lam, J.state, a, i, j, z);
 }
@@ -256,7 +297,7 @@ __global__ __launch_bounds__(256) void klm_kernel(Src src) {
 // that the in-plane three-map kernel carries no code or registers for the other cases.
 template <int NP, bool NBR3D, class Src>
 static hipError_t dispatch_lm_m(int M, Src src, uint32_t groups, hipStream_t st) {
-    const dim3 g(xcd_round_up(groups)), b(kLmTileX * kLmTileY);
+    const dim3 g(xcd_round_up(groups)), b(kLmThreads);
     switch (M) {
         case 8: hipLaunchKernelGGL((klm_kernel<8, NP, NBR3D, Src>), g, b, 0, st, src); break;
         case 16: hipLaunchKernelGGL((klm_kernel<16, NP, NBR3D, Src>), g, b, 0, st, src); break;
@@ -279,11 +320,12 @@ static hipError_t dispatch_lm(int M, int np, bool nbr3d, Src src, uint32_t group
 hipError_t launch_lm(int M, const KinTab* K, const float* x, const float* xi_in, float* xi_out, float* lam,
                      float* state, const LmArgs& a, hipStream_t st) {
     OneJob<LmJob> src{LmJob{a, K, x, xi_in, xi_out, lam, state, 0}};
-    return dispatch_lm(M, a.np, a.nbr3d != 0, src, lm_groups(a.nx, a.ny, a.nz), st);
+    return dispatch_lm(M, a.np, a.nbr3d != 0, src, lm_groups(a.nx, a.ny, a.nz, a.tile_x), st);
 }
 
 hipError_t launch_lm_jobs(int M, bool nbr3d, JobTable<LmJob> jobs, uint32_t groups, hipStream_t st) {
-    return dispatch_lm(M, 3, nbr3d, jobs, groups, st);
+    // plans fit three maps
+    return nbr3d ? dispatch_lm_m<3, true>(M, jobs, groups, st) : dispatch_lm_m<3, false>(M, jobs, groups, st);
 }
 
 }  // namespace kcs

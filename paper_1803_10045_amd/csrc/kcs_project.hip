@@ -103,20 +103,27 @@ __global__ __launch_bounds__(256) void kproj_kernel(Src src) {
     project_ray<M, RATIO>(p, J.x, J.sino, J.out, z, al, ray - al * p.n_bin);
 }
 
-// Frames staged per workgroup and threads per workgroup of the T x T tile variants: the whole
-// record for 16-pixel tiles, half of it for 32 and 4 frames for 64, so that two or more
-// workgroups fit in a CU's LDS (one stages while another traverses) while larger tiles cut the
-// partial sums (a ray leaves one partial per tile it crosses).  The frame groups of one tile
-// are adjacent work items, so they share the tile's cache lines in L2.
-__host__ __device__ constexpr int tile_frames(int M, int T) { return T == 16 ? M : (T == 32 ? M / 2 : 4); }
-__host__ __device__ constexpr int tile_threads(int T) { return T == 16 ? 256 : 512; }
+// Tile variants: a T x T pixel tile with FG = M / NG of its frames staged in LDS per workgroup
+// (NG frame groups; the groups of one tile are adjacent work items, so they share the tile's
+// cache lines in L2).  Larger tiles cut the partial sums (a ray leaves one partial per tile it
+// crosses); fewer groups walk each ray segment fewer times.  Each staged tile stays within
+// 80 KB, so that two workgroups share a CU and one stages while the other walks (measured: a
+// whole-record 32-pixel tile, one workgroup per CU, walks each segment once but runs slower).
 // LDS row stride of a staged tile in floats: padded by 4 so that vertically adjacent pixels,
 // which parallel rays of a near-horizontal angle read at the same step, fall in other banks.
-__host__ __device__ constexpr int tile_row(int M, int T) { return T * tile_frames(M, T) + 4; }
+__host__ __device__ constexpr int tile_row(int T, int FG) { return T * FG + 4; }
+__host__ __device__ constexpr size_t tile_lds_bytes(int T, int FG) { return (size_t)T * tile_row(T, FG) * sizeof(float); }
+__host__ __device__ constexpr int tile_threads(int T, int FG) { return T == 16 ? 256 : 512; }
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS of a CU
+
+// Frame groups of the tiled projector for M frames and tile T: the fewest whose staged tile
+// leaves room for two workgroups per CU (one stages its tile while the other walks).
+__host__ __device__ constexpr int tile_groups_for(int M, int T) {
+    return tile_lds_bytes(T, M) <= 80 * 1024 ? 1 : (M % 8 == 0 && tile_lds_bytes(T, M / 2) <= 80 * 1024 ? 2 : M / 4);
+}
 
 uint32_t proj_tile_groups(const ProjArgs& p, int T) {
-    const int groups_per_tile = p.fr.M / tile_frames(p.fr.M, T);
-    return (uint32_t)(((p.nx + T - 1) / T) * ((p.ny + T - 1) / T)) * p.nz * groups_per_tile;
+    return (uint32_t)(((p.nx + T - 1) / T) * ((p.ny + T - 1) / T)) * p.nz * tile_groups_for(p.fr.M, T);
 }
 
 size_t tile_partial_bytes(int T, const ProjArgs& p, int M) {
@@ -173,9 +180,20 @@ struct TileAngle {
     float px, py;
 };
 
-template <int M, int T, class Src>
-__global__ __launch_bounds__(tile_threads(T)) void kproj_tile_kernel(Src src) {
-    constexpr int FG = tile_frames(M, T), NG = M / FG, NT = tile_threads(T), TS = tile_row(M, T);
+// The angle al of work item it: start[al] <= it < start[al + 1] (binary search over the LDS table).
+__device__ __forceinline__ int item_angle(const int* start, int A_q, int it) {
+    int lo = 0, hi = A_q - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= it) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int M, int T, int NG, class Src>
+__global__ __launch_bounds__(tile_threads(T, M / NG)) void kproj_tile_kernel(Src src) {
+    constexpr int FG = M / NG, NT = tile_threads(T, FG), TS = tile_row(T, FG);
     static_assert(M % FG == 0 && FG % 4 == 0, "frame groups");
     extern __shared__ float4 lds4[];
     const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
@@ -200,6 +218,9 @@ __global__ __launch_bounds__(tile_threads(T)) void kproj_tile_kernel(Src src) {
         load_frames<FG>(src_px + ((size_t)r * p.nx + c) * M, v);
         store_frames<FG>(tile + r * TS + c * FG, v);
     }
+    // start[al] = first work item of angle al (items are the bins of each angle that can meet the
+    // tile, angle after angle); start[A_q] = number of items
+    int* start = reinterpret_cast<int*>(sT + p.A_q);
     for (int al = threadIdx.x; al < p.A_q; al += NT) {
         TileAngle t;
         double c, s;
@@ -210,17 +231,35 @@ __global__ __launch_bounds__(tile_threads(T)) void kproj_tile_kernel(Src src) {
         t.px = pt.x;
         t.py = pt.y;
         sT[al] = t;
+        start[al + 1] = min(max(t.b1 - t.b0 + 1, 0), slots);
     }
     __syncthreads();
+    if (threadIdx.x < 64) {  // inclusive scan of the counts by the first wave, 64 angles at a time
+        int carry = 0;
+        for (int base = 0; base < p.A_q; base += 64) {
+            const int al = base + (int)threadIdx.x;
+            int v = al < p.A_q ? start[al + 1] : 0;
+#pragma unroll
+            for (int d = 1; d < 64; d *= 2) {
+                const int u = __shfl_up(v, d, 64);
+                if ((int)threadIdx.x >= d) v += u;
+            }
+            if (al < p.A_q) start[al + 1] = v + carry;
+            carry += __shfl(v, 63, 64);
+        }
+        if (threadIdx.x == 0) start[0] = 0;
+    }
+    __syncthreads();
+    const int n_items = start[p.A_q];
     const size_t n_tiles = (size_t)p.nz * nty * ntx;
     float* out = J.psum + partial_offset(g, n_tiles, (size_t)z * nty * ntx + tr, p.A_q, 0, slots, 0, FG);
     const float bin_step = p.du * p.inv_h;  // bin width in pixel units
-    // Work items: one ray segment each, angle-major (a wave's lanes share an angle and walk
-    // parallel rays through the tile).
-    for (int it = threadIdx.x; it < p.A_q * slots; it += NT) {
-        const int al = it / slots, slot = it - al * slots;
+    // Work items: one ray segment each, angle after angle (a wave's lanes walk parallel rays of
+    // one or two angles through the tile, so their LDS reads stay close); only bins that can meet
+    // the tile are items.
+    for (int it = threadIdx.x; it < n_items; it += NT) {
+        const int al = item_angle(start, p.A_q, it), slot = it - start[al];
         const TileAngle ta = sT[al];
-        if (ta.b0 + slot > ta.b1) continue;
         float acc[FG];
 #pragma unroll
         for (int m = 0; m < FG; ++m) acc[m] = 0.0f;
@@ -234,13 +273,13 @@ __global__ __launch_bounds__(tile_threads(T)) void kproj_tile_kernel(Src src) {
 #pragma unroll
             for (int m = 0; m < FG; ++m) acc[m] = fmaf(len, v[m], acc[m]);
         });
-        store_frames<FG>(out + (size_t)it * FG, acc);
+        store_frames<FG>(out + ((size_t)al * slots + slot) * FG, acc);
     }
 }
 
-template <int M, int T, bool RATIO, class Src>
+template <int M, int T, int NG, bool RATIO, class Src>
 __global__ __launch_bounds__(256) void kproj_reduce_kernel(Src src) {
-    constexpr int FG = tile_frames(M, T), NG = M / FG;
+    constexpr int FG = M / NG;
     const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
     const ProjJob& J = src.find(w);
     const ProjArgs& p = J.p;
@@ -300,25 +339,29 @@ __global__ __launch_bounds__(256) void kproj_reduce_kernel(Src src) {
 // ---------------------------------------------------------------------------------------------
 // Launch helpers
 
-template <int M, int T, class Src>
+template <int M, int T, int NG, class Src>
 static hipError_t launch_tile(Src src, uint32_t groups, int max_angles, hipStream_t st) {
+    constexpr int FG = M / NG;
     static bool attr_set = false;  // the tile may exceed the default 64 KB of dynamic LDS
     if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&kproj_tile_kernel<M, T, Src>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&kproj_tile_kernel<M, T, NG, Src>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
         attr_set = true;
     }
-    const size_t lds = (size_t)T * tile_row(M, T) * sizeof(float) + (size_t)max_angles * sizeof(TileAngle);
-    hipLaunchKernelGGL((kproj_tile_kernel<M, T, Src>), dim3(xcd_round_up(groups)), dim3(tile_threads(T)), lds, st, src);
+    const size_t lds = tile_lds_bytes(T, FG) + (size_t)max_angles * sizeof(TileAngle) + (size_t)(max_angles + 1) * sizeof(int);
+    if (lds > kLdsBytes) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((kproj_tile_kernel<M, T, NG, Src>), dim3(xcd_round_up(groups)), dim3(tile_threads(T, FG)), lds,
+                       st, src);
     return hipGetLastError();
 }
 
-template <int M, int T, class Src>
+template <int M, int T, int NG, class Src>
 static hipError_t launch_reduce(Src src, uint32_t groups, bool ratio, hipStream_t st) {
     if (ratio)
-        hipLaunchKernelGGL((kproj_reduce_kernel<M, T, true, Src>), dim3(xcd_round_up(groups)), dim3(256), 0, st, src);
+        hipLaunchKernelGGL((kproj_reduce_kernel<M, T, NG, true, Src>), dim3(xcd_round_up(groups)), dim3(256), 0, st, src);
     else
-        hipLaunchKernelGGL((kproj_reduce_kernel<M, T, false, Src>), dim3(xcd_round_up(groups)), dim3(256), 0, st, src);
+        hipLaunchKernelGGL((kproj_reduce_kernel<M, T, NG, false, Src>), dim3(xcd_round_up(groups)), dim3(256), 0, st,
+                           src);
     return hipGetLastError();
 }
 
@@ -331,19 +374,31 @@ static hipError_t launch_direct(Src src, uint32_t groups, bool ratio, hipStream_
     return hipGetLastError();
 }
 
-// One step of the projector for frame count M and tile T (0 = ray-driven): the tile step
+// Whether the T x T tile with M / NG frames per group is built: whole 4-float groups, two
+// workgroups per CU.
+template <int M, int T, int NG>
+constexpr bool tile_built() {
+    return M % NG == 0 && (M / NG) % 4 == 0 && tile_lds_bytes(T, M / NG) <= 80 * 1024;
+}
+
+template <int M, int T, int NG, class Src>
+static hipError_t tile_or_reduce(Src src, uint32_t groups, int max_angles, bool ratio, bool reduce_step, hipStream_t st) {
+    if constexpr (tile_built<M, T, NG>())
+        return reduce_step ? launch_reduce<M, T, NG>(src, groups, ratio, st) : launch_tile<M, T, NG>(src, groups, max_angles, st);
+    else
+        return hipErrorInvalidValue;
+}
+
+// One step of the projector for frame count M and tile T (T = 0: ray-driven): the tile step
 // (reduce_step = false) or the reduce step of a tiled projection, or the ray-driven kernel.
 template <int M, class Src>
 static hipError_t project_step(int T, Src src, uint32_t groups, int max_angles, bool ratio, bool reduce_step,
                                hipStream_t st) {
     switch (T) {
         case 0: return reduce_step ? hipSuccess : launch_direct<M>(src, groups, ratio, st);
-        case 16:
-            return reduce_step ? launch_reduce<M, 16>(src, groups, ratio, st) : launch_tile<M, 16>(src, groups, max_angles, st);
-        case 32:
-            return reduce_step ? launch_reduce<M, 32>(src, groups, ratio, st) : launch_tile<M, 32>(src, groups, max_angles, st);
-        case 64:
-            return reduce_step ? launch_reduce<M, 64>(src, groups, ratio, st) : launch_tile<M, 64>(src, groups, max_angles, st);
+        case 16: return tile_or_reduce<M, 16, tile_groups_for(M, 16)>(src, groups, max_angles, ratio, reduce_step, st);
+        case 32: return tile_or_reduce<M, 32, tile_groups_for(M, 32)>(src, groups, max_angles, ratio, reduce_step, st);
+        case 64: return tile_or_reduce<M, 64, tile_groups_for(M, 64)>(src, groups, max_angles, ratio, reduce_step, st);
         default: return hipErrorInvalidValue;
     }
 }
