@@ -339,6 +339,7 @@ def run_serve(args):
     total_bytes = None
     runs = [r.split("@") for r in args.serve_runs.split(",")]
     for mode, when in runs:
+        label = mode
         rate = args.rate if when == "poisson" else 0.0
         t = time.perf_counter()
         reqs = make_requests(args.requests, rate, dev)
@@ -350,18 +351,28 @@ def run_serve(args):
                 total_bytes += r.n_sweeps * (r.Q * (nb["project"] + nb["osl"]) + 5 * nb["lm"])
         if mode.startswith("served"):
             # "served:N" runs at most N small-study ticks beside a large study's tick
-            cap = int(mode.split(":")[1]) if ":" in mode else args.small_beside_large
+            cap = int(mode.split(":")[1].split("/")[0]) if ":" in mode else args.small_beside_large
             ex = serve.GpuExecutor(dev, n_lanes=2)
-            comp, _, makespan, ticks = serve.serve(reqs, budget, ex, log=log, small_in_flight_beside_large=cap)
+            wait = args.small_wait
+            if "/" in mode:  # "served:N/W": W seconds of small-study wait beside a large study
+                mode, w = mode.split("/")
+                wait = float(w)
+            comp, _, makespan, ticks = serve.serve(reqs, budget, ex, log=log, small_in_flight_beside_large=cap,
+                                                   small_wait_beside_large=wait)
             ex.close()
-            extra = {"ticks": ticks, "small_in_flight_beside_large": cap}
+            extra = {"ticks": ticks, "small_in_flight_beside_large": cap, "small_wait_beside_large_s": wait}
         else:
             comp, _, makespan = serve.serve_serial(reqs, log=log)
             extra = {}
         lat = serve.latency_summary(comp)
+        size_of = {r.rid: f"{r.g.nx}x{r.g.ny}x{r.g.nz}" for r in reqs}
+        by_size = {k: serve.latency_summary([c for c in comp if size_of[c.rid] == k])
+                   for k in sorted(set(size_of.values()), key=lambda k: int(k.split("x")[0]))}
         res = {"studies_per_s": round(len(comp) / makespan, 3), "makespan_s": round(makespan, 2), **lat,
-               "hbm_frac": round(total_bytes / makespan / (HBM_PEAK_GBPS * 1e9), 4), **extra}
-        key = f"{mode}@{rate}Hz" if rate > 0 else f"{mode}@saturated"
+               "hbm_frac": round(total_bytes / makespan / (HBM_PEAK_GBPS * 1e9), 4), **extra, "by_size": by_size,
+               "largest": [(c.rid, round(c.arrival, 3), round(c.admitted, 3), round(c.finished, 3))
+                           for c in comp if size_of[c.rid] == max(size_of.values(), key=lambda k: int(k.split("x")[0]))]}
+        key = f"{label}@{rate}Hz" if rate > 0 else f"{label}@saturated"
         out_runs[key] = res
         log(f"{key}: {res}")
         torch.cuda.empty_cache()
@@ -508,8 +519,11 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=250.0)
     ap.add_argument("--small-beside-large", type=int, default=1,
                     help="serve mode: small-study ticks in flight beside a large study's tick")
+    ap.add_argument("--small-wait", type=float, default=0.0,
+                    help="serve mode: seconds a small study waits before its ticks run beside a large one")
     ap.add_argument("--serve-runs", default="served@poisson,serial@poisson,served@saturated,serial@saturated",
-                    help="comma-separated runs of the serve mode: served[:N]|serial @ poisson|saturated (N: --small-beside-large)")
+                    help="comma-separated runs of the serve mode: served[:N[/W]]|serial @ poisson|saturated "
+                         "(N: --small-beside-large, W: --small-wait)")
     ap.add_argument("--config", default="brain344", choices=["disk64", "brain128", "brain344"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--correction", action="store_true",

@@ -283,12 +283,12 @@ __global__ __launch_bounds__(kLmThreads) void klm_kernel(Src src) {
     const LmJob& J = src.find(w);
     const LmArgs& a = J.a;
     const uint32_t lw = w - J.w0;
-    const int TX = a.tile_x, TY = kLmThreads / TX;
-    const uint32_t tx = (a.nx + TX - 1) / TX, ty = (a.ny + TY - 1) / TY;
+    const int TX = a.tile_x, TY = kLmThreads / TX, sx = __builtin_ctz((unsigned)TX);  // TX a power of 2
+    const uint32_t tx = (a.nx + TX - 1) >> sx, ty = (a.ny + TY - 1) / TY;
     const int z = lw / (tx * ty);
     const uint32_t rr = lw % (tx * ty);
-    const int j = (rr / tx) * TY + threadIdx.x / TX;
-    const int i = (rr % tx) * TX + threadIdx.x % TX;
+    const int j = (rr / tx) * TY + (threadIdx.x >> sx);
+    const int i = (rr % tx) * TX + (threadIdx.x & (TX - 1));
     if (z >= a.nz || i >= a.nx || j >= a.ny) return;
     lm_voxel<M, NP, NBR3D>(J.K, J.x, J.xi_in, J.xi_out, J.lam, J.state, a, i, j, z);
 }

@@ -238,7 +238,7 @@ class Completion:
 def serve(requests: Sequence[Request], budget_bytes: int, executor, keep_results: bool = False,
           max_in_flight: int = 2, lane_of: Optional[Callable[[Request], int]] = None,
           lane_batch: Optional[Sequence[int]] = None, log: Optional[Callable[[str], None]] = None,
-          small_in_flight_beside_large: int = 1):
+          small_in_flight_beside_large: int = 1, small_wait_beside_large: float = 0.0):
     """Serves `requests` in real time (arrival times in seconds from the start).  Returns
     (completions, results, makespan_s, ticks); completion times come from the executor's clock
     (GPU events on the lane streams).  `lane_batch[i]` caps the studies per tick of lane i (0: all
@@ -248,8 +248,12 @@ def serve(requests: Sequence[Request], budget_bytes: int, executor, keep_results
     the GPU between them).  Default 1: one small tick beside each large one.  0 makes the small
     studies wait for the large study to finish, which runs it as fast as alone but holds every
     small study that arrives meanwhile for a large study's whole duration (at 4 requests/s of the
-    mixed workload the tail latency doubled).  A finished study's memory returns to the budget
-    once its last tick has completed."""
+    mixed workload the tail latency doubled).  `small_wait_beside_large` (seconds) holds a small
+    tick back while a large tick is in flight until the oldest small study of that lane has waited
+    that long since its arrival: the large studies then share the GPU only with small studies that
+    would otherwise wait too long, and the small ones still finish within about that wait plus
+    their own sweeps.  A finished study's memory returns to the budget once its last tick has
+    completed."""
     n_lanes = len(getattr(executor, "lanes", [None]))
     if lane_of is None:
         lane_of = lane_by_traffic() if n_lanes > 1 else (lambda r: 0)
@@ -290,6 +294,9 @@ def serve(requests: Sequence[Request], budget_bytes: int, executor, keep_results
             cap = max_in_flight
             if large_busy and lane < n_lanes - 1:
                 cap = min(cap, small_in_flight_beside_large)
+                oldest = min((sl.req.arrival for sl in sched.active[lane]), default=None)
+                if oldest is not None and time.perf_counter() - t0 - oldest < small_wait_beside_large:
+                    cap = 0
             if len(in_flight[lane]) >= cap:
                 continue
             slots = sched.tick(lane)

@@ -207,3 +207,21 @@ def test_lane_batch_runs_oldest_first():
     comp, _, _, _ = serve.serve(reqs, 100, ex, lane_of=lambda r: 1, lane_batch=[0, 1])
     assert all(len(t) == 1 for t in ex.ticks)
     assert [t[0][0] for t in ex.ticks] == [0, 0, 0, 1, 1, 1, 2, 2, 2]
+
+
+def test_small_studies_wait_before_running_beside_a_large_one():
+    """With small_wait_beside_large = W a small tick starts beside a large tick only once the
+    oldest small study has waited W since its arrival; without a large tick it starts at once."""
+    def run_wait(wait):
+        reqs = [FakeRequest(0, 0.0, n_sweeps=8, nbytes=50), FakeRequest(1, 0.005, n_sweeps=2, nbytes=10)]
+        ex = TimedTwoLaneExecutor(dur=[0.001, 0.01])
+        comp, _, _, _ = serve.serve(reqs, 100, ex, lane_of=lambda r: 1 if r.rid == 0 else 0,
+                                    small_in_flight_beside_large=1, small_wait_beside_large=wait)
+        return ex, {c.rid: c for c in comp}
+
+    ex, done = run_wait(0.03)
+    first_small = min(st for lane, st, _ in ex.spans if lane == 0)
+    assert first_small >= 0.005 + 0.03 - 1e-3  # waited, although a large tick was in flight
+    assert first_small < max(e for lane, _, e in ex.spans if lane == 1)  # but ran beside the large study
+    ex, done = run_wait(0.0)
+    assert min(st for lane, st, _ in ex.spans if lane == 0) < 0.005 + 0.01
