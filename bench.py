@@ -124,10 +124,10 @@ def counter_traffic(cfg_name, kind):
 
 
 def counter_busy(cfg_name, kind):
-    """Fraction of the CUs' busy time that step `kind`'s kernels issue VALU instructions, from the
-    committed busy-counter summary of this workload, or None (missing, or kernel sources changed
-    since)."""
-    path = os.path.join(ROOT, "profiles", f"sweep_{cfg_name.split('_', 1)[1]}_busy_counters.md")
+    """Fraction of SIMD cycles in which step `kind`'s main kernel issues at least one VALU
+    instruction (dual-issue cycles counted once), from the committed compute-counter summary of
+    this workload, or None (missing, or kernel sources changed since)."""
+    path = os.path.join(ROOT, "profiles", f"sweep_{cfg_name.split('_', 1)[1]}_compute_counters.md")
     if not os.path.exists(path):
         return None
     try:
