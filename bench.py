@@ -466,6 +466,39 @@ def run_ki(args):
                       "hbm_frac": round(gbps / 8000.0, 4), "config": {"workload": cfg.name}}), flush=True)
 
 
+def run_ssrb(args):
+    """Single-slice rebinning of a span-1 acquisition of the mMR's 64 rings (ring differences up to
+    60) with the headline sinogram (252 angles x 344 bins) and 4 frames into its 127 planes,
+    timed with HIP events over `steps` launches.  Algorithmic bytes: every existing ring pair's
+    sinogram read once and the planes written once."""
+    import torch
+
+    from paper_1803_10045_amd import kcs
+
+    R, D, A, B, M = 64, 60, 252, 344, 4
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(9)
+    y3d = torch.poisson(torch.full((2 * D + 1, R, A, B, M), 2.0, device="cuda:0"), generator=g)
+    y2d = torch.empty((2 * R - 1, A, B, M), device="cuda:0")
+    count = torch.empty(2 * R - 1, device="cuda:0")
+    kcs.kcs_rebin_ssrb(R, D, y3d, y2d, count)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        kcs.kcs_rebin_ssrb(R, D, y3d, y2d, count)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    pairs = int(count.sum().item())
+    nbytes = (pairs + 2 * R - 1) * A * B * M * 4
+    gbps = nbytes / ms / 1e6
+    print(json.dumps({"metric": "rebinning GB/s", "value": round(gbps, 1), "unit": "GB/s", "avg_ms": round(ms, 4),
+                      "launches": args.steps, "alg_bytes_per_launch": nbytes, "hbm_frac": round(gbps / 8000.0, 4),
+                      "config": {"workload": f"{R} rings, ring differences up to {D} ({pairs} ring pairs), "
+                                             f"{A} angles x {B} bins, {M} frames -> {2 * R - 1} planes"}}), flush=True)
+
+
 def run_compare(args):
     """The method comparison of the simulation on the ring phantom: INDIRECT, DIRECT and KCS DIRECT
     (for each spatial weight of `--beta-h`, decades apart) over `--realizations` noise
@@ -510,7 +543,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--mode", default="sweep", choices=["sweep", "batched", "serve", "copy", "ki", "compare"])
+    ap.add_argument("--mode", default="sweep", choices=["sweep", "batched", "serve", "copy", "ki", "compare", "ssrb"])
     ap.add_argument("--realizations", type=int, default=32, help="compare mode: noise realizations per method")
     ap.add_argument("--sweeps", type=int, default=10, help="compare mode: ICM sweeps per realization")
     ap.add_argument("--beta-h", default="1e2,1e3,1e4,1e5", help="compare mode: KCS spatial weights (comma-separated)")
@@ -544,6 +577,11 @@ def main():
         return
     if args.mode == "compare":
         run_compare(args)
+        return
+    if args.mode == "ssrb":
+        if args.steps is None:
+            args.steps = 10
+        run_ssrb(args)
         return
     if args.mode == "ki":
         args.steps = 20 if args.steps is None else args.steps

@@ -150,6 +150,26 @@ int kcs_backproject(const kcs_geometry* g, const kcs_frames* f, const float* d_y
  * launched); n = 0 is a no-op.  Asynchronous on `stream`; needs no workspace. */
 int kcs_ki_map(const float* d_params, int64_t n, float* d_ki, hipStream_t stream);
 
+/* Single-slice rebinning of a 3D acquisition (Sec. IV: the human study's 3D listmode data are
+ * rebinned into the sinograms this reconstruction takes).  A scanner of R rings records a
+ * sinogram for every ring pair (r1, r2) with |r2 - r1| <= D; the axial midpoint of its lines of
+ * response lies on plane z = r1 + r2 of the 2R - 1 planes spaced half a ring apart (direct planes
+ * at even z, cross planes at odd z), and the rebinning adds it there:
+ *   y2d[z][a][b][m] = sum over delta = -D..D, in increasing order, with z - delta even,
+ *                     r1 = (z - delta) / 2 and r2 = r1 + delta both in [0, R):
+ *                     y3d[delta + D][r1][a][b][m];
+ *   count[z] = the number of those ring pairs (the plane's sensitivity in units of one
+ *              sinogram: a factor of the plane's multiplicative correction, kcs_geometry.d_mult).
+ * d_y3d: [2D + 1][R][n_ang][n_bin][n_frames] device, span 1, indexed by ring difference and first
+ * ring (entries of ring pairs outside the scanner are not read); d_y2d: [2R - 1][n_ang][n_bin]
+ * [n_frames] device, written; d_count: [2R - 1] device floats, written, or NULL.  Sums in FP32
+ * (exact for integer counts below 2^24).  Caller-owned buffers; asynchronous on `stream`.
+ * Errors (nothing launched): KCS_EINVAL for R outside [1, 4096], D outside [0, R - 1], n_ang,
+ * n_bin or n_frames < 1, or a NULL d_y3d / d_y2d; KCS_ESHAPE for an output of 2^40 or more
+ * values. */
+int kcs_rebin_ssrb(int32_t n_rings, int32_t max_ring_diff, int32_t n_ang, int32_t n_bin, int32_t n_frames,
+                   const float* d_y3d, float* d_y2d, float* d_count, hipStream_t stream);
+
 /* Frame-averaged model TAC (Eq. 3's F(xi)_m, closed-form time integrals) for n voxels:
  *   F_m = (1/dt_m) int_{t0_m}^{t1_m} [(1 - vb) C_T(t; K1, k2, k3) + vb Cp(t)] dt
  * d_params: [P][n] (K1, k2, k3 with k2 + k3 > 0, and vb with k->fit_vb; P = 3 or 4); d_F: [n][M];

@@ -11,4 +11,5 @@ from .model import Kinetics, cp, input_integrals, model_tac, cumulative_tissue, 
 from .recon import (Frames, LMOptions, Prior, expected_counts, huber, huber_grad, icm, icm_sweep,
                     initial_image, initial_state, lm_fit, lm_iteration, neighbour_terms, osl_update,
                     subset_mult)
+from .rebin import ssrb
 from .study import Study, fitting_blood_fraction, initial_maps, make_plane_study, make_study

@@ -1061,6 +1061,19 @@ int kcs_ki_map(const float* d_params, int64_t n, float* d_ki, hipStream_t stream
     return launched(launch_ki(d_params, n, d_ki, stream), "K_i map");
 }
 
+int kcs_rebin_ssrb(int32_t n_rings, int32_t max_ring_diff, int32_t n_ang, int32_t n_bin, int32_t n_frames,
+                   const float* d_y3d, float* d_y2d, float* d_count, hipStream_t stream) {
+    if (n_rings < 1 || n_rings > 4096) return fail(KCS_EINVAL, "n_rings must be in [1, 4096]");
+    if (max_ring_diff < 0 || max_ring_diff > n_rings - 1) return fail(KCS_EINVAL, "need 0 <= max_ring_diff <= n_rings - 1");
+    if (n_ang < 1 || n_bin < 1 || n_frames < 1) return fail(KCS_EINVAL, "n_ang, n_bin and n_frames must be >= 1");
+    if (!d_y3d || !d_y2d) return fail(KCS_EINVAL, "device pointers must not be NULL");
+    const double out_values = (double)(2 * n_rings - 1) * n_ang * n_bin * n_frames;
+    if (out_values / 256.0 >= 4294967295.0) return fail(KCS_ESHAPE, "output too large for one launch");
+    g_err.clear();
+    const RebinArgs a{n_rings, max_ring_diff, n_ang, n_bin, n_frames};
+    return launched(launch_ssrb(a, d_y3d, d_y2d, d_count, stream), "single-slice rebinning");
+}
+
 int kcs_osl_update(const kcs_geometry* g, const kcs_frames* f, const kcs_kinetics* k, const kcs_prior* p,
                    const float* d_sino, const float* d_params, int32_t q, int32_t Q, float* d_x, void* d_work,
                    size_t work_bytes, hipStream_t stream) {

@@ -171,6 +171,12 @@ hipError_t launch_lm(int M, const KinTab* K, const float* x, const float* xi_in,
                      float* state, const LmArgs& a, hipStream_t st);
 hipError_t launch_ki(const float* params, int64_t n, float* ki, hipStream_t st);
 
+// Single-slice rebinning: R rings, ring differences up to D, sinograms of n_ang x n_bin x M.
+struct RebinArgs {
+    int32_t R, D, n_ang, n_bin, M;
+};
+hipError_t launch_ssrb(const RebinArgs& a, const float* y3d, float* y2d, float* count, hipStream_t st);
+
 // Streaming read (kind 0: one partial sum per thread into dst, stream_read_out_floats(groups)
 // floats) or copy (kind 1) of bytes (a multiple of 16) for bandwidth measurement.
 size_t stream_read_out_floats(int groups);

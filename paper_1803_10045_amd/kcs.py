@@ -20,7 +20,7 @@ KCS_OK, KCS_EINVAL, KCS_ESHAPE, KCS_EWORKSPACE, KCS_EHIP = 0, -1, -2, -3, -4
 
 # Entry points declared in include/kcs.h (checked against the header by the tests).
 ENTRY_POINTS = ("kcs_workspace_bytes", "kcs_study_footprint_bytes", "kcs_project", "kcs_backproject",
-                "kcs_model_tac", "kcs_ki_map", "kcs_osl_update", "kcs_lm_fit", "kcs_init_state", "kcs_icm_sweep",
+                "kcs_model_tac", "kcs_ki_map", "kcs_rebin_ssrb", "kcs_osl_update", "kcs_lm_fit", "kcs_init_state", "kcs_icm_sweep",
                 "kcs_icm_sweep_noalloc",
                 "kcs_plan_create", "kcs_plan_run", "kcs_plan_describe", "kcs_plan_destroy",
                 "kcs_timing_enable", "kcs_timing_collect", "kcs_stream_probe", "kcs_last_error")
@@ -87,6 +87,7 @@ def lib() -> ctypes.CDLL:
     L.kcs_backproject.argtypes = [P(c_geometry), P(c_frames), vp, i32, i32, vp, vp, vp]
     L.kcs_model_tac.argtypes = [P(c_frames), P(c_kinetics), vp, i64, vp, vp, vp, sz, vp]
     L.kcs_ki_map.argtypes = [vp, i64, vp, vp]
+    L.kcs_rebin_ssrb.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp, vp]
     L.kcs_osl_update.argtypes = [P(c_geometry), P(c_frames), P(c_kinetics), P(c_prior), vp, vp, i32, i32, vp, vp, sz,
                                  vp]
     L.kcs_lm_fit.argtypes = [P(c_geometry), P(c_frames), P(c_kinetics), P(c_prior), P(c_lm_opts), vp, vp, vp, vp, sz,
@@ -96,7 +97,8 @@ def lib() -> ctypes.CDLL:
                                 vp, vp, vp, sz, vp]
     L.kcs_icm_sweep_noalloc.argtypes = [P(c_geometry), P(c_frames), P(c_kinetics), P(c_prior), P(c_lm_opts), vp, i32,
                                         i32, vp, vp, vp, vp]
-    for name in ("kcs_project", "kcs_backproject", "kcs_model_tac", "kcs_ki_map", "kcs_osl_update", "kcs_lm_fit",
+    for name in ("kcs_project", "kcs_backproject", "kcs_model_tac", "kcs_ki_map", "kcs_rebin_ssrb", "kcs_osl_update",
+                 "kcs_lm_fit",
                  "kcs_init_state", "kcs_icm_sweep", "kcs_icm_sweep_noalloc"):
         getattr(L, name).restype = ctypes.c_int
     L.kcs_plan_create.argtypes = [P(c_study), i32, i32, vp, P(vp)]
@@ -312,6 +314,17 @@ def kcs_ki_map(params, ki, stream=None):
     n = ki.numel()
     _check(lib().kcs_ki_map(_ptr(params, (3,) + tuple(ki.shape), "params"), n, _ptr(ki, tuple(ki.shape), "ki"),
                             _stream(stream)))
+
+
+def kcs_rebin_ssrb(n_rings: int, max_ring_diff: int, y3d, y2d, count=None, stream=None):
+    """Single-slice rebinning: y3d [2D + 1][R][n_ang][n_bin][M] (span 1, by ring difference and
+    first ring) into y2d [2R - 1][n_ang][n_bin][M]; count [2R - 1] (ring pairs per plane) or None."""
+    nd, R, n_ang, n_bin, M = tuple(y3d.shape)
+    if nd != 2 * max_ring_diff + 1 or R != n_rings:
+        raise ValueError("y3d must be [2 * max_ring_diff + 1][n_rings][n_ang][n_bin][M]")
+    _check(lib().kcs_rebin_ssrb(n_rings, max_ring_diff, n_ang, n_bin, M, _ptr(y3d, tuple(y3d.shape), "y3d"),
+                                _ptr(y2d, (2 * n_rings - 1, n_ang, n_bin, M), "y2d"),
+                                _ptr(count, (2 * n_rings - 1,), "count"), _stream(stream)))
 
 
 def kcs_osl_update(g: Geometry, f: Frames, k: Kinetics, p: Prior, sino, params, q: int, Q: int, x, work,

@@ -254,3 +254,17 @@ def test_blood_fraction_options_validated():
     out = ctypes.c_void_p()
     assert kcs.lib().kcs_plan_create(arr, 1, 0, None, ctypes.byref(out)) == kcs.KCS_EINVAL
     assert "fit_vb" in kcs.kcs_last_error() and out.value is None
+
+
+def test_rebin_arguments_validated():
+    """Single-slice rebinning refuses bad ring counts, ring differences, sizes and NULL pointers on
+    the host."""
+    L = kcs.lib()
+    vp = ctypes.c_void_p
+    assert L.kcs_rebin_ssrb(0, 0, 4, 4, 1, vp(256), vp(256), None, None) == kcs.KCS_EINVAL
+    assert L.kcs_rebin_ssrb(8, 8, 4, 4, 1, vp(256), vp(256), None, None) == kcs.KCS_EINVAL  # D > R - 1
+    assert L.kcs_rebin_ssrb(8, -1, 4, 4, 1, vp(256), vp(256), None, None) == kcs.KCS_EINVAL
+    assert L.kcs_rebin_ssrb(8, 2, 0, 4, 1, vp(256), vp(256), None, None) == kcs.KCS_EINVAL
+    assert L.kcs_rebin_ssrb(8, 2, 4, 4, 1, None, vp(256), None, None) == kcs.KCS_EINVAL
+    assert "NULL" in kcs.kcs_last_error()
+    assert L.kcs_rebin_ssrb(4096, 10, 4096, 4096, 32, vp(256), vp(256), None, None) == kcs.KCS_ESHAPE
