@@ -309,7 +309,7 @@ TuneKey tune_key(const kcs_geometry& g, int M, int32_t Q) {
     return TuneKey{g.nx, g.ny, g.n_bin, (g.n_ang + Q - 1) / Q, M, (float)(g.pixel_mm / g.bin_mm)};
 }
 
-std::mutex g_tune_mu;
+std::recursive_mutex g_tune_mu;  // recursive: the tuner builds job arguments that look tuned values up
 std::vector<std::pair<TuneKey, int>> g_tuned;  // guarded by g_tune_mu
 bool g_tune_file_read = false;
 
@@ -341,6 +341,18 @@ int tuned_tile_locked(const TuneKey& k) {
     return -1;
 }
 
+// Voxel tile width of the MAP-LM kernel for a plane shape: the width the plan autotuner measured
+// fastest for that shape in this process, otherwise lm_tile_x's rule.  The tile does not change
+// any voxel's result.
+std::vector<std::pair<std::pair<int, int>, int>> g_lm_tile;  // (nx, ny) -> tile width; guarded by g_tune_mu
+
+int lm_tile_for(int nx, int ny) {
+    std::lock_guard<std::recursive_mutex> lk(g_tune_mu);
+    for (const auto& e : g_lm_tile)
+        if (e.first == std::make_pair(nx, ny)) return e.second;
+    return lm_tile_x(nx, ny);
+}
+
 // Variant for a study shape: KCS_PROJ_TILE (0, 16, 32, 64) overrides; then a tuned variant of
 // this shape; otherwise LDS tiles of 32 pixels for planes beyond an XCD's L2 share (2 MB),
 // ray-driven below.
@@ -350,7 +362,7 @@ int projector_tile(const kcs_geometry& g, int M, int32_t Q) {
         if (t == 0 || t == 16 || t == 32 || t == 64) return t;
     }
     {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
+        std::lock_guard<std::recursive_mutex> lk(g_tune_mu);
         const int t = tuned_tile_locked(tune_key(g, M, Q));
         if (t >= 0) return t;
     }
@@ -507,7 +519,7 @@ int do_lm(const kcs_geometry& g, const Schedule& S, int np, const kcs_prior& p, 
     a.nx = g.nx;
     a.ny = g.ny;
     a.nz = g.nz;
-    a.tile_x = lm_tile_x(g.nx, g.ny);
+    a.tile_x = lm_tile_for(g.nx, g.ny);
     a.fr = S.fr;
     a.beta_h = (float)p.beta_h;
     set_neighbourhood(a, p);
@@ -622,7 +634,7 @@ LmArgs lm_args(const StudyPrep& P) {
     a.nx = s.g.nx;
     a.ny = s.g.ny;
     a.nz = s.g.nz;
-    a.tile_x = lm_tile_x(s.g.nx, s.g.ny);
+    a.tile_x = lm_tile_for(s.g.nx, s.g.ny);
     a.fr = P.S.fr;
     a.beta_h = (float)s.p.beta_h;
     set_neighbourhood(a, s.p);
@@ -796,11 +808,65 @@ void store_tile(const TuneKey& k, int T, float ms) {
     }
 }
 
+// Times one MAP-LM iteration of the studies `cls` (one plane shape) with each voxel tile width
+// and keeps the fastest for the shape (caller holds g_tune_mu).  The iteration reads the study's
+// image and maps and writes only workspace regions: the maps into the ping-pong buffer, lambda
+// into the model-TAC region, the normal equations into their own region.
+int tune_lm_tile(const std::vector<StudyPrep*>& cls, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    const kcs_study& s0 = *cls[0]->s;
+    const std::pair<int, int> shape{s0.g.nx, s0.g.ny};
+    for (const auto& e : g_lm_tile)
+        if (e.first == shape) return KCS_OK;
+    const int M = s0.f.n_frames;
+    const bool nb = s0.p.plane_ratio > 0;
+    for (const StudyPrep* P : cls)
+        if (P->s->f.n_frames != M || (P->s->p.plane_ratio > 0) != nb) return KCS_OK;  // mixed class: keep the rule
+    int best = lm_tile_x(shape.first, shape.second);
+    float best_ms = 1e30f;
+    for (int tx : {64, 32, 16, 8}) {
+        TableBuilder tb;
+        std::vector<LmJob> jobs;
+        std::vector<uint32_t> g;
+        for (const StudyPrep* P : cls) {
+            const kcs_study& s = *P->s;
+            LmArgs a = lm_args(*P);
+            a.tile_x = tx;
+            a.reset_lambda = 1;
+            a.have_state = 0;
+            a.need_state = 0;
+            jobs.push_back(LmJob{a, at<KinTab>(s.d_work, P->L.kin), s.d_x, s.d_params, at<float>(s.d_work, P->L.xi),
+                                 at<float>(s.d_work, P->L.F), at<float>(s.d_work, P->L.lms), 0});
+            g.push_back(lm_groups(s.g.nx, s.g.ny, s.g.nz, tx));
+        }
+        tb.add(PH_LM, M, nb ? 1 : 0, jobs, g, 0);
+        void* dtab = nullptr;
+        if (hipMalloc(&dtab, std::max<size_t>(tb.buf.size(), 256)) != hipSuccess) return fail(KCS_EHIP, "tuning table");
+        hipError_t e = hipMemcpy(dtab, tb.buf.data(), tb.buf.size(), hipMemcpyHostToDevice);
+        float ms = 0.0f;
+        for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {  // rep 0 warms up
+            if (rep == 1) e = hipEventRecord(e0, st);
+            for (const PlanPhase& ph : tb.phases)
+                if (e == hipSuccess) e = run_phase(ph, (const char*)dtab, st);
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        (void)hipFree(dtab);
+        if (e != hipSuccess) return hip_fail(e, "MAP-LM tile tuning");
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = tx;
+        }
+    }
+    g_lm_tile.push_back({shape, best});
+    return KCS_OK;
+}
+
 // Times the projector variants on the studies of each shape not tuned yet in this process (or in
 // the KCS_TUNE_CACHE file), keeps the fastest for the shape (plain calls of that shape use it from
 // now on) and appends it to the file.
 int autotune(std::vector<StudyPrep>& preps, hipStream_t st) {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::lock_guard<std::recursive_mutex> lk(g_tune_mu);
     std::vector<TuneKey> keys;
     for (const StudyPrep& P : preps) {
         const TuneKey k = tune_key(P.s->g, P.s->f.n_frames, P.s->Q);
@@ -852,6 +918,8 @@ int autotune(std::vector<StudyPrep>& preps, hipStream_t st) {
             store_tile(k, best, best_ms / 3.0f);
         }
         for (StudyPrep* P : cls) P->T = best;
+        if (rc == KCS_OK) rc = tune_lm_tile(cls, st, e0, e1);
+        if (rc != KCS_OK) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -927,6 +995,7 @@ using namespace kcs;
 struct kcs_plan {
     std::vector<PlanPhase> phases;
     std::vector<int> tiles;
+    std::vector<int> lm_tiles;  // voxel tile width of the fit, per study
     int n_studies = 0;
     void* d_tables = nullptr;
     void* h_tables = nullptr;  // pinned staging of the tables (the upload is asynchronous)
@@ -1179,6 +1248,7 @@ int kcs_plan_create(const kcs_study* studies, int32_t n, int32_t flags, hipStrea
     kcs_plan* plan = new kcs_plan();
     plan->phases = tb.phases;
     for (const StudyPrep& P : preps) plan->tiles.push_back(P.T);
+    for (const StudyPrep& P : preps) plan->lm_tiles.push_back(lm_tile_for(P.s->g.nx, P.s->g.ny));
     plan->n_studies = n;
     const size_t tbytes = std::max<size_t>(tb.buf.size(), 256);
     hipError_t e = hipMalloc(&plan->d_tables, tbytes);
@@ -1230,6 +1300,8 @@ int kcs_plan_describe(const kcs_plan* plan, char* buf, size_t len) {
     std::string t = "studies=" + std::to_string(plan->n_studies) + " launches=" + std::to_string(plan->phases.size()) +
                     " graph=" + (plan->exec ? "yes" : "no") + " tiles=";
     for (size_t i = 0; i < plan->tiles.size(); ++i) t += (i ? "," : "") + std::to_string(plan->tiles[i]);
+    t += " lm_tiles=";
+    for (size_t i = 0; i < plan->lm_tiles.size(); ++i) t += (i ? "," : "") + std::to_string(plan->lm_tiles[i]);
     snprintf(buf, len, "%s", t.c_str());
     return KCS_OK;
 }
