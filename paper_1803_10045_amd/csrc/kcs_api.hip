@@ -669,7 +669,7 @@ void add_projection(TableBuilder& tb, const std::vector<const StudyPrep*>& ps, i
             jobs.push_back(j);
             g.push_back(key.second ? proj_tile_groups(j.p, key.second) : proj_direct_groups(j.p));
             red.push_back(j);
-            gr.push_back(proj_direct_groups(j.p));
+            gr.push_back(proj_reduce_groups(j.p));
         }
         tb.add(PH_PROJ, key.first, key.second, jobs, g, max_a);
         if (key.second) tb.add(PH_REDUCE, key.first, key.second, red, gr, max_a);

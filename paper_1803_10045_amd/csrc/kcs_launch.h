@@ -141,6 +141,7 @@ struct JobTable {
 
 // Workgroups each job needs.
 uint32_t proj_direct_groups(const ProjArgs& p);
+uint32_t proj_reduce_groups(const ProjArgs& p);
 uint32_t proj_tile_groups(const ProjArgs& p, int T);
 uint32_t staged_tile_groups(int nx, int ny, int nz);
 bool staged_fits(int M, float h, float du);  // one angle's staged bin records fit in the LDS

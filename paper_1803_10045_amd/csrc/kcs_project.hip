@@ -88,6 +88,15 @@ __host__ __device__ __forceinline__ void project_ray(const ProjArgs& p, const fl
 
 uint32_t proj_direct_groups(const ProjArgs& p) { return (uint32_t)((p.rays_per_plane + 255) / 256) * p.nz; }
 
+// Lanes per ray of the reduce step of a tiled projection (a power of 2 dividing 64): a ray's
+// partial sums lie in about one tile per tile row, so the lanes split the rows and more loads are
+// in flight than with one lane walking all of them.
+constexpr int kReduceLanes = 4;
+
+uint32_t proj_reduce_groups(const ProjArgs& p) {
+    return (uint32_t)(((int64_t)p.rays_per_plane * kReduceLanes + 255) / 256) * p.nz;
+}
+
 template <int M, bool RATIO, class Src>
 __global__ __launch_bounds__(256) void kproj_kernel(Src src) {
     const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
@@ -285,10 +294,14 @@ __global__ __launch_bounds__(256) void kproj_reduce_kernel(Src src) {
     const ProjArgs& p = J.p;
     const int slots = J.slots;
     const uint32_t lw = w - J.w0;
-    const uint32_t blocks_per_plane = (p.rays_per_plane + 255u) / 256u;
+    const uint32_t blocks_per_plane = (p.rays_per_plane * kReduceLanes + 255u) / 256u;
     const uint32_t z = lw / blocks_per_plane;
     if (z >= (uint32_t)p.nz) return;
-    const uint32_t ray = (lw % blocks_per_plane) * 256u + threadIdx.x;
+    // kReduceLanes adjacent lanes share a ray (all of them in range or none), each summing the
+    // tile rows ty = part, part + kReduceLanes, ...; their sums are added by a butterfly below
+    const uint32_t lane_id = (lw % blocks_per_plane) * 256u + threadIdx.x;
+    const uint32_t ray = lane_id / kReduceLanes;
+    const int part = (int)(lane_id % kReduceLanes);
     if (ray >= (uint32_t)p.rays_per_plane) return;
     const int al = ray / p.n_bin;
     const int b = ray - al * p.n_bin;
@@ -305,7 +318,7 @@ __global__ __launch_bounds__(256) void kproj_reduce_kernel(Src src) {
     // one, so the interval still covers it).
     const float slope = (float)T * p.h * A.c * p.inv_du;
     const float bc = 0.5f * (float)(p.n_bin - 1);
-    for (int ty = 0; ty < nty; ++ty) {
+    for (int ty = part; ty < nty; ty += kReduceLanes) {
         int lo = 0, hi = ntx - 1;
         if (fabsf(slope) > 1e-3f) {
             const float xl = -0.5f * (float)p.nx * p.h, xr = xl + (float)T * p.h;
@@ -333,7 +346,12 @@ __global__ __launch_bounds__(256) void kproj_reduce_kernel(Src src) {
             }
         }
     }
-    ray_epilogue<M, RATIO>(p, J.sino, J.out, z, al, b, acc);
+    // every lane of the ray ends with the same total (a + b == b + a exactly)
+#pragma unroll
+    for (int d = 1; d < kReduceLanes; d *= 2)
+#pragma unroll
+        for (int m = 0; m < M; ++m) acc[m] += __shfl_xor(acc[m], d, 64);
+    if (part == 0) ray_epilogue<M, RATIO>(p, J.sino, J.out, z, al, b, acc);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -428,7 +446,7 @@ hipError_t launch_project_tiled(int M, int T, const float* x, const float* sino,
     OneJob<ProjJob> src{ProjJob{p, x, sino, out, psum, tile_slots(T, p.h, p.du), 0}};
     hipError_t e = dispatch_project(M, T, src, proj_tile_groups(p, T), p.A_q, ratio, false, st);
     if (e != hipSuccess) return e;
-    return dispatch_project(M, T, src, proj_direct_groups(p), p.A_q, ratio, true, st);
+    return dispatch_project(M, T, src, proj_reduce_groups(p), p.A_q, ratio, true, st);
 }
 
 // Batched: a device table of jobs.  For T > 0 the tile step and the reduce step are separate

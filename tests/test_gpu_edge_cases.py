@@ -6,10 +6,11 @@ import pytest
 
 import oracle
 from paper_1803_10045_amd import inputs
-from kcs_testutil import geometry_pair, make_image, rel_l2
+from kcs_testutil import geometry_pair, make_image, oracle_fit_history, rel_l2, same_fit_path
 
 torch = pytest.importorskip("torch")
 from paper_1803_10045_amd import kcs  # noqa: E402
+from gpu_schedule_util import gpu_fit_history  # noqa: E402
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
@@ -84,12 +85,10 @@ def test_other_frame_counts(M, gaps):
                             inputs.LM_ETA)
     lm_k = kcs.LMOptions(5, inputs.LM_TAU, inputs.LM_LAM_MIN, inputs.LM_LAM_MAX, inputs.LM_LO, inputs.LM_HI,
                          inputs.LM_ETA)
-    pd, ld = dev(p0), dev(np.zeros((nz, ny, nx)))
-    kcs.kcs_lm_fit(kg, kfr, KK, prior_k, lm_k, dev(xt), pd, ld, kcs.alloc_workspace(kg, M, 0, DEV))
-    torch.cuda.synchronize()
-    op, ol = oracle.lm_fit(ofr, KIN, prior_o, lm_o, xt, p0, np.zeros((nz, ny, nx)))
-    same = np.abs(ld.cpu().numpy() / ol - 1.0) < 1e-3
-    gp = pd.cpu().numpy()
+    gp, gl, gh = gpu_fit_history(kg, kfr, KK, prior_k, lm_k, xt, p0, np.zeros((nz, ny, nx)))
+    st = type("FitStudy", (), {"frames": ofr, "kin": KIN})()
+    op, ol, oh = oracle_fit_history(st, prior_o, lm_o, xt, p0, np.zeros((nz, ny, nx)))
+    same = same_fit_path(gh, oh)  # decisions agreed in every iteration
     e_lm = max(rel_l2(gp[i][same], op[i][same]) for i in range(3))
     print(f"M={M} gaps={gaps}: project {e_proj:.2e} F {e_F:.2e} J {e_J:.2e} OSL pass {e_osl:.2e} "
           f"LM {e_lm:.2e} ({(~same).sum()} voxels on another path)")
