@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void kproj_kernel(Src src) {
 // which parallel rays of a near-horizontal angle read at the same step, fall in other banks.
 __host__ __device__ constexpr int tile_row(int T, int FG) { return T * FG + 4; }
 __host__ __device__ constexpr size_t tile_lds_bytes(int T, int FG) { return (size_t)T * tile_row(T, FG) * sizeof(float); }
-__host__ __device__ constexpr int tile_threads(int T, int FG) { return T == 16 ? 256 : 512; }
+__host__ __device__ constexpr int tile_threads(int T) { return T == 16 ? 256 : 512; }
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS of a CU
 
 // Frame groups of the tiled projector for M frames and tile T: the fewest whose staged tile
@@ -201,8 +201,8 @@ __device__ __forceinline__ int item_angle(const int* start, int A_q, int it) {
 }
 
 template <int M, int T, int NG, class Src>
-__global__ __launch_bounds__(tile_threads(T, M / NG)) void kproj_tile_kernel(Src src) {
-    constexpr int FG = M / NG, NT = tile_threads(T, FG), TS = tile_row(T, FG);
+__global__ __launch_bounds__(tile_threads(T)) void kproj_tile_kernel(Src src) {
+    constexpr int FG = M / NG, NT = tile_threads(T), TS = tile_row(T, FG);
     static_assert(M % FG == 0 && FG % 4 == 0, "frame groups");
     extern __shared__ float4 lds4[];
     const uint32_t w = xcd_work_index(blockIdx.x, gridDim.x);
@@ -368,7 +368,7 @@ static hipError_t launch_tile(Src src, uint32_t groups, int max_angles, hipStrea
     }
     const size_t lds = tile_lds_bytes(T, FG) + (size_t)max_angles * sizeof(TileAngle) + (size_t)(max_angles + 1) * sizeof(int);
     if (lds > kLdsBytes) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((kproj_tile_kernel<M, T, NG, Src>), dim3(xcd_round_up(groups)), dim3(tile_threads(T, FG)), lds,
+    hipLaunchKernelGGL((kproj_tile_kernel<M, T, NG, Src>), dim3(xcd_round_up(groups)), dim3(tile_threads(T)), lds,
                        st, src);
     return hipGetLastError();
 }
