@@ -165,6 +165,9 @@ __host__ __device__ __forceinline__ void siddon_traverse_box(const AngleRec& A, 
     int idx = j * row + i * col;
     const int dix = si * col, diy = sj * row;
     const int max_steps = nx + ny + 2;
+    // two crossings per loop pass: the loop-back branch and the copies of lnext and of the
+    // pixel offset come once per two crossings
+#pragma unroll 2
     for (int step = 0; step < max_steps; ++step) {
         const float lnext = fminf(fminf(lx, ly), lend);
         visit(idx, lnext - lcur);
