@@ -566,7 +566,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the ICM sweep shards by plane with no "
-              "exchange, so a multi-GPU run is not part of this build.", file=sys.stderr)
+              "exchange, and runs on more than one GPU are not supported.", file=sys.stderr)
         sys.exit(2)
     if args.mode == "serve":
         run_serve(args)
