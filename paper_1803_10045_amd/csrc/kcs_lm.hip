@@ -2,8 +2,9 @@
 //
 // Per voxel: model TAC F and its 3 Jacobian columns from the closed form (frame by frame,
 // accumulating J^T J and J^T r on the fly, so no Jacobian is stored), the Huber neighbour
-// gradient over the in-plane 8-neighbourhood read from the previous maps (Jacobi update, all
-// voxels see the same old neighbours), the damped 3x3 normal equations solved by a
+// gradient over the in-plane 8-neighbourhood of the previous maps (Jacobi update, all voxels see
+// the same old neighbours; a workgroup stages its tile of the maps with a one-voxel border in LDS
+// once, and both Huber evaluations read it there), the damped 3x3 normal equations solved by a
 // diagonally scaled Cholesky factorisation in registers, box clipping, and the accept test on
 // the change of the voxel objective,
 //   dPhi = (r'^T r' - r^T r) / 2 + beta_h (E(xi') - E(xi)),   r = x - F(xi), r' = x - F(xi').
@@ -26,6 +27,13 @@ __host__ __device__ __forceinline__ float huber(float t, float d) {
     return at <= d ? 0.5f * t * t : d * at - 0.5f * d * d;
 }
 
+// The maps of a workgroup's voxel tile with a one-voxel border, staged in LDS: for each staged
+// plane (the voxel's own, and with the 3x3x3 neighbourhood the planes below and above, slots 0 to
+// 2 from below), (TY + 2) rows of (TX + 2) voxels, the NP maps of a voxel adjacent; the tile's
+// voxel (i, j) sits at row j - j0 + 1, column i - i0 + 1.  Entries outside the image are not
+// written and never read.
+constexpr int kHaloMaxTile = 66 * 6;  // (TX + 2)(TY + 2) at most, over TX in {8, 16, 32, 64}, TY = 256 / TX
+
 // Weighted Huber energy sum_k w_k sum_p H(q_p - xi_kp) over the neighbours k of voxel (i, j, z)
 // in the NP maps xi (neighbours outside the image dropped), and the gradient terms
 // psi_p = sum_k w_k clip(q_p - xi_kp, -delta_p, delta_p).  The neighbours are the 8 in-plane ones
@@ -33,45 +41,48 @@ __host__ __device__ __forceinline__ float huber(float t, float d) {
 // a.w_plane by the number of in-plane offsets).
 // Adds the terms of the 3x3 neighbours in plane zz of voxel (i, j) (the voxel itself skipped when
 // zz is its own plane); w_edge, w_diag weight neighbours with one and two in-plane offsets.
+// corner: the staged maps of voxel (i - 1, j - 1) in plane zz; w: staged voxels per row.
 template <int NP>
-__host__ __device__ __forceinline__ void plane_terms(const float* __restrict__ xi, const LmArgs& a, int i, int j,
-                                                     int zz, bool own, float w_centre, float w_edge, float w_diag,
-                                                     size_t N, const float (&q)[NP], float& e, float (&psi)[NP]) {
-    const size_t plane = (size_t)a.nx * a.ny;
+__device__ __forceinline__ void plane_terms(const float* corner, int w, const LmArgs& a, int i, int j, bool own,
+                                            float w_centre, float w_edge, float w_diag, const float (&q)[NP], float& e,
+                                            float (&psi)[NP]) {
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
+        const float* row = corner + (dy + 1) * w * NP;
 #pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
             if (own && dy == 0 && dx == 0) continue;
             const int jj = j + dy, ii = i + dx;
             if (jj < 0 || jj >= a.ny || ii < 0 || ii >= a.nx) continue;
-            const size_t u = (size_t)zz * plane + (size_t)jj * a.nx + ii;
             const int off = (dx != 0) + (dy != 0);
-            const float w = off == 0 ? w_centre : (off == 1 ? w_edge : w_diag);
+            const float wk = off == 0 ? w_centre : (off == 1 ? w_edge : w_diag);
             float h = 0.0f;
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
-                const float d = q[p] - xi[p * N + u];
-                psi[p] += w * fminf(fmaxf(d, -a.delta[p]), a.delta[p]);
+                const float d = q[p] - row[(dx + 1) * NP + p];
+                psi[p] += wk * fminf(fmaxf(d, -a.delta[p]), a.delta[p]);
                 h = p == 0 ? huber(d, a.delta[p]) : h + huber(d, a.delta[p]);
             }
-            e += w * h;
+            e += wk * h;
         }
     }
 }
 
+// own: the staged maps of voxel (i - 1, j - 1) in the voxel's own plane; plane_step: staged
+// values per plane.
 template <int NP, bool NBR3D>
-__host__ __device__ __forceinline__ float neighbour_energy(const float* __restrict__ xi, const LmArgs& a, int i, int j,
-                                                           int z, size_t N, const float (&q)[NP], float (&psi)[NP]) {
+__device__ __forceinline__ float neighbour_energy(const float* own, int w, int plane_step, const LmArgs& a, int i,
+                                                  int j, int z, const float (&q)[NP], float (&psi)[NP]) {
     float e = 0.0f;
 #pragma unroll
     for (int p = 0; p < NP; ++p) psi[p] = 0.0f;
-    plane_terms<NP>(xi, a, i, j, z, true, 0.0f, 1.0f, 0.70710678118654752f, N, q, e, psi);
+    plane_terms<NP>(own, w, a, i, j, true, 0.0f, 1.0f, 0.70710678118654752f, q, e, psi);
     if (NBR3D) {
 #pragma unroll 1
         for (int dz = -1; dz <= 1; dz += 2) {
             if (z + dz < 0 || z + dz >= a.nz) continue;
-            plane_terms<NP>(xi, a, i, j, z + dz, false, a.w_plane[0], a.w_plane[1], a.w_plane[2], N, q, e, psi);
+            plane_terms<NP>(own + dz * plane_step, w, a, i, j, false, a.w_plane[0], a.w_plane[1], a.w_plane[2], q, e,
+                            psi);
         }
     }
     return e;
@@ -150,11 +161,12 @@ __host__ __device__ __forceinline__ void store_normal(float* __restrict__ st, si
     st[(Normal<NP>::kFloats - 1) * N + v] = n.rr;
 }
 
+// xi_in: the staged maps of voxel (i - 1, j - 1) in the voxel's own plane (see kHaloMaxTile);
+// w: staged voxels per row; plane_step: staged values per plane.
 template <int M, int NP, bool NBR3D>
-__host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, const float* __restrict__ x,
-                                                  const float* __restrict__ xi_in, float* __restrict__ xi_out,
-                                                  float* __restrict__ lam_io, float* __restrict__ state,
-                                                  const LmArgs& a, int i, int j, int z) {
+__device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, const float* __restrict__ x, const float* xi_in,
+                                         int w, int plane_step, float* __restrict__ xi_out, float* __restrict__ lam_io,
+                                         float* __restrict__ state, const LmArgs& a, int i, int j, int z) {
     const size_t plane = (size_t)a.nx * a.ny;
     const size_t N = plane * a.nz;
     const size_t v = (size_t)z * plane + (size_t)j * a.nx + i;
@@ -162,13 +174,13 @@ __host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, 
     const float* xv = x + v * M;
     float p[NP];
 #pragma unroll
-    for (int k = 0; k < NP; ++k) p[k] = xi_in[k * N + v];
+    for (int k = 0; k < NP; ++k) p[k] = xi_in[(w + 1) * NP + k];
 
     // Huber terms over the neighbours of the previous maps: psi (gradient) and e0 (energy) at the
-    // current parameters.  The neighbours are read again for the trial energy below instead of
-    // being held in registers through the model evaluations (they are cache hits).
+    // current parameters.  The neighbours are read again from LDS for the trial energy below
+    // instead of being held in registers through the model evaluations.
     float psi[NP];
-    const float e0 = neighbour_energy<NP, NBR3D>(xi_in, a, i, j, z, N, p, psi);
+    const float e0 = neighbour_energy<NP, NBR3D>(xi_in, w, plane_step, a, i, j, z, p, psi);
     // data-term normal equations at the current parameters
     const Normal<NP> n0 = a.have_state ? load_normal<NP>(state, N, v) : normal_equations<M, NP>(a.fr, *K, xv, p);
     float g[NP];
@@ -227,7 +239,7 @@ __host__ __device__ __forceinline__ void lm_voxel(const KinTab* __restrict__ K, 
     for (int k = 0; k < NP; ++k) q[k] = fminf(fmaxf(p[k] + zz[k] * sc[k], a.lo[k]), a.hi[k]);
 
     float unused[NP];
-    const float e1 = neighbour_energy<NP, NBR3D>(xi_in, a, i, j, z, N, q, unused);
+    const float e1 = neighbour_energy<NP, NBR3D>(xi_in, w, plane_step, a, i, j, z, q, unused);
 
     // data term at the trial parameters, with its normal equations when another iteration follows
     // (they are the next iteration's if the step is kept); the last iteration of a fit needs only
@@ -287,10 +299,31 @@ __global__ __launch_bounds__(kLmThreads) void klm_kernel(Src src) {
     const uint32_t tx = (a.nx + TX - 1) >> sx, ty = (a.ny + TY - 1) / TY;
     const int z = lw / (tx * ty);
     const uint32_t rr = lw % (tx * ty);
-    const int j = (rr / tx) * TY + (threadIdx.x >> sx);
-    const int i = (rr % tx) * TX + (threadIdx.x & (TX - 1));
-    if (z >= a.nz || i >= a.nx || j >= a.ny) return;
-    lm_voxel<M, NP, NBR3D>(J.K, J.x, J.xi_in, J.xi_out, J.lam, J.state, a, i, j, z);
+    const int j0 = (rr / tx) * TY, i0 = (rr % tx) * TX;
+    const int j = j0 + (threadIdx.x >> sx);
+    const int i = i0 + (threadIdx.x & (TX - 1));
+    if (z >= a.nz) return;  // the whole workgroup: its tiles are past the last plane
+    // stage the previous maps of the tile and its border (and of the neighbouring planes) in LDS
+    constexpr int NPL = NBR3D ? 3 : 1;
+    __shared__ float halo[NPL * kHaloMaxTile * NP];
+    const int hw = TX + 2, n_tile = hw * (TY + 2);
+    const size_t plane = (size_t)a.nx * a.ny, N = plane * a.nz;
+    for (int e = threadIdx.x; e < NPL * n_tile; e += kLmThreads) {
+        const int slot = e / n_tile, t = e - slot * n_tile;
+        const int zz = z + (NPL == 1 ? 0 : slot - 1);
+        const int r = t / hw, c = t - r * hw;
+        const int jj = j0 - 1 + r, ii = i0 - 1 + c;
+        if (zz >= 0 && zz < a.nz && jj >= 0 && jj < a.ny && ii >= 0 && ii < a.nx) {
+            const size_t u = (size_t)zz * plane + (size_t)jj * a.nx + ii;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) halo[e * NP + p] = J.xi_in[p * N + u];
+        }
+    }
+    __syncthreads();
+    if (i >= a.nx || j >= a.ny) return;
+    // the staged maps of voxel (i - 1, j - 1) in the voxel's own plane (slot 1 of 3, or 0 of 1)
+    const float* corner = halo + (((NPL == 1 ? 0 : 1) * (TY + 2) + (j - j0)) * hw + (i - i0)) * NP;
+    lm_voxel<M, NP, NBR3D>(J.K, J.x, corner, hw, n_tile * NP, J.xi_out, J.lam, J.state, a, i, j, z);
 }
 
 // All jobs of one launch share the neighbourhood (nbr3d) and the number of fitted maps (np), so
