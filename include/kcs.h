@@ -267,7 +267,10 @@ enum {
                              back by later processes (which then start from them).  It also times one
                              MAP-LM iteration with voxel tiles 64, 32, 16 and 8 voxels wide for every
                              plane shape not tuned yet (writing only workspace regions) and keeps the
-                             fastest for the process; the tile changes no result */
+                             fastest for the process; the tile changes no result.  The environment
+                             variables KCS_PROJ_TILE (0 = ray-driven, 16, 32, 64) and KCS_LM_TILE (8,
+                             16, 32, 64), read at every call, override the projector variant and the
+                             fit's voxel tile of every study (for measurements and tests) */
 };
 
 /* Validates every study (on failure: KCS_EINVAL / KCS_EWORKSPACE naming the study, nothing is

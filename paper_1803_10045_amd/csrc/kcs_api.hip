@@ -341,12 +341,16 @@ int tuned_tile_locked(const TuneKey& k) {
     return -1;
 }
 
-// Voxel tile width of the MAP-LM kernel for a plane shape: the width the plan autotuner measured
-// fastest for that shape in this process, otherwise lm_tile_x's rule.  The tile does not change
-// any voxel's result.
+// Voxel tile width of the MAP-LM kernel for a plane shape: KCS_LM_TILE (8, 16, 32, 64)
+// overrides; then the width the plan autotuner measured fastest for that shape in this process,
+// otherwise lm_tile_x's rule.  The tile does not change any voxel's result.
 std::vector<std::pair<std::pair<int, int>, int>> g_lm_tile;  // (nx, ny) -> tile width; guarded by g_tune_mu
 
 int lm_tile_for(int nx, int ny) {
+    if (const char* e = getenv("KCS_LM_TILE")) {
+        const int t = atoi(e);
+        if (t == 8 || t == 16 || t == 32 || t == 64) return t;
+    }
     std::lock_guard<std::recursive_mutex> lk(g_tune_mu);
     for (const auto& e : g_lm_tile)
         if (e.first == std::make_pair(nx, ny)) return e.second;

@@ -244,3 +244,39 @@ def test_largest_supported_shapes(case):
     # at the 252 angles of the headline study the nearest oblique angle is 0.71 degrees and the
     # same pass is within 5e-6)
     assert err < (5e-5 if case == "max_angles" else 1e-5)
+
+
+@pytest.mark.parametrize("n_maps,plane_ratio", [(3, 0.0), (3, 0.971), (4, 0.0), (4, 0.971)])
+def test_lm_voxel_tile_changes_no_result(n_maps, plane_ratio, monkeypatch):
+    """The MAP-LM fit with voxel tiles 64, 32, 16 and 8 voxels wide on planes that no tile width
+    divides (each workgroup stages its tile of the maps with a one-voxel border, three planes with
+    the 3x3x3 neighbourhood): three maps or four, in-plane or 3x3x3 neighbourhood, every result is
+    the same bit for bit, and the fit moves the maps."""
+    nx, ny, nz, M = 37, 29, 3, 24
+    _, kfr = schedule(M, seed=21)
+    x = make_image(nz, ny, nx, M, seed=22)
+    maps = maps_in_box((nz, ny, nx), seed=23)
+    if n_maps == 4:
+        vb = np.random.default_rng(24).uniform(0.02, 0.1, (1, nz, ny, nx)).astype(np.float32)
+        maps = np.concatenate([maps, vb.astype(np.float64)])
+    kk = kcs.Kinetics(KIN.A1, KIN.A2, KIN.A3, KIN.l1, KIN.l2, KIN.l3, KIN.vb, fit_vb=n_maps == 4)
+    kg = kcs.Geometry(nx, ny, nz, 2.0, 30, 40, 2.0, 0.0)
+    prior = kcs.Prior(0.1, 0.01, 0.5, (2e-3,) * n_maps, True, plane_ratio)
+    lo = tuple(inputs.LM_LO) + ((inputs.LM_LO_VB,) if n_maps == 4 else ())
+    hi = tuple(inputs.LM_HI) + ((inputs.LM_HI_VB,) if n_maps == 4 else ())
+    lm = kcs.LMOptions(3, inputs.LM_TAU, inputs.LM_LAM_MIN, inputs.LM_LAM_MAX, lo, hi, inputs.LM_ETA)
+    xd = dev(x)
+    work = kcs.alloc_workspace(kg, M, 0, DEV)
+    results = []
+    for tile in ("64", "32", "16", "8"):
+        monkeypatch.setenv("KCS_LM_TILE", tile)
+        p = dev(maps)
+        lam = torch.zeros((nz, ny, nx), device=DEV)
+        kcs.kcs_lm_fit(kg, kfr, kk, prior, lm, xd, p, lam, work)
+        torch.cuda.synchronize()
+        results.append((p.cpu(), lam.cpu()))
+    moved = float((results[0][0] - torch.from_numpy(maps.astype(np.float32))).abs().max())
+    print(f"{n_maps} maps, plane ratio {plane_ratio}: largest map change {moved:.3e}")
+    assert moved > 1e-4
+    for p, lam in results[1:]:
+        assert torch.equal(p, results[0][0]) and torch.equal(lam, results[0][1])
