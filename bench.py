@@ -358,9 +358,10 @@ def run_serve(args):
                 mode, w = mode.split("/")
                 wait = float(w)
             comp, _, makespan, ticks = serve.serve(reqs, budget, ex, log=log, small_in_flight_beside_large=cap,
-                                                   small_wait_beside_large=wait)
+                                                   small_wait_beside_large=wait, large_resident=args.large_resident)
             ex.close()
-            extra = {"ticks": ticks, "small_in_flight_beside_large": cap, "small_wait_beside_large_s": wait}
+            extra = {"ticks": ticks, "small_in_flight_beside_large": cap, "small_wait_beside_large_s": wait,
+                     "large_resident": args.large_resident}
         else:
             comp, _, makespan = serve.serve_serial(reqs, log=log)
             extra = {}
@@ -554,6 +555,8 @@ def main():
                     help="serve mode: small-study ticks in flight beside a large study's tick")
     ap.add_argument("--small-wait", type=float, default=0.0,
                     help="serve mode: seconds a small study waits before its ticks run beside a large one")
+    ap.add_argument("--large-resident", type=int, default=1,
+                    help="serve mode: most large studies resident (admitted and loaded) at once (0: no limit)")
     ap.add_argument("--serve-runs", default="served@poisson,serial@poisson,served@saturated,serial@saturated",
                     help="comma-separated runs of the serve mode: served[:N[/W]]|serial @ poisson|saturated "
                          "(N: --small-beside-large, W: --small-wait)")

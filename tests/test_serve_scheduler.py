@@ -225,3 +225,64 @@ def test_small_studies_wait_before_running_beside_a_large_one():
     assert first_small < max(e for lane, _, e in ex.spans if lane == 1)  # but ran beside the large study
     ex, done = run_wait(0.0)
     assert min(st for lane, st, _ in ex.spans if lane == 0) < 0.005 + 0.01
+
+
+def test_lane_resident_cap_holds_requests_in_order_and_lets_other_lanes_pass():
+    """With at most one resident study in lane 1, a second lane-1 request is held (in order)
+    while later lane-0 requests are admitted; it is admitted once the first has finished."""
+    reqs = [FakeRequest(0, 0.0, 2, 10), FakeRequest(1, 0.0, 2, 10), FakeRequest(2, 0.0, 1, 1),
+            FakeRequest(3, 0.0, 1, 10), FakeRequest(4, 0.0, 1, 1)]
+    lane = {0: 1, 1: 1, 2: 0, 3: 1, 4: 0}
+    sched = serve.Scheduler(100, lambda r: lane[r.rid], 2, lane_resident=[0, 1])
+    for r in reqs:
+        sched.arrive(r)
+    assert [s.req.rid for s in sched.admit(0.0)] == [0, 2, 4]
+    assert [r.rid for r in sched.queue] == [1, 3]
+    first = sched.tick(1)
+    assert [s.req.rid for s in first] == [0]
+    sched.advance(first)
+    assert sched.admit(0.0) == []  # study 0 still has a sweep to run
+    for s in sched.advance(sched.tick(1)):
+        sched.release(s)
+    assert [s.req.rid for s in sched.admit(0.0)] == [1]
+    assert [r.rid for r in sched.queue] == [3]
+
+
+def test_lane_resident_cap_reserves_the_budget_of_held_requests():
+    """A held request keeps its place in memory: a later request of another lane passes it only
+    if the budget also has room for the held one."""
+    reqs = [FakeRequest(0, 0.0, 1, 40), FakeRequest(1, 0.0, 1, 40), FakeRequest(2, 0.0, 1, 30),
+            FakeRequest(3, 0.0, 1, 10)]
+    lane = {0: 1, 1: 1, 2: 0, 3: 0}
+    sched = serve.Scheduler(100, lambda r: lane[r.rid], 2, lane_resident=[0, 1])
+    for r in reqs:
+        sched.arrive(r)
+    # 40 used; request 1 (40) held; request 2 (30) would leave no room for it: it waits, and so
+    # does request 3 behind it (first come, first served)
+    assert [s.req.rid for s in sched.admit(0.0)] == [0]
+    assert [r.rid for r in sched.queue] == [1, 2, 3]
+    for s in sched.advance(sched.tick(1)):
+        sched.release(s)
+    assert [s.req.rid for s in sched.admit(0.0)] == [1, 2, 3]
+    assert sched.used == 80
+
+
+def test_served_with_large_resident_cap_runs_every_study():
+    """The serving loop with one resident large study at a time: every study runs its sweeps,
+    and at most one lane-1 study is resident at any tick."""
+    reqs = [FakeRequest(i, 0.0, 3, 10 if i % 3 == 0 else 1) for i in range(9)]
+    ex = FakeExecutor()
+    ex.lanes = [None, None]
+    resident_large = []
+    run_tick = ex.run_tick
+
+    def tick(slots, lane=0):
+        resident_large.append(sum(1 for rid in ex.resident if rid % 3 == 0))
+        run_tick(slots, lane)
+
+    ex.run_tick = tick
+    comp, _, _, _ = serve.serve(reqs, 1000, ex, lane_of=lambda r: 1 if r.rid % 3 == 0 else 0, large_resident=1)
+    assert sorted(c.rid for c in comp) == list(range(9))
+    assert max(resident_large) == 1
+    for rid in range(9):
+        assert sum(1 for t in ex.ticks for r, _ in t if r == rid) == 3
