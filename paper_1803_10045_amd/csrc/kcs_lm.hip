@@ -88,6 +88,22 @@ __device__ __forceinline__ float neighbour_energy(const float* own, int w, int p
     return e;
 }
 
+// Frame m of a voxel's image record read four frames at a time: the lanes of a wave read records
+// M floats apart, so a load of one float per lane touches as many cache lines as a load of four.
+// Called with m = 0, 1, ..., M - 1 in order from the frame loop of model_frames, which is unrolled
+// by four, so m % 4 is a constant in every call and the selects fold away.
+template <int M>
+struct RecordReader {
+    static_assert(M % 4 == 0, "frames must be a multiple of 4");
+    const float4* p;  // the record, 16-byte aligned
+    float4 q;
+    __host__ __device__ __forceinline__ float operator()(int m) {
+        if ((m & 3) == 0) q = p[m >> 2];
+        const int k = m & 3;
+        return k == 0 ? q.x : (k == 1 ? q.y : (k == 2 ? q.z : q.w));
+    }
+};
+
 // Normal equations of the data term at maps xi: J^T J (packed lower triangle, row by row:
 // A[r(r+1)/2 + c] for c <= r), J^T r (g) and r^T r (rr).  NP(NP + 1)/2 + NP + 1 floats: the
 // per-voxel state a fit carries between iterations (10 for 3 maps, 15 for 4).
@@ -111,10 +127,11 @@ __host__ __device__ __forceinline__ Normal<NP> normal_equations(const FrameTab& 
 #pragma unroll
     for (int k = 0; k < NP; ++k) n.g[k] = 0.0f;
     n.rr = 0.0f;
+    RecordReader<M> xr{reinterpret_cast<const float4*>(xv), {}};
     model_frames<M, true, false, NP>(fr, K, xi[0], xi[1], xi[2], NP == 4 ? xi[NP - 1] : 0.0f,
                                      [&](int m, float F, float j0, float j1, float j2, float j3) {
                                          const float jv[4] = {j0, j1, j2, j3};
-                                         const float r = xv[m] - F;
+                                         const float r = xr(m) - F;
 #pragma unroll
                                          for (int rw = 0; rw < NP; ++rw)
 #pragma unroll
@@ -133,9 +150,10 @@ template <int M, int NP>
 __host__ __device__ __forceinline__ float residual_norm(const FrameTab& fr, const KinTab& K, const float* xv,
                                                         const float (&xi)[NP]) {
     float rr = 0.0f;
+    RecordReader<M> xr{reinterpret_cast<const float4*>(xv), {}};
     model_frames<M, false, false, NP>(fr, K, xi[0], xi[1], xi[2], NP == 4 ? xi[NP - 1] : 0.0f,
                                       [&](int m, float F, float, float, float, float) {
-                                          const float r = xv[m] - F;
+                                          const float r = xr(m) - F;
                                           rr = fmaf(r, r, rr);
                                       });
     return rr;

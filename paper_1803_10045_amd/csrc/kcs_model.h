@@ -132,8 +132,9 @@ __host__ __device__ __forceinline__ void boundary_J(const KinTab& K, const Bound
 // !DERIV).  NP = 3: the blood fraction is the study's (FT.one_minus_vb, FT.blood) and vb is
 // ignored; NP = 4: it is the voxel's vb (the fourth fitted parameter), and
 // dF/dvb = (int_frame Cp - int_frame C_T) / dt.
-// UNROLL = false keeps the frame loop rolled (small code, few registers; the sink then sees a
-// run-time frame index and must not index register arrays with it).
+// UNROLL = false keeps the frame loop rolled, four frames per pass (small code, few registers; the
+// sink then sees a run-time frame index and must not index register arrays with it, but m % 4 is
+// known in each of the four copies of the body).
 template <int M, bool DERIV, bool UNROLL = true, int NP = 3, class Sink>
 __host__ __device__ __forceinline__ void model_frames(const FrameTab& FT, const KinTab& K, float K1, float k2, float k3,
                                              float vb, Sink&& sink) {
@@ -141,7 +142,7 @@ __host__ __device__ __forceinline__ void model_frames(const FrameTab& FT, const 
     const VoxelRates R = voxel_rates(K, k2, k3);
     const float g = NP == 4 ? 1.0f - vb : FT.one_minus_vb;
     float Jprev = 0.0f, dJprev = 0.0f;
-#pragma unroll(UNROLL ? M : 2)
+#pragma unroll(UNROLL ? M : 4)
     for (int m = 0; m < M; ++m) {
         if (m == 0 || !FT.contiguous) boundary_J<DERIV>(K, K.b[K.i0[m]], R, Jprev, dJprev);
         float J1, dJ1 = 0.0f;
